@@ -1,0 +1,238 @@
+/*
+ * dsmc.h -- C ABI of the MI355X (gfx950) DSMC particle step and DSMC<->LBM
+ * mapping library (libdsmc.so).
+ *
+ * Method: Di Staso, Clercx, Succi & Toschi, "DSMC-LBM mapping scheme for
+ * rarefied and non-rarefied gas flows", arXiv:1512.08042.
+ *
+ * Geometry and units (the nondimensionalisation of the paper's appendix
+ * "Scaling factors"): a 2-D channel of nx x ny unit cells, periodic in x,
+ * walls at y = 0 and y = H = ny with full diffuse reflection at the reference
+ * temperature, body force along +x.  Particles carry three velocity
+ * components (hard spheres in 3-D velocity space).  Speeds are in units in
+ * which kT/m = kT_over_m (1 by default), so the Hermite variable is
+ * xi = v / sqrt(kT/m).  Kn is on the channel height: lambda = Kn H, and the
+ * hard-sphere relation of Eq. (MFP) fixes F_N sigma_T / V_c = 1/(sqrt(2) lambda ppc).
+ *
+ * Memory: every device buffer is allocated and owned by the caller and must
+ * outlive the context; the library allocates no device memory after
+ * dsmc_init (dsmc_init itself allocates none either) and owns only the small
+ * host-side context.  All calls that take a stream enqueue asynchronous work
+ * on it (NULL = the null stream) and return immediately unless stated.
+ *
+ * Errors: calls return DSMC_OK (0) or a negative DSMC_E* code; argument
+ * errors are detected on the host before anything is enqueued.  Conditions
+ * found on the device set bits of a status word read by dsmc_read_status.
+ * No exception crosses the ABI and the library prints nothing.
+ *
+ * Determinism: the same configuration, seed and call sequence give
+ * bitwise-identical results on the same build and GPU (the random numbers
+ * are counter-based Philox4x32-10 keyed by (draw, entity, step, tag), and
+ * no result depends on the order of atomic operations).
+ */
+#ifndef DSMC_H
+#define DSMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define DSMC_OK 0
+#define DSMC_EINVAL (-1)   /* bad argument (reported before any work is enqueued) */
+#define DSMC_ECAPACITY (-2) /* a size exceeds the configured capacity */
+#define DSMC_EHIP (-3)     /* a HIP runtime call failed */
+#define DSMC_ESTATE (-4)   /* call not valid in the context's current state */
+
+/* device status bits (sticky until dsmc_read_status with clear = 1) */
+#define DSMC_ST_WALL_LIMIT 0x1u   /* a particle hit the walls 16 times in one step and was stopped on the wall */
+#define DSMC_ST_FAR_OVERFLOW 0x2u /* more long jumps (> 1 cell) in one step than far_capacity: that step's sort is invalid */
+#define DSMC_ST_CAPACITY 0x4u     /* a reseed would exceed capacity: it was skipped, state unchanged */
+#define DSMC_ST_AR_LIMIT 0x8u     /* acceptance-rejection reached ar_max_tries: the last try was kept */
+#define DSMC_ST_NONFINITE 0x10u   /* non-finite populations in a reseeded cell: it received no particles */
+#define DSMC_ST_NNEW_LIMIT 0x20u  /* more than 2^24-1 new particles requested for one cell: clamped */
+#define DSMC_ST_BAD_CELL 0x40u    /* reseed cell list had an out-of-range or repeated id: reseed skipped */
+
+#define DSMC_NMOM 11 /* sampled sums per cell, see dsmc_sample_moments */
+
+/* Velocity ordering of lattice populations f[a] (shared by every call that
+ * takes populations): shells of increasing |e|, counter-clockwise inside a
+ * shell starting from the first-octant representative:
+ *   a = 0: (0,0); 1-4: (1,0) (0,1) (-1,0) (0,-1); 5-8: (1,1) (-1,1) (-1,-1) (1,-1);
+ *   D2Q37 continues 9-12: (2,0) (0,2) (-2,0) (0,-2);
+ *   13-20: (2,1) (1,2) (-1,2) (-2,1) (-2,-1) (-1,-2) (1,-2) (2,-1);
+ *   21-24: (2,2) (-2,2) (-2,-2) (2,-2); 25-28: (3,0) (0,3) (-3,0) (0,-3);
+ *   29-36: (3,1) (1,3) (-1,3) (-3,1) (-3,-1) (-1,-3) (1,-3) (3,-1).
+ * Hermite abscissae xi_a = r e_a with r = sqrt(3) (D2Q9) or the D2Q37 scale
+ * obtained by solving the Gauss-Hermite conditions (Section 2.1: the lattice
+ * must integrate the Hermite weight exactly to degree >= 2N; D2Q37 is exact
+ * to degree 9).  Populations are laid out f[a * ncells + cell]. */
+
+typedef struct dsmc_config {
+    int32_t nx;            /* cells along the periodic direction x (>= 1) */
+    int32_t ny;            /* cells across the channel, H = ny (>= 1) */
+    int32_t ppc;           /* particles per cell at density 1 (>= 1) */
+    int32_t nbar_mode;     /* NTC pair factor: 0 = N * running mean of N (Eq. (collisionnumber)), 1 = N (N - 1) */
+    int64_t capacity;      /* particles each state buffer can hold (>= nx*ny*ppc for dsmc_init mode 0) */
+    double kn;             /* Knudsen number on the channel height (> 0) */
+    double dt;             /* time step (> 0) */
+    double body_force_x;   /* acceleration along x */
+    double kT_over_m;      /* kT/m of the gas and of the walls (> 0; 1 in the default units) */
+    double sigcr_max0;     /* initial (sigma_T c_r)_max / sigma_T of every cell, a speed (> 0) */
+    uint64_t seed;         /* Philox key */
+    int32_t ar_max_tries;  /* acceptance-rejection try limit per particle (<= 0: 65536) */
+    int32_t far_capacity;  /* long-jump list entries per step (<= 0: min(capacity, 65536)) */
+} dsmc_config;
+
+typedef struct dsmc_sizes {
+    int64_t ncells;          /* nx * ny */
+    int64_t capacity;        /* particles per state array */
+    size_t state_array_bytes; /* bytes of each of the 10 state arrays (capacity * 8) */
+    size_t workspace_bytes;  /* bytes of the single workspace buffer */
+} dsmc_sizes;
+
+typedef struct dsmc_buffers {
+    /* two structure-of-arrays particle buffers, [buffer][x, y, vx, vy, vz],
+     * each array `capacity` doubles of device memory; the library sorts from
+     * one into the other every step (see dsmc_get_views for which is current) */
+    double *state[2][5];
+    void *workspace;        /* device memory, >= dsmc_sizes.workspace_bytes, 256-byte aligned */
+    size_t workspace_bytes;
+} dsmc_buffers;
+
+typedef struct dsmc_views {
+    int32_t current;          /* index (0/1) of the state buffer that holds the particles, sorted by cell */
+    const int32_t *cell_start; /* device, ncells + 1: particles of cell c are slots [cell_start[c], cell_start[c+1]) */
+    double *nbar;             /* device, ncells: running mean of N per cell (NTC) */
+    double *sigcmax;          /* device, ncells: (sigma_T c_r)_max / sigma_T per cell */
+    double *rem;              /* device, ncells: carried fractional candidate count per cell */
+    const double *mom_sums;   /* device, [11][ncells]: sums over samples, see dsmc_sample_moments */
+    int64_t nsamples;         /* samples in mom_sums (host-side count, includes a pending sample) */
+    int64_t step;             /* DSMC steps taken since dsmc_init */
+    int64_t reseed_events;    /* map_lbm_to_dsmc calls so far */
+} dsmc_views;
+
+typedef struct dsmc_status {
+    uint32_t bits;           /* DSMC_ST_* */
+    uint32_t reserved;
+    int64_t n_particles;     /* current particle count */
+    uint64_t ncoll;          /* accepted collisions since init */
+    uint64_t ncand;          /* collision candidates since init */
+    uint64_t nwall;          /* wall hits since init */
+    uint64_t nfar;           /* long jumps since init */
+} dsmc_status;
+
+typedef struct dsmc_ctx dsmc_ctx;
+
+/* Sizes of the caller-owned buffers for a configuration.  Host only,
+ * synchronous.  Returns DSMC_EINVAL for an invalid configuration. */
+int dsmc_query_sizes(const dsmc_config *cfg, dsmc_sizes *out);
+
+/* Create a context over caller buffers and set the initial particle state.
+ * mode 0: exactly ppc particles in every cell (Section 3.1), uniform in the
+ *   cell, Maxwellian velocities at kT_over_m by Box-Muller (Table 1 step 4
+ *   names the transformation); particle g = c*ppc + k of cell c.
+ * mode 1: adopt n_load particles the caller wrote into state[0] (any order;
+ *   positions in [0,nx) x [0,ny]): they are stably sorted by cell.
+ * Per-cell NTC state starts at nbar = 0, sigcmax = sigcr_max0, rem = 0.
+ * Errors: DSMC_EINVAL (config, buffers, mode), DSMC_ECAPACITY (too many
+ * particles), DSMC_EHIP.  On success *out receives the context. */
+int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int64_t n_load, void *stream,
+              dsmc_ctx **out);
+
+/* Advance nsteps DSMC steps.  One step: free flight under the body force
+ * with diffuse wall reflection, cell indexing and a stable counting sort by
+ * cell, No-Time-Counter hard-sphere collisions per cell
+ * (Eq. (collisionnumber)), then, when (step + 1) % sample_every == 0 and
+ * sample_every > 0, one sample of the per-cell velocity moments (the
+ * cumulative averages that feed DSMC2LB, Section 2.1).  Errors: DSMC_EINVAL. */
+int dsmc_step(dsmc_ctx *ctx, int32_t nsteps, int32_t sample_every, void *stream);
+
+/* Write the time averages of the 11 sampled sums per cell to out (device,
+ * [11][ncells] doubles; may be NULL to only reset): the mean over samples of
+ * N, sum vx, sum vy, sum vx^2, sum vx vy, sum vy^2, sum vx^3, sum vx^2 vy,
+ * sum vx vy^2, sum vy^3, sum vz^2 (raw velocities).  reset != 0 zeroes the
+ * sums afterwards.  Errors: DSMC_ESTATE if no sample has been taken and out
+ * is not NULL. */
+int dsmc_sample_moments(dsmc_ctx *ctx, double *out, int32_t reset, void *stream);
+
+/* DSMC2LB projection (Eq. (discretefunctions)) of every cell's cumulative
+ * averages: a(0) = rho = <N>/ppc (the appendix's mass scale), a(1..3) the
+ * absolute-frame Hermite coefficients of Eq. (nordercoefficients) from the
+ * sampled moments, f_a = w_a sum_{n<=order} a(n):H(n)(xi_a)/n!.
+ * lattice 9 or 37, order 0..3 (D2Q9 drops H_xxx and H_yyy, which vanish on
+ * its nodes).  f_out: device, [Q][ncells].  Errors: DSMC_EINVAL,
+ * DSMC_ESTATE (no samples). */
+int map_dsmc_to_lbm(dsmc_ctx *ctx, int32_t lattice, int32_t order, double *f_out, void *stream);
+
+/* The same projection from caller-given averages (device, [11][ncells]). */
+int dsmc_project_moments(const double *avg, int64_t ncells, int32_t ppc, double kT_over_m, int32_t lattice,
+                         int32_t order, double *f_out, void *stream);
+
+/* LB2DSMC reconstruction (Section 2.2, Table 1) of the listed cells.
+ * f_in: device, [Q][ncells] populations; cell_ids: device, nsel distinct ids.
+ * Per listed cell: rho, u and the comoving, density-normalised a(2), a(3)
+ * (Table 1 step 1), M and C = 1 + 30 M (steps 2-3), N_new = floor(rho ppc + R)
+ * (mass conservation at the coupling site), then for each new particle
+ * Box-Muller tries accepted when C R <= G(xi) (steps 4-5) and
+ * v = sqrt(kT/m) (xi + u), v_z = sqrt(kT/m) z, position uniform in the cell.
+ * The cell's previous particles are removed; every other cell keeps its
+ * particles in order.  order 2 or 3.  A cell list with bad ids, or a result
+ * above capacity, skips the whole reseed and sets a status bit.
+ * Errors: DSMC_EINVAL. */
+int map_lbm_to_dsmc(dsmc_ctx *ctx, int32_t lattice, int32_t order, const double *f_in, const int32_t *cell_ids,
+                    int32_t nsel, void *stream);
+
+typedef struct lbm_config {
+    int32_t nx, ny;       /* nodes; x periodic */
+    int32_t lattice;      /* 9 or 37 */
+    int32_t y_mode;       /* 0: y periodic; 1: the max|e_y| rows at each y edge hold caller-set populations */
+    double tau;           /* BGK relaxation time in lattice steps (> 1/2), e.g. from Eq. (tau) */
+    double body_force_x;  /* velocity gain along x per lattice step, in units of sqrt(kT/m) */
+} lbm_config;
+
+/* nsteps BGK steps (Section 3.1) on populations f (device, [Q][nx*ny],
+ * pre-collision), with f_tmp (same size) as scratch; the result is in f.
+ * Per interior node: rho, u = (sum f xi + rho g/2)/rho, Hermite equilibrium
+ * of order 2 (D2Q9) or 3 (D2Q37), BGK relaxation, second-order Hermite force
+ * term (1 - 1/(2 tau)) w rho [xi.g + (xi.g)(xi.u) - g.u], streaming along
+ * e_a.  Errors: DSMC_EINVAL. */
+int lbm_step(const lbm_config *cfg, double *f, double *f_tmp, int32_t nsteps, void *stream);
+
+/* Host copy of a lattice table: e_out int[Q][2], w_out double[Q], r_out. */
+int dsmc_lattice(int32_t lattice, int32_t *e_out, double *w_out, double *r_out);
+
+/* Synchronise the context's last stream and read the status word and
+ * counters; clear != 0 resets the status bits.  Errors: DSMC_EHIP. */
+int dsmc_read_status(dsmc_ctx *ctx, dsmc_status *out, int32_t clear, void *stream);
+
+/* Pointers into the caller's buffers describing the current state. */
+int dsmc_get_views(dsmc_ctx *ctx, dsmc_views *out);
+
+/* Kernel timing with HIP events on the launch stream.  dsmc_profile_enable
+ * starts (enable = 1) or stops recording; dsmc_profile_read synchronises and
+ * returns, for kernel id k (DSMC_K_*), the summed duration in ms and the
+ * number of timed launches, then clears the records of that kernel. */
+#define DSMC_K_COLLIDE 0
+#define DSMC_K_PASS_COUNT 1
+#define DSMC_K_CELL_COUNT 2
+#define DSMC_K_SCAN 3
+#define DSMC_K_CELL_FINAL 4
+#define DSMC_K_PASS_SCATTER 5
+#define DSMC_K_SAMPLE 6
+#define DSMC_K_PROJECT 7
+#define DSMC_K_RESEED 8
+#define DSMC_K_COUNT 9
+int dsmc_profile_enable(dsmc_ctx *ctx, int32_t enable);
+int dsmc_profile_read(dsmc_ctx *ctx, int32_t kernel, double *ms_total, int64_t *launches);
+
+void dsmc_destroy(dsmc_ctx *ctx);
+const char *dsmc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSMC_H */

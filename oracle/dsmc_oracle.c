@@ -633,8 +633,9 @@ int64_t or_ar_sample_batch(uint64_t seed, const double prm[12], uint32_t c, uint
  * v = sqrt(kT/m) (xi + u), v_z = sqrt(kT/m) z, position uniform in the cell
  * from counters (0, c, e, RESEED_POS|k) and z from (1, c, e, RESEED_POS|k).
  * The cell's old particles are removed; all other cells keep their
- * particles in order.  Returns 0, or -1 (bad arguments), -2 (capacity: the
- * state is left unchanged). */
+ * particles in order.  Every call uses up one event index e.  Returns 0, or
+ * -1 (a repeated or out-of-range cell id), -2 (capacity); in both error
+ * cases the state is left unchanged. */
 int or_lb2dsmc(or_sim *s, int32_t Q, int32_t order, const double *xi, const double *f, const int32_t *cells,
                int32_t nsel)
 {
@@ -642,7 +643,12 @@ int or_lb2dsmc(or_sim *s, int32_t Q, int32_t order, const double *xi, const doub
     int32_t *mark = (int32_t *)xalloc((size_t)nc * 4);
     for (int32_t i = 0; i < nsel; ++i) {
         int32_t c = cells[i];
-        if (c < 0 || c >= nc || mark[c]) { free(mark); s->status |= OR_ST_BAD_CELL; return -1; }
+        if (c < 0 || c >= nc || mark[c]) {
+            free(mark);
+            s->status |= OR_ST_BAD_CELL;
+            s->reseed_events += 1;
+            return -1;
+        }
         mark[c] = i + 1;
     }
     uint32_t e = (uint32_t)s->reseed_events;

@@ -177,6 +177,38 @@ def _system_37(r: float):
     return A, b
 
 
+def _refine_decimal(W, r, digits=50, iters=6):
+    """Newton steps on A(r) W = b in 50-digit decimal arithmetic, so that the
+    returned doubles are the correctly rounded solution."""
+    import decimal
+
+    ctx = decimal.Context(prec=digits)
+    D = ctx.create_decimal
+    shells = [_shell(p, q) for (p, q) in _SHELLS_37]
+    S = [[D(sum(ex ** p * ey ** q for (ex, ey) in sh)) for sh in shells] for (p, q) in _CONDS_37]
+    b = [D(int(_dfact(p) * _dfact(q))) for (p, q) in _CONDS_37]
+    deg = [p + q for (p, q) in _CONDS_37]
+    x = [D(float(v)) for v in W] + [D(float(r))]
+    for _ in range(iters):
+        rr = x[8]
+        rp = [ctx.power(rr, d) for d in deg]
+        F = [ctx.subtract(sum((rp[i] * S[i][s] * x[s] for s in range(8)), D(0)), b[i]) for i in range(9)]
+        J = [[rp[i] * S[i][s] for s in range(8)] +
+             [sum((D(deg[i]) * rp[i] / rr * S[i][s] * x[s] for s in range(8)), D(0))] for i in range(9)]
+        # Gaussian elimination with partial pivoting on J dx = F
+        M = [J[i] + [F[i]] for i in range(9)]
+        for col in range(9):
+            piv = max(range(col, 9), key=lambda i: abs(M[i][col]))
+            M[col], M[piv] = M[piv], M[col]
+            for i in range(9):
+                if i != col:
+                    f = M[i][col] / M[col][col]
+                    M[i] = [a - f * c for a, c in zip(M[i], M[col])]
+        dx = [M[i][9] / M[i][i] for i in range(9)]
+        x = [a - d for a, d in zip(x, dx)]
+    return np.array([float(v) for v in x[:8]]), float(x[8])
+
+
 def _derive_d2q37():
     """Gauss-Hermite conditions for the 37-speed 2-D lattice.
 
@@ -221,6 +253,7 @@ def _derive_d2q37():
         step = np.linalg.solve(J, F)
         W = W - step[:8]
         r = r - step[8]
+    W, r = _refine_decimal(W, r)
     e, w = [], []
     for (p, q), ws in zip(_SHELLS_37, W):
         for v in _shell(p, q):

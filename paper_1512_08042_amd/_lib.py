@@ -1,0 +1,105 @@
+"""ctypes declarations of the C ABI in include/dsmc.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdsmc.so")
+
+c_i32, c_i64, c_u32, c_u64, c_d, c_p, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64,
+                                              ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t)
+
+OK, EINVAL, ECAPACITY, EHIP, ESTATE = 0, -1, -2, -3, -4
+ST_WALL_LIMIT, ST_FAR_OVERFLOW, ST_CAPACITY, ST_AR_LIMIT = 0x1, 0x2, 0x4, 0x8
+ST_NONFINITE, ST_NNEW_LIMIT, ST_BAD_CELL = 0x10, 0x20, 0x40
+NMOM = 11
+K_COLLIDE, K_PASS_COUNT, K_CELL_COUNT, K_SCAN, K_CELL_FINAL, K_PASS_SCATTER, K_SAMPLE, K_PROJECT, K_RESEED = range(9)
+KERNEL_NAMES = ("collide", "pass_count", "cell_count", "scan", "cell_final", "pass_scatter", "sample", "project",
+                "reseed")
+
+# every symbol include/dsmc.h declares
+EXPORTS = ("dsmc_query_sizes", "dsmc_init", "dsmc_step", "dsmc_sample_moments", "map_dsmc_to_lbm",
+           "dsmc_project_moments", "map_lbm_to_dsmc", "lbm_step", "dsmc_lattice", "dsmc_read_status",
+           "dsmc_get_views", "dsmc_profile_enable", "dsmc_profile_read", "dsmc_destroy", "dsmc_strerror")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("nx", c_i32), ("ny", c_i32), ("ppc", c_i32), ("nbar_mode", c_i32), ("capacity", c_i64),
+                ("kn", c_d), ("dt", c_d), ("body_force_x", c_d), ("kT_over_m", c_d), ("sigcr_max0", c_d),
+                ("seed", c_u64), ("ar_max_tries", c_i32), ("far_capacity", c_i32)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("ncells", c_i64), ("capacity", c_i64), ("state_array_bytes", c_sz), ("workspace_bytes", c_sz)]
+
+
+class Buffers(ctypes.Structure):
+    _fields_ = [("state", (c_p * 5) * 2), ("workspace", c_p), ("workspace_bytes", c_sz)]
+
+
+class Views(ctypes.Structure):
+    _fields_ = [("current", c_i32), ("cell_start", c_p), ("nbar", c_p), ("sigcmax", c_p), ("rem", c_p),
+                ("mom_sums", c_p), ("nsamples", c_i64), ("step", c_i64), ("reseed_events", c_i64)]
+
+
+class Status(ctypes.Structure):
+    _fields_ = [("bits", c_u32), ("reserved", c_u32), ("n_particles", c_i64), ("ncoll", c_u64), ("ncand", c_u64),
+                ("nwall", c_u64), ("nfar", c_u64)]
+
+
+class LbmConfig(ctypes.Structure):
+    _fields_ = [("nx", c_i32), ("ny", c_i32), ("lattice", c_i32), ("y_mode", c_i32), ("tau", c_d),
+                ("body_force_x", c_d)]
+
+
+_lib = None
+
+
+class LibraryMissing(ImportError):
+    pass
+
+
+def lib():
+    """Load libdsmc.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing("libdsmc.so is not built: run __graft_entry__.build() "
+                                 "or python paper_1512_08042_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.dsmc_query_sizes.argtypes = [P(Config), P(Sizes)]
+        L.dsmc_init.argtypes = [P(Config), P(Buffers), c_i32, c_i64, c_p, P(c_p)]
+        L.dsmc_step.argtypes = [c_p, c_i32, c_i32, c_p]
+        L.dsmc_sample_moments.argtypes = [c_p, c_p, c_i32, c_p]
+        L.map_dsmc_to_lbm.argtypes = [c_p, c_i32, c_i32, c_p, c_p]
+        L.dsmc_project_moments.argtypes = [c_p, c_i64, c_i32, c_d, c_i32, c_i32, c_p, c_p]
+        L.map_lbm_to_dsmc.argtypes = [c_p, c_i32, c_i32, c_p, c_p, c_i32, c_p]
+        L.lbm_step.argtypes = [P(LbmConfig), c_p, c_p, c_i32, c_p]
+        L.dsmc_lattice.argtypes = [c_i32, c_p, c_p, c_p]
+        L.dsmc_read_status.argtypes = [c_p, P(Status), c_i32, c_p]
+        L.dsmc_get_views.argtypes = [c_p, P(Views)]
+        L.dsmc_profile_enable.argtypes = [c_p, c_i32]
+        L.dsmc_profile_read.argtypes = [c_p, c_i32, P(c_d), P(c_i64)]
+        L.dsmc_destroy.argtypes = [c_p]
+        L.dsmc_destroy.restype = None
+        L.dsmc_strerror.argtypes = [ctypes.c_int]
+        L.dsmc_strerror.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("dsmc_destroy", "dsmc_strerror"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class DsmcError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = lib().dsmc_strerror(code).decode()
+        super().__init__("%s failed: %s (%d)" % (where, msg, code))
+
+
+def check(rc, where):
+    if rc != OK:
+        raise DsmcError(rc, where)

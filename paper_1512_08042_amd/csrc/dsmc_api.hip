@@ -1,0 +1,833 @@
+// Host side of libdsmc: the C ABI declared in include/dsmc.h.
+// Built as one translation unit with the kernel sources (unity build), so
+// every kernel is launched from the unit that defines it.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/dsmc.h"
+#include "dsmc_device.hpp"
+#include "step_kernels.hpp"
+#include "step_kernels.hip"
+#include "map_kernels.hip"
+
+using namespace dsmc;
+
+namespace {
+
+// ---- lattices -----------------------------------------------------------------
+// Ordering (the ABI order of populations): shells of increasing |e|, counter-
+// clockwise within a shell from the first-octant representative.
+void shell(int p, int q, std::vector<int> &ex, std::vector<int> &ey)
+{
+    auto add = [&](int a, int b) {
+        ex.push_back(a);
+        ey.push_back(b);
+    };
+    if (p == 0 && q == 0) {
+        add(0, 0);
+    } else if (q == 0) {
+        add(p, 0), add(0, p), add(-p, 0), add(0, -p);
+    } else if (p == q) {
+        add(p, p), add(-p, p), add(-p, -p), add(p, -p);
+    } else {
+        add(p, q), add(q, p), add(-q, p), add(-p, q), add(-p, -q), add(-q, -p), add(q, -p), add(p, -q);
+    }
+}
+
+const int SHELLS37[8][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}, {3, 0}, {3, 1}};
+
+long double gauss_moment(int n)  // (n-1)!! for even n
+{
+    if (n % 2) return 0.0L;
+    long double v = 1.0L;
+    for (int k = n - 1; k > 0; k -= 2) v *= (long double)k;
+    return v;
+}
+
+// sum over shell s of e_x^p e_y^q
+long double shell_moment(int s, int p, int q)
+{
+    std::vector<int> ex, ey;
+    shell(SHELLS37[s][0], SHELLS37[s][1], ex, ey);
+    long double acc = 0.0L;
+    for (size_t i = 0; i < ex.size(); ++i) acc += powl((long double)ex[i], p) * powl((long double)ey[i], q);
+    return acc;
+}
+
+// D2Q37 by the Gauss-Hermite conditions: for a trial scale r the shell
+// weights follow from eight moment conditions (a linear solve; this subset
+// of the degree <= 8 conditions is the well-conditioned one), and r is the
+// root of the residual of the ninth condition, x^8, found by secant
+// iteration in extended precision.
+bool d2q37_weights(long double r, long double W[8], long double *resid)
+{
+    static const int cond[8][2] = {{0, 0}, {2, 0}, {4, 0}, {2, 2}, {6, 0}, {4, 2}, {6, 2}, {4, 4}};
+    long double A[8][9];
+    for (int i = 0; i < 8; ++i) {
+        const int p = cond[i][0], q = cond[i][1];
+        const long double rp = powl(r, p + q);
+        for (int s = 0; s < 8; ++s) A[i][s] = rp * shell_moment(s, p, q);
+        A[i][8] = gauss_moment(p) * gauss_moment(q);
+    }
+    for (int col = 0; col < 8; ++col) {
+        int piv = col;
+        for (int i = col + 1; i < 8; ++i)
+            if (fabsl(A[i][col]) > fabsl(A[piv][col])) piv = i;
+        if (A[piv][col] == 0.0L) return false;
+        if (piv != col)
+            for (int k = 0; k < 9; ++k) {
+                const long double t = A[col][k];
+                A[col][k] = A[piv][k];
+                A[piv][k] = t;
+            }
+        for (int i = 0; i < 8; ++i) {
+            if (i == col) continue;
+            const long double m = A[i][col] / A[col][col];
+            for (int k = col; k < 9; ++k) A[i][k] -= m * A[col][k];
+        }
+    }
+    for (int s = 0; s < 8; ++s) W[s] = A[s][8] / A[s][s];
+    long double m80 = 0.0L;
+    for (int s = 0; s < 8; ++s) m80 += W[s] * shell_moment(s, 8, 0);
+    *resid = m80 * powl(r, 8) - gauss_moment(8);
+    return true;
+}
+
+bool make_lattice(int Q, Lattice &L)
+{
+    std::memset(&L, 0, sizeof(L));
+    std::vector<int> ex, ey;
+    std::vector<long double> w;
+    long double r;
+    if (Q == 9) {
+        shell(0, 0, ex, ey), shell(1, 0, ex, ey), shell(1, 1, ex, ey);
+        w = {4.0L / 9.0L, 1.0L / 9.0L, 1.0L / 9.0L, 1.0L / 9.0L, 1.0L / 9.0L,
+             1.0L / 36.0L, 1.0L / 36.0L, 1.0L / 36.0L, 1.0L / 36.0L};
+        L.Q = 9;
+        L.r = std::sqrt(3.0);
+        for (int a = 0; a < 9; ++a) {
+            L.w[a] = (double)w[a];
+            L.xi[a][0] = L.r * (double)ex[a];
+            L.xi[a][1] = L.r * (double)ey[a];
+        }
+        return true;
+    }
+    if (Q != 37) return false;
+    long double r0 = 1.18L, r1 = 1.21L, W[8], f0, f1;
+    if (!d2q37_weights(r0, W, &f0) || !d2q37_weights(r1, W, &f1)) return false;
+    for (int it = 0; it < 100; ++it) {
+        if (f1 == f0) break;
+        const long double r2 = r1 - f1 * (r1 - r0) / (f1 - f0);
+        r0 = r1, f0 = f1;
+        r1 = r2;
+        if (!d2q37_weights(r1, W, &f1)) return false;
+        if (fabsl(r1 - r0) < 1e-19L * r1) break;
+    }
+    r = r1;
+    if (!d2q37_weights(r, W, &f1)) return false;
+    for (int s = 0; s < 8; ++s) {
+        std::vector<int> sx, sy;
+        shell(SHELLS37[s][0], SHELLS37[s][1], sx, sy);
+        for (size_t i = 0; i < sx.size(); ++i) {
+            ex.push_back(sx[i]);
+            ey.push_back(sy[i]);
+            w.push_back(W[s]);
+        }
+    }
+    L.Q = 37;
+    L.r = (double)r;
+    for (int a = 0; a < 37; ++a) {
+        L.w[a] = (double)w[a];
+        L.xi[a][0] = L.r * (double)ex[a];
+        L.xi[a][1] = L.r * (double)ey[a];
+    }
+    return true;
+}
+
+struct LatticeTables {
+    Lattice q9, q37;
+    int e9[9][2], e37[37][2];
+    bool ok;
+    LatticeTables()
+    {
+        ok = make_lattice(9, q9) && make_lattice(37, q37);
+        for (int a = 0; a < 9; ++a) {
+            e9[a][0] = (int)std::lround(q9.xi[a][0] / q9.r);
+            e9[a][1] = (int)std::lround(q9.xi[a][1] / q9.r);
+        }
+        for (int a = 0; a < 37; ++a) {
+            e37[a][0] = (int)std::lround(q37.xi[a][0] / q37.r);
+            e37[a][1] = (int)std::lround(q37.xi[a][1] / q37.r);
+        }
+    }
+};
+
+const LatticeTables &tables()
+{
+    static const LatticeTables t;
+    return t;
+}
+
+// ---- configuration and workspace ---------------------------------------------
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool valid_config(const dsmc_config *c)
+{
+    if (!c) return false;
+    if (c->nx < 1 || c->ny < 1 || c->ppc < 1) return false;
+    if ((int64_t)c->nx * (int64_t)c->ny > (int64_t)0x3FFFFFFF) return false;
+    if (c->capacity < 1 || c->capacity > (int64_t)0x7FFFFFFF) return false;
+    if (!(c->kn > 0.0) || !(c->dt > 0.0) || !(c->kT_over_m > 0.0) || !(c->sigcr_max0 > 0.0)) return false;
+    if (!std::isfinite(c->kn) || !std::isfinite(c->dt) || !std::isfinite(c->body_force_x)) return false;
+    if (!std::isfinite(c->kT_over_m) || !std::isfinite(c->sigcr_max0)) return false;
+    if (c->nbar_mode != 0 && c->nbar_mode != 1) return false;
+    return true;
+}
+
+int far_cap_of(const dsmc_config &c)
+{
+    if (c.far_capacity > 0) return c.far_capacity;
+    return (int)(c.capacity < 65536 ? c.capacity : 65536);
+}
+
+struct Layout {
+    size_t cs0, cs1, cnt, base, countnew, farcnt, blocksum, far, nbar, sigcmax, rem, mom, mark, prm, nnew, perm, ctr,
+        total;
+};
+
+Layout make_layout(const dsmc_config &c)
+{
+    const size_t nc = (size_t)c.nx * (size_t)c.ny;
+    const size_t nblk = (nc + 255) / 256;
+    const size_t cap = (size_t)c.capacity;
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += al(bytes);
+        return at;
+    };
+    L.cs0 = take((nc + 1) * 4);
+    L.cs1 = take((nc + 1) * 4);
+    L.cnt = take(NDIR * nc * 4);
+    L.base = take(NDIR * nc * 4);
+    L.countnew = take(nc * 4);
+    L.farcnt = take(nc * 4);
+    L.blocksum = take(nblk * 4);
+    L.far = take((size_t)far_cap_of(c) * 16);
+    L.nbar = take(nc * 8);
+    L.sigcmax = take(nc * 8);
+    L.rem = take(nc * 8);
+    L.mom = take(NMOM * nc * 8);
+    L.mark = take(nc * 4);
+    L.prm = take(nc * 12 * 8);
+    L.nnew = take(nc * 4);
+    L.perm = take(cap * 8);  // permutation and per-particle cell ids of an adopted set
+    L.ctr = take(sizeof(Counters));
+    L.total = o;
+    return L;
+}
+
+struct ProfRec {
+    int kid;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct dsmc_ctx {
+    dsmc_config cfg;
+    double *st[2][5];
+    int32_t *cs[2];
+    int32_t *cnt, *base, *countnew, *farcnt, *blocksum, *far, *mark, *nnew, *perm;
+    double *nbar, *sigcmax, *rem, *mom, *prm;
+    Counters *ctr;
+    int ncells, nblk, far_cap;
+    double K, s_th;
+    Geometry G;
+    int cur;
+    int64_t step, nsamples, reseed_events;
+    bool pending_sample;
+    hipStream_t last;
+    bool prof;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+template <class F>
+int launch(dsmc_ctx *x, int kid, hipStream_t s, F &&f)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool timed = x && x->prof && kid >= 0;
+    if (timed) {
+        for (hipEvent_t *e : {&e0, &e1}) {
+            if (!x->pool.empty()) {
+                *e = x->pool.back();
+                x->pool.pop_back();
+            } else if (hipEventCreate(e) != hipSuccess) {
+                return DSMC_EHIP;
+            }
+        }
+        if (hipEventRecord(e0, s) != hipSuccess) return DSMC_EHIP;
+    }
+    f();
+    if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
+    if (timed) {
+        if (hipEventRecord(e1, s) != hipSuccess) return DSMC_EHIP;
+        x->recs.push_back(ProfRec{kid, e0, e1});
+    }
+    return DSMC_OK;
+}
+
+#define TRY(expr)                  \
+    do {                           \
+        const int rc_ = (expr);    \
+        if (rc_ != DSMC_OK) return rc_; \
+    } while (0)
+
+inline unsigned grid_cells_wave(int ncells) { return (unsigned)((ncells + 3) / 4); }
+inline unsigned grid_threads(size_t n) { return (unsigned)((n + 255) / 256); }
+
+MoveParams move_params(const dsmc_ctx *x)
+{
+    MoveParams M;
+    M.dt = x->cfg.dt;
+    M.g = x->cfg.body_force_x;
+    M.s_th = x->s_th;
+    M.k0 = (uint32_t)x->cfg.seed;
+    M.k1 = (uint32_t)(x->cfg.seed >> 32);
+    M.step = (uint32_t)x->step;
+    return M;
+}
+
+// take the pending sample of the current state (post-collision state of the
+// last step) if the last dsmc_step left one
+int flush_sample(dsmc_ctx *x, hipStream_t s)
+{
+    if (!x->pending_sample) return DSMC_OK;
+    SampleArgs a;
+    for (int k = 0; k < 3; ++k) a.v[k] = x->st[x->cur][2 + k];
+    a.cs = x->cs[x->cur];
+    a.mom = x->mom;
+    a.ncells = x->ncells;
+    x->pending_sample = false;
+    return launch(x, DSMC_K_SAMPLE, s, [&] { k_sample<<<grid_cells_wave(x->ncells), 256, 0, s>>>(a); });
+}
+
+int fill_f64(double *p, size_t n, double v, hipStream_t s)
+{
+    if (n == 0) return DSMC_OK;
+    k_fill_f64<<<grid_threads(n), 256, 0, s>>>(p, n, v);
+    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
+int fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t s)
+{
+    if (n == 0) return DSMC_OK;
+    k_fill_i32<<<grid_threads(n), 256, 0, s>>>(p, n, v);
+    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
+// exclusive scan of per-cell counts into cs[0..ncells] (cs[ncells] = total)
+int scan_counts(dsmc_ctx *x, const int32_t *counts, int32_t *cs, hipStream_t s)
+{
+    k_block_sums<<<x->nblk, 256, 0, s>>>(counts, x->ncells, x->blocksum);
+    k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, cs, x->ncells);
+    k_block_scan<<<x->nblk, 256, 0, s>>>(counts, x->ncells, x->blocksum, cs);
+    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
+const Lattice *lattice_of(int q)
+{
+    const LatticeTables &t = tables();
+    if (!t.ok) return nullptr;
+    if (q == 9) return &t.q9;
+    if (q == 37) return &t.q37;
+    return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dsmc_strerror(int code)
+{
+    switch (code) {
+        case DSMC_OK: return "ok";
+        case DSMC_EINVAL: return "invalid argument";
+        case DSMC_ECAPACITY: return "capacity exceeded";
+        case DSMC_EHIP: return "HIP runtime error";
+        case DSMC_ESTATE: return "invalid call for the current state";
+        default: return "unknown error";
+    }
+}
+
+int dsmc_query_sizes(const dsmc_config *cfg, dsmc_sizes *out)
+{
+    if (!valid_config(cfg) || !out) return DSMC_EINVAL;
+    const Layout L = make_layout(*cfg);
+    out->ncells = (int64_t)cfg->nx * cfg->ny;
+    out->capacity = cfg->capacity;
+    out->state_array_bytes = (size_t)cfg->capacity * 8;
+    out->workspace_bytes = L.total;
+    return DSMC_OK;
+}
+
+int dsmc_lattice(int32_t lattice, int32_t *e_out, double *w_out, double *r_out)
+{
+    const Lattice *L = lattice_of(lattice);
+    if (!L) return DSMC_EINVAL;
+    const LatticeTables &t = tables();
+    for (int a = 0; a < L->Q; ++a) {
+        if (e_out) {
+            e_out[2 * a] = lattice == 9 ? t.e9[a][0] : t.e37[a][0];
+            e_out[2 * a + 1] = lattice == 9 ? t.e9[a][1] : t.e37[a][1];
+        }
+        if (w_out) w_out[a] = L->w[a];
+    }
+    if (r_out) *r_out = L->r;
+    return DSMC_OK;
+}
+
+int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int64_t n_load, void *stream,
+              dsmc_ctx **out)
+{
+    if (!out || !valid_config(cfg) || !buf || !buf->workspace) return DSMC_EINVAL;
+    *out = nullptr;
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < 5; ++k)
+            if (!buf->state[b][k]) return DSMC_EINVAL;
+    if (((uintptr_t)buf->workspace & 255u) != 0) return DSMC_EINVAL;
+    const Layout L = make_layout(*cfg);
+    if (buf->workspace_bytes < L.total) return DSMC_EINVAL;
+    if (mode != 0 && mode != 1) return DSMC_EINVAL;
+    const int64_t ncells = (int64_t)cfg->nx * cfg->ny;
+    if (mode == 0 && ncells * cfg->ppc > cfg->capacity) return DSMC_ECAPACITY;
+    if (mode == 1 && (n_load < 0 || n_load > cfg->capacity)) return n_load < 0 ? DSMC_EINVAL : DSMC_ECAPACITY;
+    if (!tables().ok) return DSMC_EINVAL;
+
+    dsmc_ctx *x = new (std::nothrow) dsmc_ctx();
+    if (!x) return DSMC_EINVAL;
+    x->cfg = *cfg;
+    char *w = (char *)buf->workspace;
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < 5; ++k) x->st[b][k] = buf->state[b][k];
+    x->cs[0] = (int32_t *)(w + L.cs0);
+    x->cs[1] = (int32_t *)(w + L.cs1);
+    x->cnt = (int32_t *)(w + L.cnt);
+    x->base = (int32_t *)(w + L.base);
+    x->countnew = (int32_t *)(w + L.countnew);
+    x->farcnt = (int32_t *)(w + L.farcnt);
+    x->blocksum = (int32_t *)(w + L.blocksum);
+    x->far = (int32_t *)(w + L.far);
+    x->nbar = (double *)(w + L.nbar);
+    x->sigcmax = (double *)(w + L.sigcmax);
+    x->rem = (double *)(w + L.rem);
+    x->mom = (double *)(w + L.mom);
+    x->mark = (int32_t *)(w + L.mark);
+    x->prm = (double *)(w + L.prm);
+    x->nnew = (int32_t *)(w + L.nnew);
+    x->perm = (int32_t *)(w + L.perm);
+    x->ctr = (Counters *)(w + L.ctr);
+    x->ncells = (int)ncells;
+    x->nblk = (int)((ncells + 255) / 256);
+    x->far_cap = far_cap_of(*cfg);
+    const double lambda = cfg->kn * (double)cfg->ny;
+    // Eq. (MFP): lambda = 1/(sqrt(2) pi d^2 n), n = ppc F_N / V_c
+    x->K = 1.0 / (std::sqrt(2.0) * lambda * (double)cfg->ppc);
+    x->s_th = std::sqrt(cfg->kT_over_m);
+    x->G.nx = cfg->nx;
+    x->G.ny = cfg->ny;
+    x->G.Lx = (double)cfg->nx;
+    x->G.H = (double)cfg->ny;
+    x->cur = 0;
+    x->step = 0;
+    x->nsamples = 0;
+    x->reseed_events = 0;
+    x->pending_sample = false;
+    x->prof = false;
+    hipStream_t s = S(stream);
+    x->last = s;
+
+    int rc = DSMC_OK;
+    k_zero_counters<<<1, 64, 0, s>>>(x->ctr);
+    if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
+    if (rc == DSMC_OK) rc = fill_f64(x->mom, (size_t)NMOM * ncells, 0.0, s);
+    if (rc == DSMC_OK) rc = fill_i32(x->farcnt, (size_t)ncells, 0, s);
+    if (rc == DSMC_OK) rc = fill_i32(x->mark, (size_t)ncells, 0, s);
+    if (rc == DSMC_OK && mode == 0) {
+        InitArgs a;
+        for (int k = 0; k < 5; ++k) a.st[k] = x->st[0][k];
+        a.cs = x->cs[0];
+        a.nbar = x->nbar;
+        a.sigcmax = x->sigcmax;
+        a.rem = x->rem;
+        a.nx = cfg->nx;
+        a.ncells = x->ncells;
+        a.ppc = cfg->ppc;
+        a.s_th = x->s_th;
+        a.sigcr0 = cfg->sigcr_max0;
+        a.k0 = (uint32_t)cfg->seed;
+        a.k1 = (uint32_t)(cfg->seed >> 32);
+        const size_t n = (size_t)ncells * cfg->ppc;
+        const size_t nthreads = n > (size_t)ncells + 1 ? n : (size_t)ncells + 1;
+        k_init_maxwell<<<grid_threads(nthreads), 256, 0, s>>>(a);
+        if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
+        x->cur = 0;
+    } else if (rc == DSMC_OK) {
+        // adopt: stable sort of buffer 0 into buffer 1 by cell
+        AdoptArgs a;
+        for (int k = 0; k < 5; ++k) {
+            a.in[k] = x->st[0][k];
+            a.out[k] = x->st[1][k];
+        }
+        a.cellid = x->perm + cfg->capacity;  // second half of the permutation space
+        a.counts = x->countnew;
+        a.cursor = x->farcnt;
+        a.perm = x->perm;
+        a.cs = x->cs[1];
+        a.G = x->G;
+        a.n = n_load;
+        {
+            rc = fill_i32(x->countnew, (size_t)ncells, 0, s);
+            if (rc == DSMC_OK && n_load > 0) {
+                k_adopt_count<<<grid_threads((size_t)n_load), 256, 0, s>>>(a);
+                if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
+            }
+            if (rc == DSMC_OK) rc = scan_counts(x, x->countnew, x->cs[1], s);
+            if (rc == DSMC_OK && n_load > 0) {
+                k_adopt_place<<<grid_threads((size_t)n_load), 256, 0, s>>>(a);
+                k_adopt_sortcell<<<grid_threads((size_t)ncells), 256, 0, s>>>(a);
+                k_adopt_gather<<<grid_threads((size_t)n_load), 256, 0, s>>>(a);
+                if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
+            }
+            if (rc == DSMC_OK) rc = fill_f64(x->nbar, (size_t)ncells, 0.0, s);
+            if (rc == DSMC_OK) rc = fill_f64(x->sigcmax, (size_t)ncells, cfg->sigcr_max0, s);
+            if (rc == DSMC_OK) rc = fill_f64(x->rem, (size_t)ncells, 0.0, s);
+            x->cur = 1;
+        }
+    }
+    if (rc != DSMC_OK) {
+        delete x;
+        return rc;
+    }
+    *out = x;
+    return DSMC_OK;
+}
+
+int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
+{
+    if (!x || nsteps < 0 || sample_every < 0) return DSMC_EINVAL;
+    hipStream_t s = S(stream);
+    x->last = s;
+    const int nc = x->ncells;
+    for (int32_t it = 0; it < nsteps; ++it) {
+        const int cur = x->cur, nxt = 1 - cur;
+        PassArgs p;
+        for (int k = 0; k < 5; ++k) {
+            p.in[k] = x->st[cur][k];
+            p.out[k] = x->st[nxt][k];
+        }
+        p.cs = x->cs[cur];
+        p.cnt = x->cnt;
+        p.base = x->base;
+        p.farcnt = x->farcnt;
+        p.far = x->far;
+        p.ctr = x->ctr;
+        p.mom = x->mom;
+        p.G = x->G;
+        p.M = move_params(x);
+        p.ncells = nc;
+        p.far_cap = x->far_cap;
+        p.sample = x->pending_sample ? 1 : 0;
+        x->pending_sample = false;
+        TRY(launch(x, DSMC_K_PASS_COUNT, s, [&] { k_pass<false><<<grid_cells_wave(nc), 256, 0, s>>>(p); }));
+
+        CellArgs c;
+        c.cnt = x->cnt;
+        c.base = x->base;
+        c.farcnt = x->farcnt;
+        c.far = x->far;
+        c.countnew = x->countnew;
+        c.blocksum = x->blocksum;
+        c.cs_new = x->cs[nxt];
+        c.ctr = x->ctr;
+        c.nx = x->cfg.nx;
+        c.ny = x->cfg.ny;
+        c.ncells = nc;
+        c.far_cap = x->far_cap;
+        TRY(launch(x, DSMC_K_CELL_COUNT, s, [&] { k_cell_count<<<x->nblk, 256, 0, s>>>(c); }));
+        TRY(launch(x, DSMC_K_SCAN, s,
+                   [&] { k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, x->cs[nxt], nc); }));
+        TRY(launch(x, DSMC_K_CELL_FINAL, s, [&] { k_cell_final<<<x->nblk, 256, 0, s>>>(c); }));
+
+        p.sample = 0;
+        TRY(launch(x, DSMC_K_PASS_SCATTER, s, [&] { k_pass<true><<<grid_cells_wave(nc), 256, 0, s>>>(p); }));
+        x->cur = nxt;
+
+        CollideArgs ca;
+        for (int k = 0; k < 3; ++k) ca.v[k] = x->st[nxt][2 + k];
+        ca.cs = x->cs[nxt];
+        ca.nbar = x->nbar;
+        ca.sigcmax = x->sigcmax;
+        ca.rem = x->rem;
+        ca.ctr = x->ctr;
+        ca.ncells = nc;
+        ca.nbar_mode = x->cfg.nbar_mode;
+        ca.K = x->K;
+        ca.dt = x->cfg.dt;
+        ca.k0 = (uint32_t)x->cfg.seed;
+        ca.k1 = (uint32_t)(x->cfg.seed >> 32);
+        ca.step = (uint32_t)x->step;
+        TRY(launch(x, DSMC_K_COLLIDE, s, [&] { k_collide<<<grid_threads((size_t)nc), 256, 0, s>>>(ca); }));
+        if (sample_every > 0 && ((x->step + 1) % sample_every) == 0) {
+            x->pending_sample = true;
+            x->nsamples += 1;
+        }
+        x->step += 1;
+    }
+    return DSMC_OK;
+}
+
+int dsmc_sample_moments(dsmc_ctx *x, double *out, int32_t reset, void *stream)
+{
+    if (!x) return DSMC_EINVAL;
+    hipStream_t s = S(stream);
+    x->last = s;
+    TRY(flush_sample(x, s));
+    if (out) {
+        if (x->nsamples <= 0) return DSMC_ESTATE;
+        const size_t n = (size_t)NMOM * x->ncells;
+        const double Sd = (double)x->nsamples;
+        TRY(launch(x, -1, s, [&] { k_average<<<grid_threads(n), 256, 0, s>>>(x->mom, out, n, Sd); }));
+    }
+    if (reset) {
+        TRY(fill_f64(x->mom, (size_t)NMOM * x->ncells, 0.0, s));
+        x->nsamples = 0;
+    }
+    return DSMC_OK;
+}
+
+static int project(dsmc_ctx *x, const double *mom, double S_, int64_t ncells, int32_t ppc, double kT, int32_t lattice,
+                   int32_t order, double *f_out, hipStream_t s)
+{
+    const Lattice *L = lattice_of(lattice);
+    if (!L || order < 0 || order > 3 || !f_out || !mom || ncells < 1 || ppc < 1 || !(kT > 0.0)) return DSMC_EINVAL;
+    ProjectArgs a;
+    a.mom = mom;
+    a.S = S_;
+    a.f = f_out;
+    a.L = *L;
+    a.ncells = (int)ncells;
+    a.ppc = ppc;
+    a.order = order;
+    a.s1 = std::sqrt(kT);
+    return launch(x, DSMC_K_PROJECT, s, [&] { k_project<<<grid_threads((size_t)ncells), 256, 0, s>>>(a); });
+}
+
+int map_dsmc_to_lbm(dsmc_ctx *x, int32_t lattice, int32_t order, double *f_out, void *stream)
+{
+    if (!x) return DSMC_EINVAL;
+    if (!lattice_of(lattice) || order < 0 || order > 3 || !f_out) return DSMC_EINVAL;
+    hipStream_t s = S(stream);
+    x->last = s;
+    TRY(flush_sample(x, s));
+    if (x->nsamples <= 0) return DSMC_ESTATE;
+    return project(x, x->mom, (double)x->nsamples, x->ncells, x->cfg.ppc, x->cfg.kT_over_m, lattice, order, f_out, s);
+}
+
+int dsmc_project_moments(const double *avg, int64_t ncells, int32_t ppc, double kT_over_m, int32_t lattice,
+                         int32_t order, double *f_out, void *stream)
+{
+    if (ncells > (int64_t)0x3FFFFFFF) return DSMC_EINVAL;
+    return project(nullptr, avg, 1.0, ncells, ppc, kT_over_m, lattice, order, f_out, S(stream));
+}
+
+int map_lbm_to_dsmc(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f_in, const int32_t *cell_ids,
+                    int32_t nsel, void *stream)
+{
+    if (!x) return DSMC_EINVAL;
+    const Lattice *L = lattice_of(lattice);
+    if (!L || (order != 2 && order != 3) || !f_in || nsel < 0 || (nsel > 0 && !cell_ids)) return DSMC_EINVAL;
+    if (nsel > x->ncells) return DSMC_EINVAL;
+    hipStream_t s = S(stream);
+    x->last = s;
+    TRY(flush_sample(x, s));
+    const uint32_t event = (uint32_t)x->reseed_events;
+    x->reseed_events += 1;
+    const int cur = x->cur, nxt = 1 - cur;
+    ReseedArgs a;
+    a.f = f_in;
+    a.cells = cell_ids;
+    a.nsel = nsel;
+    a.mark = x->mark;
+    a.prm = x->prm;
+    a.nnew = x->nnew;
+    a.cs_old = x->cs[cur];
+    a.cs_new = x->cs[nxt];
+    a.countnew = x->countnew;
+    a.blocksum = x->blocksum;
+    for (int k = 0; k < 5; ++k) {
+        a.in[k] = x->st[cur][k];
+        a.out[k] = x->st[nxt][k];
+    }
+    a.ctr = x->ctr;
+    a.L = *L;
+    a.nx = x->cfg.nx;
+    a.ncells = x->ncells;
+    a.ppc = x->cfg.ppc;
+    a.order = order;
+    a.ar_max_tries = x->cfg.ar_max_tries > 0 ? x->cfg.ar_max_tries : 65536;
+    a.capacity = x->cfg.capacity;
+    a.s_th = x->s_th;
+    a.k0 = (uint32_t)x->cfg.seed;
+    a.k1 = (uint32_t)(x->cfg.seed >> 32);
+    a.event = event;
+    const unsigned gsel = grid_threads((size_t)(nsel > 0 ? nsel : 1));
+    TRY(launch(x, DSMC_K_RESEED, s, [&] {
+        if (nsel > 0) k_reseed_prep<<<gsel, 256, 0, s>>>(a);
+        k_reseed_count<<<x->nblk, 256, 0, s>>>(a);
+        k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, x->cs[nxt], x->ncells);
+        k_block_scan<<<x->nblk, 256, 0, s>>>(x->countnew, x->ncells, x->blocksum, x->cs[nxt]);
+        k_reseed_check<<<1, 64, 0, s>>>(a);
+        k_reseed_scatter<<<grid_cells_wave(x->ncells), 256, 0, s>>>(a);
+        k_reseed_unmark<<<gsel, 256, 0, s>>>(a);
+    }));
+    x->cur = nxt;
+    return DSMC_OK;
+}
+
+int lbm_step(const lbm_config *cfg, double *f, double *f_tmp, int32_t nsteps, void *stream)
+{
+    if (!cfg || !f || !f_tmp || nsteps < 0 || cfg->nx < 1 || cfg->ny < 1) return DSMC_EINVAL;
+    if ((int64_t)cfg->nx * cfg->ny > (int64_t)0x3FFFFFFF) return DSMC_EINVAL;
+    const Lattice *L = lattice_of(cfg->lattice);
+    if (!L || !(cfg->tau > 0.5) || !std::isfinite(cfg->tau) || !std::isfinite(cfg->body_force_x)) return DSMC_EINVAL;
+    if (cfg->y_mode != 0 && cfg->y_mode != 1) return DSMC_EINVAL;
+    const LatticeTables &t = tables();
+    LbmArgs a;
+    a.L = *L;
+    int K = 0;
+    for (int q = 0; q < L->Q; ++q) {
+        a.ex[q] = cfg->lattice == 9 ? t.e9[q][0] : t.e37[q][0];
+        a.ey[q] = cfg->lattice == 9 ? t.e9[q][1] : t.e37[q][1];
+        if (std::abs(a.ey[q]) > K) K = std::abs(a.ey[q]);
+    }
+    a.nx = cfg->nx;
+    a.ny = cfg->ny;
+    a.y_mode = cfg->y_mode;
+    a.K = K;
+    a.tau = cfg->tau;
+    a.gx = cfg->body_force_x;
+    hipStream_t s = S(stream);
+    const size_t nn = (size_t)cfg->nx * cfg->ny;
+    double *src = f, *dst = f_tmp;
+    for (int32_t it = 0; it < nsteps; ++it) {
+        a.f = src;
+        a.ft = dst;
+        k_lbm<<<grid_threads(nn), 256, 0, s>>>(a);
+        if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
+        double *t2 = src;
+        src = dst;
+        dst = t2;
+    }
+    if (src != f) {
+        if (hipMemcpyAsync(f, src, nn * (size_t)L->Q * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return DSMC_EHIP;
+    }
+    return DSMC_OK;
+}
+
+int dsmc_read_status(dsmc_ctx *x, dsmc_status *out, int32_t clear, void *stream)
+{
+    if (!x || !out) return DSMC_EINVAL;
+    hipStream_t s = S(stream);
+    Counters h;
+    int32_t n = 0;
+    if (hipMemcpyAsync(&h, x->ctr, sizeof(Counters), hipMemcpyDeviceToHost, s) != hipSuccess) return DSMC_EHIP;
+    if (hipMemcpyAsync(&n, x->cs[x->cur] + x->ncells, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return DSMC_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return DSMC_EHIP;
+    out->bits = h.status;
+    out->reserved = 0;
+    out->n_particles = n;
+    out->ncoll = h.ncoll;
+    out->ncand = h.ncand;
+    out->nwall = h.nwall;
+    out->nfar = h.nfar_total + h.nfar;
+    if (clear) {
+        k_clear_status<<<1, 64, 0, s>>>(x->ctr);
+        if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
+    }
+    return DSMC_OK;
+}
+
+int dsmc_get_views(dsmc_ctx *x, dsmc_views *out)
+{
+    if (!x || !out) return DSMC_EINVAL;
+    TRY(flush_sample(x, x->last));
+    out->current = x->cur;
+    out->cell_start = x->cs[x->cur];
+    out->nbar = x->nbar;
+    out->sigcmax = x->sigcmax;
+    out->rem = x->rem;
+    out->mom_sums = x->mom;
+    out->nsamples = x->nsamples;
+    out->step = x->step;
+    out->reseed_events = x->reseed_events;
+    return DSMC_OK;
+}
+
+int dsmc_profile_enable(dsmc_ctx *x, int32_t enable)
+{
+    if (!x) return DSMC_EINVAL;
+    x->prof = enable != 0;
+    return DSMC_OK;
+}
+
+int dsmc_profile_read(dsmc_ctx *x, int32_t kernel, double *ms_total, int64_t *launches)
+{
+    if (!x || kernel < 0 || kernel >= DSMC_K_COUNT) return DSMC_EINVAL;
+    double tot = 0.0;
+    int64_t cnt = 0;
+    std::vector<ProfRec> keep;
+    for (const ProfRec &r : x->recs) {
+        if (r.kid != kernel) {
+            keep.push_back(r);
+            continue;
+        }
+        if (hipEventSynchronize(r.b) != hipSuccess) return DSMC_EHIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return DSMC_EHIP;
+        tot += ms;
+        cnt += 1;
+        x->pool.push_back(r.a);
+        x->pool.push_back(r.b);
+    }
+    x->recs.swap(keep);
+    if (ms_total) *ms_total = tot;
+    if (launches) *launches = cnt;
+    return DSMC_OK;
+}
+
+void dsmc_destroy(dsmc_ctx *x)
+{
+    if (!x) return;
+    for (const ProfRec &r : x->recs) {
+        (void)hipEventSynchronize(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : x->pool) (void)hipEventDestroy(e);
+    delete x;
+}
+
+}  // extern "C"

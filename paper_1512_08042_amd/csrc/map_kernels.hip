@@ -1,0 +1,364 @@
+// DSMC<->LBM mapping kernels and the BGK lattice step on gfx950.
+// Method: Di Staso, Clercx, Succi & Toschi, arXiv:1512.08042, Section 2.
+#include "dsmc_device.hpp"
+#include "step_kernels.hpp"
+
+namespace dsmc {
+
+// ---- DSMC2LB (Eq. (discretefunctions)), one thread per cell ------------------
+// From the cumulative averages of the sampled sums: rho = <N>/ppc (the mass
+// scale of the appendix), the absolute-frame Hermite coefficients a(1..3)
+// of Eq. (nordercoefficients) from the raw velocity moments (in units of
+// sqrt(kT/m)), and f_a = w_a sum_{n<=order} a(n):H(n)(xi_a)/n!.  D2Q9
+// cannot carry H_xxx and H_yyy (they vanish on its nodes): those terms are
+// left out there.
+__global__ __launch_bounds__(256) void k_project(ProjectArgs a)
+{
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= a.ncells) return;
+    const int nc = a.ncells;
+    double m[NMOM];
+#pragma unroll
+    for (int k = 0; k < NMOM; ++k) m[k] = a.mom[(size_t)k * nc + c] / a.S;
+    const int Q = a.L.Q;
+    if (!(m[0] > 0.0)) {
+        for (int q = 0; q < Q; ++q) a.f[(size_t)q * nc + c] = 0.0;
+        return;
+    }
+    const double s1 = a.s1;
+    const double rho = m[0] / (double)a.ppc;
+    const double ex = (m[1] / m[0]) / s1, ey = (m[2] / m[0]) / s1;
+    const double s2 = s1 * s1, s3 = s2 * s1;
+    const double exx = (m[3] / m[0]) / s2, exy = (m[4] / m[0]) / s2, eyy = (m[5] / m[0]) / s2;
+    const double exxx = (m[6] / m[0]) / s3, exxy = (m[7] / m[0]) / s3;
+    const double exyy = (m[8] / m[0]) / s3, eyyy = (m[9] / m[0]) / s3;
+    const double a1x = rho * ex, a1y = rho * ey;
+    const double a2xx = rho * (exx - 1.0), a2xy = rho * exy, a2yy = rho * (eyy - 1.0);
+    const double a3xxx = rho * (exxx - 3.0 * ex), a3xxy = rho * (exxy - ey);
+    const double a3xyy = rho * (exyy - ex), a3yyy = rho * (eyyy - 3.0 * ey);
+    const int order = a.order;
+    for (int q = 0; q < Q; ++q) {
+        const double x = a.L.xi[q][0], y = a.L.xi[q][1];
+        double v = rho;
+        if (order >= 1) v += a1x * x + a1y * y;
+        if (order >= 2) {
+            const double hxx = x * x - 1.0, hxy = x * y, hyy = y * y - 1.0;
+            v += 0.5 * (a2xx * hxx + 2.0 * a2xy * hxy + a2yy * hyy);
+        }
+        if (order >= 3) {
+            const double hxxy = x * x * y - y, hxyy = x * y * y - x;
+            double t3 = 3.0 * a3xxy * hxxy + 3.0 * a3xyy * hxyy;
+            if (Q != 9) {
+                const double hxxx = x * x * x - 3.0 * x, hyyy = y * y * y - 3.0 * y;
+                t3 += a3xxx * hxxx + a3yyy * hyyy;
+            }
+            v += t3 / 6.0;
+        }
+        a.f[(size_t)q * nc + c] = a.L.w[q] * v;
+    }
+}
+
+// ---- LB2DSMC (Section 2.2, Table 1) ------------------------------------------
+// Table 1 steps 1-3 on node populations f[q * stride]: rho, u, comoving and
+// density-normalised a(2), a(3) about u, M = max |component|, C = 1 + 30 M.
+// prm: rho, ux, uy, a2xx, a2xy, a2yy, a3xxx, a3xxy, a3xyy, a3yyy, M, C.
+__device__ void grad_params(const double *f, size_t stride, const Lattice &L, int order, double *prm)
+{
+    const int Q = L.Q;
+    double rho = 0.0, jx = 0.0, jy = 0.0;
+    for (int q = 0; q < Q; ++q) {
+        const double fa = f[(size_t)q * stride];
+        rho += fa;
+        jx += fa * L.xi[q][0];
+        jy += fa * L.xi[q][1];
+    }
+    for (int k = 0; k < 12; ++k) prm[k] = 0.0;
+    prm[0] = rho;
+    if (!(rho > 0.0)) return;
+    const double ux = jx / rho, uy = jy / rho;
+    double sxx = 0, sxy = 0, syy = 0, sxxx = 0, sxxy = 0, sxyy = 0, syyy = 0;
+    for (int q = 0; q < Q; ++q) {
+        const double fa = f[(size_t)q * stride];
+        const double cx = L.xi[q][0] - ux, cy = L.xi[q][1] - uy;
+        sxx += fa * (cx * cx - 1.0);
+        sxy += fa * (cx * cy);
+        syy += fa * (cy * cy - 1.0);
+        sxxx += fa * (cx * cx * cx - 3.0 * cx);
+        sxxy += fa * (cx * cx * cy - cy);
+        sxyy += fa * (cx * cy * cy - cx);
+        syyy += fa * (cy * cy * cy - 3.0 * cy);
+    }
+    double a2xx = sxx / rho, a2xy = sxy / rho, a2yy = syy / rho;
+    double a3xxx = sxxx / rho, a3xxy = sxxy / rho, a3xyy = sxyy / rho, a3yyy = syyy / rho;
+    if (order < 3) {
+        a3xxx = 0.0;
+        a3xxy = 0.0;
+        a3xyy = 0.0;
+        a3yyy = 0.0;
+    }
+    if (Q == 9) {
+        a3xxx = 0.0;
+        a3yyy = 0.0;
+    }
+    if (order < 2) {
+        a2xx = 0.0;
+        a2xy = 0.0;
+        a2yy = 0.0;
+    }
+    const double comp[7] = {a2xx, a2xy, a2yy, a3xxx, a3xxy, a3xyy, a3yyy};
+    double M = 0.0;
+    for (int k = 0; k < 7; ++k) {
+        const double v = fabs(comp[k]);
+        if (v > M) M = v;
+    }
+    prm[1] = ux;
+    prm[2] = uy;
+    prm[3] = a2xx;
+    prm[4] = a2xy;
+    prm[5] = a2yy;
+    prm[6] = a3xxx;
+    prm[7] = a3xxy;
+    prm[8] = a3xyy;
+    prm[9] = a3yyy;
+    prm[10] = M;
+    prm[11] = 1.0 + 30.0 * M;
+}
+
+// G of Eq. (distr_outeq) at xi: 1 + a(2):H(2)/2! + a(3):H(3)/3!
+__device__ __forceinline__ double grad_G(const double *p, double x, double y)
+{
+    const double hxx = x * x - 1.0, hxy = x * y, hyy = y * y - 1.0;
+    const double hxxx = x * x * x - 3.0 * x, hxxy = x * x * y - y;
+    const double hxyy = x * y * y - x, hyyy = y * y * y - 3.0 * y;
+    const double t2 = p[3] * hxx + 2.0 * p[4] * hxy + p[5] * hyy;
+    const double t3 = p[6] * hxxx + 3.0 * p[7] * hxxy + 3.0 * p[8] * hxyy + p[9] * hyyy;
+    return 1.0 + t2 / 2.0 + t3 / 6.0;
+}
+
+// Table 1 steps 4-5 for new particle k of cell c in reseed event e: Box-
+// Muller tries from counters (2t, c, e, RESEED|k), accepted when
+// C R <= G(xi) with R from counters (2t+1, c, e, RESEED|k).  After
+// max_tries rejections the last try is kept and `limit` is raised.
+__device__ __forceinline__ void ar_sample(uint32_t k0, uint32_t k1, const double *prm, uint32_t c, uint32_t e, uint32_t k,
+                                          int max_tries, double &z0, double &z1, bool &limit)
+{
+    const double C = prm[11];
+    long long t = 0;
+    for (;;) {
+        const U4 A = draw(k0, k1, (uint32_t)(2 * t), c, e, TAG_RESEED, k);
+        const U4 B = draw(k0, k1, (uint32_t)(2 * t + 1), c, e, TAG_RESEED, k);
+        box_muller(u53(A.x, A.y), u53(A.z, A.w), z0, z1);
+        const double R = u53(B.x, B.y);
+        const double G = grad_G(prm, z0, z1);
+        t += 1;
+        if (C * R <= G) break;
+        if (t >= max_tries) {
+            limit = true;
+            break;
+        }
+    }
+}
+
+// one thread per listed cell: mark the cell, Table 1 steps 1-3, and the
+// number of new particles floor(rho ppc + R) (mass conservation at the
+// coupling site), R from counters (0, c, e, RESEED_N)
+__global__ __launch_bounds__(256) void k_reseed_prep(ReseedArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.nsel) return;
+    const int c = a.cells[i];
+    a.nnew[i] = 0;
+    if (c < 0 || c >= a.ncells) {
+        atomicOr(&a.ctr->reseed_err, ST_BAD_CELL);
+        return;
+    }
+    if (atomicCAS(&a.mark[c], 0, i + 1) != 0) {
+        atomicOr(&a.ctr->reseed_err, ST_BAD_CELL);
+        return;
+    }
+    double *pr = a.prm + (size_t)i * 12;
+    grad_params(a.f + c, (size_t)a.ncells, a.L, a.order, pr);
+    const U4 r = draw(a.k0, a.k1, 0u, (uint32_t)c, a.event, TAG_RESEED_N, 0u);
+    const double target = pr[0] * (double)a.ppc + u53(r.x, r.y);
+    bool finite = true;
+    for (int k = 0; k < 12; ++k)
+        if (!isfinite(pr[k])) finite = false;
+    int nn = 0;
+    if (!finite) {
+        atomicOr(&a.ctr->status, ST_NONFINITE);
+        nn = 0;
+    } else if (target >= 16777215.0) {
+        atomicOr(&a.ctr->status, ST_NNEW_LIMIT);
+        nn = 16777215;
+    } else if (target >= 1.0) {
+        nn = (int)floor(target);
+    }
+    if (!(pr[0] > 0.0)) nn = 0;
+    a.nnew[i] = nn;
+    atomicAdd(&a.ctr->reseed_new, (unsigned long long)nn);
+    atomicAdd(&a.ctr->reseed_removed, (unsigned long long)(a.cs_old[c + 1] - a.cs_old[c]));
+}
+
+// per-cell particle counts after the reseed, and their block sums
+__global__ __launch_bounds__(256) void k_reseed_count(ReseedArgs a)
+{
+    __shared__ int lds[4];
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    int v = 0;
+    if (c < a.ncells) {
+        const int mk = a.mark[c];
+        v = mk ? a.nnew[mk - 1] : (a.cs_old[c + 1] - a.cs_old[c]);
+        a.countnew[c] = v;
+    }
+    // block sum (same reduction as the step's cell count)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) a.blocksum[blockIdx.x] = lds[0] + lds[1] + lds[2] + lds[3];
+}
+
+// decide whether the reseed goes ahead (single thread)
+__global__ void k_reseed_check(ReseedArgs a)
+{
+    if (threadIdx.x != 0) return;
+    Counters *ct = a.ctr;
+    if (ct->reseed_err & ST_BAD_CELL) ct->status |= ST_BAD_CELL;
+    const long long total = (long long)a.cs_old[a.ncells] + (long long)ct->reseed_new - (long long)ct->reseed_removed;
+    if (total > a.capacity) {
+        ct->reseed_err |= ST_CAPACITY;
+        ct->status |= ST_CAPACITY;
+    }
+}
+
+// one wave per cell: copy a kept cell's particles in order, or generate the
+// listed cell's new particles (Table 1 steps 4-6); when the reseed was
+// rejected every cell is copied unchanged
+__global__ __launch_bounds__(256) void k_reseed_scatter(ReseedArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= a.ncells) return;
+    const bool err = a.ctr->reseed_err != 0u;
+    const int s0 = a.cs_old[c], e0 = a.cs_old[c + 1];
+    if (err) {
+        if (lane == 0) {
+            a.cs_new[c] = s0;
+            if (c == a.ncells - 1) a.cs_new[a.ncells] = e0;
+        }
+        for (int p = s0 + lane; p < e0; p += 64) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) a.out[k][p] = a.in[k][p];
+        }
+        return;
+    }
+    const int d0 = a.cs_new[c];
+    const int mk = a.mark[c];
+    if (mk == 0) {
+        for (int p = s0 + lane; p < e0; p += 64) {
+            const int q = d0 + (p - s0);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) a.out[k][q] = a.in[k][p];
+        }
+        return;
+    }
+    const int i = mk - 1;
+    const int nn = a.nnew[i];
+    double prm[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) prm[k] = a.prm[(size_t)i * 12 + k];
+    const int ix = c % a.nx, iy = c / a.nx;
+    bool limit = false;
+    for (int k = lane; k < nn; k += 64) {
+        double z0, z1, zz0, zz1;
+        ar_sample(a.k0, a.k1, prm, (uint32_t)c, a.event, (uint32_t)k, a.ar_max_tries, z0, z1, limit);
+        const U4 P = draw(a.k0, a.k1, 0u, (uint32_t)c, a.event, TAG_RESEED_POS, (uint32_t)k);
+        const U4 V = draw(a.k0, a.k1, 1u, (uint32_t)c, a.event, TAG_RESEED_POS, (uint32_t)k);
+        box_muller(u53(V.x, V.y), u53(V.z, V.w), zz0, zz1);
+        const int q = d0 + k;
+        a.out[0][q] = inside_cell(ix, u53(P.x, P.y));
+        a.out[1][q] = inside_cell(iy, u53(P.z, P.w));
+        a.out[2][q] = a.s_th * (z0 + prm[1]);
+        a.out[3][q] = a.s_th * (z1 + prm[2]);
+        a.out[4][q] = a.s_th * zz0;
+    }
+    if (__ballot(limit) != 0 && lane == 0) atomicOr(&a.ctr->status, ST_AR_LIMIT);
+}
+
+__global__ __launch_bounds__(256) void k_reseed_unmark(ReseedArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) {
+        a.ctr->reseed_err = 0u;
+        a.ctr->reseed_new = 0ull;
+        a.ctr->reseed_removed = 0ull;
+    }
+    if (i >= a.nsel) return;
+    const int c = a.cells[i];
+    if (c >= 0 && c < a.ncells) a.mark[c] = 0;
+}
+
+// ---- BGK lattice step (Section 3.1), one thread per node, push streaming ----
+template <int Q>
+__device__ __forceinline__ void lbm_node(const LbmArgs &a, int node)
+{
+    const int nx = a.nx, ny = a.ny;
+    const size_t nn = (size_t)nx * ny;
+    const int ix = node % nx, iy = node / nx;
+    const bool buffer = (a.y_mode == 1) && (iy < a.K || iy >= ny - a.K);
+    double fe[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fe[q] = a.f[(size_t)q * nn + node];
+    if (buffer) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) a.ft[(size_t)q * nn + node] = fe[q];
+    } else {
+        double rho = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            rho += fe[q];
+            jx += fe[q] * a.L.xi[q][0];
+            jy += fe[q] * a.L.xi[q][1];
+        }
+        const double gx = a.gx, tau = a.tau;
+        const double ux = (jx + 0.5 * rho * gx) / rho;
+        const double uy = jy / rho;
+        const double uu = ux * ux + uy * uy;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const double cu = a.L.xi[q][0] * ux + a.L.xi[q][1] * uy;
+            double eq = 1.0 + cu + 0.5 * (cu * cu - uu);
+            if (Q != 9) eq += (cu * (cu * cu - 3.0 * uu)) / 6.0;
+            const double feq = a.L.w[q] * rho * eq;
+            const double cg = a.L.xi[q][0] * gx;
+            const double F = (1.0 - 0.5 / tau) * a.L.w[q] * rho * (cg + cg * cu - gx * ux);
+            const double fa = fe[q];
+            fe[q] = fa - (fa - feq) / tau + F;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        int jx2 = ix + a.ex[q];
+        int jy2 = iy + a.ey[q];
+        jx2 = ((jx2 % nx) + nx) % nx;
+        if (a.y_mode == 1) {
+            if (jy2 < a.K || jy2 >= ny - a.K) continue;
+        } else {
+            jy2 = ((jy2 % ny) + ny) % ny;
+        }
+        a.ft[(size_t)q * nn + (size_t)jy2 * nx + jx2] = fe[q];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lbm(LbmArgs a)
+{
+    const int node = blockIdx.x * 256 + threadIdx.x;
+    if (node >= a.nx * a.ny) return;
+    if (a.L.Q == 9)
+        lbm_node<9>(a, node);
+    else
+        lbm_node<37>(a, node);
+}
+
+}  // namespace dsmc

@@ -1,0 +1,172 @@
+"""Python binding of libdsmc: device buffers and streams come from PyTorch,
+every step of the DSMC particle step and the DSMC<->LBM mappings runs in the
+HIP kernels behind the C ABI (include/dsmc.h).  There is no CPU fallback:
+without the built library or a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+from .config import ChannelConfig
+
+NMOM = _lib.NMOM
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+def lattice(q: int):
+    """(e int[Q,2], w float64[Q], r) of the library's D2Q9 / D2Q37 tables (host copy)."""
+    import numpy as np
+
+    n = {9: 9, 37: 37}[q]
+    e = np.zeros((n, 2), dtype=np.int32)
+    w = np.zeros(n)
+    r = ctypes.c_double()
+    check(lib().dsmc_lattice(q, e.ctypes.data, w.ctypes.data, ctypes.byref(r)), "dsmc_lattice")
+    return e, w, r.value
+
+
+class Channel:
+    """A DSMC channel (periodic x, diffuse walls at y = 0 and y = ny) on one GPU."""
+
+    def __init__(self, cfg: ChannelConfig, particles=None, device: str = "cuda", stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1512_08042_amd needs a ROCm GPU; no CPU fallback exists")
+        self.cfg = c = cfg.resolved()
+        self.device = torch.device(device)
+        self._c = _lib.Config(c.nx, c.ny, c.ppc, c.nbar_mode, c.capacity, c.kn, c.dt, c.body_force_x, c.kT_over_m,
+                              c.sigcr_max0, c.seed, c.ar_max_tries, c.far_capacity)
+        sz = _lib.Sizes()
+        check(lib().dsmc_query_sizes(ctypes.byref(self._c), ctypes.byref(sz)), "dsmc_query_sizes")
+        self.ncells = int(sz.ncells)
+        self.capacity = int(sz.capacity)
+        self.state = torch.zeros((2, 5, self.capacity), dtype=torch.float64, device=self.device)
+        self.workspace = torch.zeros(int(sz.workspace_bytes) + 256, dtype=torch.uint8, device=self.device)
+        ws = _ptr(self.workspace)
+        self._ws = (ws + 255) & ~255
+        b = _lib.Buffers()
+        for i in range(2):
+            for k in range(5):
+                b.state[i][k] = _ptr(self.state[i, k])
+        b.workspace = self._ws
+        b.workspace_bytes = int(sz.workspace_bytes)
+        mode, n = 0, 0
+        if particles is not None:
+            mode = 1
+            n = int(particles[0].numel())
+            for k in range(5):
+                self.state[0, k, :n].copy_(torch.as_tensor(particles[k], dtype=torch.float64))
+        self._h = ctypes.c_void_p()
+        check(lib().dsmc_init(ctypes.byref(self._c), ctypes.byref(b), mode, n, _stream(stream), ctypes.byref(self._h)),
+              "dsmc_init")
+
+    # ---- lifecycle -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            torch.cuda.synchronize(self.device)
+            lib().dsmc_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- the hot path -------------------------------------------------------------
+    def step(self, nsteps: int = 1, sample_every: int = 0, stream=None):
+        check(lib().dsmc_step(self._h, int(nsteps), int(sample_every), _stream(stream)), "dsmc_step")
+
+    def sample_moments(self, reset: bool = False, stream=None) -> torch.Tensor:
+        out = torch.empty((NMOM, self.ncells), dtype=torch.float64, device=self.device)
+        check(lib().dsmc_sample_moments(self._h, _ptr(out), int(reset), _stream(stream)), "dsmc_sample_moments")
+        return out
+
+    def reset_moments(self, stream=None):
+        check(lib().dsmc_sample_moments(self._h, None, 1, _stream(stream)), "dsmc_sample_moments")
+
+    def map_to_lbm(self, lattice_q: int, order: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((lattice_q, self.ncells), dtype=torch.float64, device=self.device)
+        check(lib().map_dsmc_to_lbm(self._h, int(lattice_q), int(order), _ptr(out), _stream(stream)),
+              "map_dsmc_to_lbm")
+        return out
+
+    def map_from_lbm(self, f: torch.Tensor, cell_ids: torch.Tensor, lattice_q: int, order: int, stream=None):
+        assert f.dtype == torch.float64 and f.is_contiguous() and f.shape == (lattice_q, self.ncells)
+        assert cell_ids.dtype == torch.int32 and cell_ids.is_contiguous()
+        check(lib().map_lbm_to_dsmc(self._h, int(lattice_q), int(order), _ptr(f), _ptr(cell_ids),
+                                    int(cell_ids.numel()), _stream(stream)), "map_lbm_to_dsmc")
+
+    # ---- inspection ---------------------------------------------------------------
+    def views(self) -> _lib.Views:
+        v = _lib.Views()
+        check(lib().dsmc_get_views(self._h, ctypes.byref(v)), "dsmc_get_views")
+        return v
+
+    def _ws_view(self, addr: int, n: int, dtype) -> torch.Tensor:
+        itemsize = torch.tensor([], dtype=dtype).element_size()
+        off = addr - _ptr(self.workspace)
+        return self.workspace[off:off + n * itemsize].view(dtype)
+
+    def cell_start(self) -> torch.Tensor:
+        return self._ws_view(self.views().cell_start, self.ncells + 1, torch.int32)
+
+    def cell_state(self):
+        v = self.views()
+        return (self._ws_view(v.nbar, self.ncells, torch.float64), self._ws_view(v.sigcmax, self.ncells, torch.float64),
+                self._ws_view(v.rem, self.ncells, torch.float64))
+
+    def status(self, clear: bool = False, stream=None) -> dict:
+        s = _lib.Status()
+        check(lib().dsmc_read_status(self._h, ctypes.byref(s), int(clear), _stream(stream)), "dsmc_read_status")
+        return {"bits": int(s.bits), "n": int(s.n_particles), "ncoll": int(s.ncoll), "ncand": int(s.ncand),
+                "nwall": int(s.nwall), "nfar": int(s.nfar)}
+
+    def particles(self):
+        """(x, y, vx, vy, vz) device views of the current, cell-sorted state."""
+        n = self.status()["n"]
+        cur = self.views().current
+        return tuple(self.state[cur, k, :n] for k in range(5))
+
+    def profile(self, enable: bool = True):
+        check(lib().dsmc_profile_enable(self._h, int(enable)), "dsmc_profile_enable")
+
+    def profile_read(self, kernel: int):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        check(lib().dsmc_profile_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n)), "dsmc_profile_read")
+        return ms.value, n.value
+
+
+def project_moments(avg: torch.Tensor, ppc: int, lattice_q: int, order: int, kT_over_m: float = 1.0,
+                    stream=None) -> torch.Tensor:
+    """DSMC2LB projection of given per-cell averages avg[11][ncells] (device FP64)."""
+    assert avg.dtype == torch.float64 and avg.is_contiguous() and avg.shape[0] == NMOM
+    ncells = avg.shape[1]
+    out = torch.empty((lattice_q, ncells), dtype=torch.float64, device=avg.device)
+    check(lib().dsmc_project_moments(_ptr(avg), ncells, int(ppc), float(kT_over_m), int(lattice_q), int(order),
+                                     _ptr(out), _stream(stream)), "dsmc_project_moments")
+    return out
+
+
+def lbm_step(f: torch.Tensor, nx: int, ny: int, lattice_q: int, tau: float, body_force_x: float = 0.0,
+             y_mode: int = 0, nsteps: int = 1, f_tmp: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """nsteps BGK steps on f[Q][nx*ny] in place (returns f)."""
+    assert f.dtype == torch.float64 and f.is_contiguous() and f.shape == (lattice_q, nx * ny)
+    if f_tmp is None:
+        f_tmp = torch.empty_like(f)
+    cfg = _lib.LbmConfig(int(nx), int(ny), int(lattice_q), int(y_mode), float(tau), float(body_force_x))
+    check(lib().lbm_step(ctypes.byref(cfg), _ptr(f), _ptr(f_tmp), int(nsteps), _stream(stream)), "lbm_step")
+    return f

@@ -1,0 +1,71 @@
+"""CPU-side checks of the C ABI: the library builds, loads and exports every
+symbol include/dsmc.h declares; host-only calls validate their arguments."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1512_08042_amd import _lib, config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dsmc.h")).read()
+    return set(re.findall(r"^(?:int|void|const char \*)\s*\*?\s*(\w+)\(", src, re.M))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    declared = _declared()
+    assert declared == set(_lib.EXPORTS)
+    for name in declared:
+        assert getattr(L, name) is not None
+
+
+def test_query_sizes_validates_config():
+    L = _lib.lib()
+    c = _lib.Config(4, 8, 10, 0, 1000, 0.1, 0.1, 0.0, 1.0, 6.0, 1, 0, 0)
+    s = _lib.Sizes()
+    assert L.dsmc_query_sizes(ctypes.byref(c), ctypes.byref(s)) == 0
+    assert s.ncells == 32 and s.state_array_bytes == 8000 and s.workspace_bytes > 0
+    for field, bad in (("nx", 0), ("kn", 0.0), ("dt", -1.0), ("capacity", 0), ("nbar_mode", 2),
+                       ("kT_over_m", float("nan"))):
+        d = _lib.Config.from_buffer_copy(c)
+        setattr(d, field, bad)
+        assert L.dsmc_query_sizes(ctypes.byref(d), ctypes.byref(s)) == _lib.EINVAL, field
+
+
+def test_null_arguments_rejected_without_gpu():
+    L = _lib.lib()
+    assert L.dsmc_step(None, 1, 0, None) == _lib.EINVAL
+    assert L.dsmc_sample_moments(None, None, 0, None) == _lib.EINVAL
+    assert L.map_dsmc_to_lbm(None, 9, 2, None, None) == _lib.EINVAL
+    assert L.map_lbm_to_dsmc(None, 9, 2, None, None, 0, None) == _lib.EINVAL
+    cfg = _lib.LbmConfig(4, 4, 10, 0, 0.8, 0.0)  # lattice 10 does not exist
+    assert L.lbm_step(ctypes.byref(cfg), None, None, 1, None) == _lib.EINVAL
+    assert L.dsmc_project_moments(None, 4, 10, 1.0, 9, 2, None, None) == _lib.EINVAL
+    assert L.dsmc_strerror(_lib.ECAPACITY) == b"capacity exceeded"
+
+
+@pytest.mark.parametrize("q", [9, 37])
+def test_library_lattice_matches_oracle_lattice(q):
+    # two independent derivations of the Gauss-Hermite lattice agree
+    e = np.zeros((q, 2), dtype=np.int32)
+    w = np.zeros(q)
+    r = ctypes.c_double()
+    assert _lib.lib().dsmc_lattice(q, e.ctypes.data, w.ctypes.data, ctypes.byref(r)) == 0
+    lo = O.lattice(q)
+    assert np.array_equal(e, lo["e"])
+    assert r.value == lo["r"]
+    assert np.allclose(w, lo["w"], rtol=4e-16, atol=0)
+
+
+def test_run_parameters_agree_with_oracle_reading():
+    for kn, ny in ((0.1, 64), (0.05, 256), (0.02, 1024), (0.01, 32)):
+        assert config.time_step(kn, ny) == O.default_dt(kn, ny)
+        assert config.body_force(kn, ny, 0.1) == O.body_force_for_mach(kn, ny, 0.1)
+    assert config.bgk_tau(0.1, 64, 3 ** 0.5) == O.lbm_tau(0.1, 64, 3 ** 0.5)
