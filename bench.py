@@ -36,15 +36,13 @@ STEPS_PER_CYCLE, STRIP = 10, 16
 
 # algorithmic bytes per unit (FP64): a particle is 5 doubles = 40 B
 BYTES = {
-    # read the cell-sorted state, write it sorted by the new cells; per cell
-    # the 9 group bases and the cell_start pair
-    "pass_scatter": (80.0, 9 * 4 + 8),
-    # read the state once; per cell write the 9 group counts, read cell_start,
-    # and read + write the 11 moment sums (sampling every step)
-    "pass_count": (40.0, 9 * 4 + 8 + 2 * 11 * 8),
-    # per cell: cell_start pair, nbar/sigcmax/rem read + write; the candidate
-    # pairs touch ~2.4 pairs x 2 particles x 24 B at 100 per cell
-    "collide": (0.0, 8 + 6 * 8 + 2.4 * 2 * 24 * 2),
+    # one DSMC step: read the cell-sorted state and write it sorted by the
+    # new cells (80 B per particle); per cell the cell_start pair (8 B), the
+    # NTC state nbar/sigcmax/rem read + written (48 B) and the 11 moment sums
+    # read + written (176 B, sampling every step)
+    "step": (80.0, 8 + 48 + 176),
+    # classification of a state set from outside: read x, y, vx, vy
+    "classify": (32.0, 8 + 9 * 4),
 }
 
 
@@ -54,11 +52,14 @@ def _parse():
     ap.add_argument("--steps", type=int, default=20, help="timed coupling cycles")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cycles", type=int, default=4, help="coupling cycles the CPU oracle is timed on")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run three plain 1 GiB device copies (reference for HBM byte counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(lat, strip):
-    """One cycle of the same workload with the FP64 oracle on the host."""
+def cpu_baseline(strip, cycles):
+    """`cycles` coupling cycles of the same workload with the FP64 oracle on the host."""
     import numpy as np
 
     from oracle import oracle as O
@@ -69,17 +70,21 @@ def cpu_baseline(lat, strip):
     sim.init_maxwell()
     olat = O.lattice(37)
     tau = O.lbm_tau(KN, NY, olat["r"])
+    cells = np.asarray(strip, dtype=np.int32)
     t0 = time.perf_counter()
-    sim.step(STEPS_PER_CYCLE, sample_every=1)
-    f = O.dsmc2lb(sim.averages(), PPC, olat, 3)
-    sim.reset_moments()
-    f = O.lbm_step(f, olat, NX, NY, tau, g / olat["r"], 1, 1)
-    sim.lb2dsmc(olat, 3, f, np.asarray(strip, dtype=np.int32))
+    for _ in range(cycles):
+        sim.step(STEPS_PER_CYCLE, sample_every=1)
+        f = O.dsmc2lb(sim.averages(), PPC, olat, 3)
+        sim.reset_moments()
+        f = O.lbm_step(f, olat, NX, NY, tau, g / olat["r"], 1, 1)
+        sim.lb2dsmc(olat, 3, f, cells)
     t1 = time.perf_counter()
     n = NX * NY * PPC
-    return {"value": n * STEPS_PER_CYCLE / (t1 - t0), "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "one coupling cycle (10 DSMC steps with sampling, D2Q37 projection of all cells, one BGK "
-                      "step, strip reseed) of the same 512x256x100 channel, single-threaded C, %.1f s" % (t1 - t0)}
+    return {"value": n * STEPS_PER_CYCLE * cycles / (t1 - t0), "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d coupling cycles (each 10 DSMC steps with sampling, D2Q37 projection of all cells, one BGK "
+                      "step, strip reseed) of the same 512x256x100 channel after its Maxwellian start, "
+                      "single-threaded C, %.1f s" % (cycles, t1 - t0)}
 
 
 def main():
@@ -96,6 +101,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # plain device-to-device copies of known size: 1 GiB read + 1 GiB written each
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = ChannelConfig(nx=NX, ny=NY, ppc=PPC, kn=KN, mach=MACH, seed=SEED).resolved()
     ch = D.Channel(cfg)
     e, w, r = D.lattice(37)
@@ -180,7 +193,7 @@ def main():
         "status_bits": st["bits"],
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(None, strip)
+        out["cpu_baseline"] = cpu_baseline(strip, args.cpu_cycles)
     print(json.dumps(out), flush=True)
 
 

@@ -55,6 +55,7 @@ extern "C" {
 #define DSMC_ST_NONFINITE 0x10u   /* non-finite populations in a reseeded cell: it received no particles */
 #define DSMC_ST_NNEW_LIMIT 0x20u  /* more than 2^24-1 new particles requested for one cell: clamped */
 #define DSMC_ST_BAD_CELL 0x40u    /* reseed cell list had an out-of-range or repeated id: reseed skipped */
+#define DSMC_ST_INTERNAL 0x80u    /* inconsistent sort tables inside a step (a library fault; never expected) */
 
 #define DSMC_NMOM 11 /* sampled sums per cell, see dsmc_sample_moments */
 
@@ -110,7 +111,7 @@ typedef struct dsmc_views {
     double *sigcmax;          /* device, ncells: (sigma_T c_r)_max / sigma_T per cell */
     double *rem;              /* device, ncells: carried fractional candidate count per cell */
     const double *mom_sums;   /* device, [11][ncells]: sums over samples, see dsmc_sample_moments */
-    int64_t nsamples;         /* samples in mom_sums (host-side count, includes a pending sample) */
+    int64_t nsamples;         /* samples in mom_sums */
     int64_t step;             /* DSMC steps taken since dsmc_init */
     int64_t reseed_events;    /* map_lbm_to_dsmc calls so far */
 } dsmc_views;
@@ -216,16 +217,15 @@ int dsmc_get_views(dsmc_ctx *ctx, dsmc_views *out);
  * starts (enable = 1) or stops recording; dsmc_profile_read synchronises and
  * returns, for kernel id k (DSMC_K_*), the summed duration in ms and the
  * number of timed launches, then clears the records of that kernel. */
-#define DSMC_K_COLLIDE 0
-#define DSMC_K_PASS_COUNT 1
-#define DSMC_K_CELL_COUNT 2
-#define DSMC_K_SCAN 3
-#define DSMC_K_CELL_FINAL 4
-#define DSMC_K_PASS_SCATTER 5
-#define DSMC_K_SAMPLE 6
-#define DSMC_K_PROJECT 7
-#define DSMC_K_RESEED 8
-#define DSMC_K_COUNT 9
+#define DSMC_K_CLASSIFY 0   /* moves of a state set from outside (first step after init or a reseed) */
+#define DSMC_K_CELL_COUNT 1 /* particles arriving per cell */
+#define DSMC_K_SCAN 2       /* scan of the block sums */
+#define DSMC_K_CELL_FINAL 3 /* new cell_start and group destinations */
+#define DSMC_K_STEP 4       /* gather + move + collide + sample + write + next classification */
+#define DSMC_K_PROJECT 5    /* DSMC2LB projection */
+#define DSMC_K_RESEED 6     /* LB2DSMC reseed (all of its kernels) */
+#define DSMC_K_INVERT 7     /* source slot of every new slot */
+#define DSMC_K_COUNT 8
 int dsmc_profile_enable(dsmc_ctx *ctx, int32_t enable);
 int dsmc_profile_read(dsmc_ctx *ctx, int32_t kernel, double *ms_total, int64_t *launches);
 

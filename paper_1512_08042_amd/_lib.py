@@ -12,11 +12,10 @@ c_i32, c_i64, c_u32, c_u64, c_d, c_p, c_sz = (ctypes.c_int32, ctypes.c_int64, ct
 
 OK, EINVAL, ECAPACITY, EHIP, ESTATE = 0, -1, -2, -3, -4
 ST_WALL_LIMIT, ST_FAR_OVERFLOW, ST_CAPACITY, ST_AR_LIMIT = 0x1, 0x2, 0x4, 0x8
-ST_NONFINITE, ST_NNEW_LIMIT, ST_BAD_CELL = 0x10, 0x20, 0x40
+ST_NONFINITE, ST_NNEW_LIMIT, ST_BAD_CELL, ST_INTERNAL = 0x10, 0x20, 0x40, 0x80
 NMOM = 11
-K_COLLIDE, K_PASS_COUNT, K_CELL_COUNT, K_SCAN, K_CELL_FINAL, K_PASS_SCATTER, K_SAMPLE, K_PROJECT, K_RESEED = range(9)
-KERNEL_NAMES = ("collide", "pass_count", "cell_count", "scan", "cell_final", "pass_scatter", "sample", "project",
-                "reseed")
+K_CLASSIFY, K_CELL_COUNT, K_SCAN, K_CELL_FINAL, K_STEP, K_PROJECT, K_RESEED, K_INVERT = range(8)
+KERNEL_NAMES = ("classify", "cell_count", "scan", "cell_final", "step", "project", "reseed", "invert")
 
 # every symbol include/dsmc.h declares
 EXPORTS = ("dsmc_query_sizes", "dsmc_init", "dsmc_step", "dsmc_sample_moments", "map_dsmc_to_lbm",

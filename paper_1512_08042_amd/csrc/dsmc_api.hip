@@ -195,8 +195,8 @@ int far_cap_of(const dsmc_config &c)
 }
 
 struct Layout {
-    size_t cs0, cs1, cnt, base, countnew, farcnt, blocksum, far, nbar, sigcmax, rem, mom, mark, prm, nnew, perm, ctr,
-        total;
+    size_t cs0, cs1, cnt, base, countnew, farcnt, blocksum, far0, far1, code0, code1, nbar, sigcmax, rem, mom, mark, prm,
+        nnew, perm, ctr, total;
 };
 
 Layout make_layout(const dsmc_config &c)
@@ -218,7 +218,10 @@ Layout make_layout(const dsmc_config &c)
     L.countnew = take(nc * 4);
     L.farcnt = take(nc * 4);
     L.blocksum = take(nblk * 4);
-    L.far = take((size_t)far_cap_of(c) * 16);
+    L.far0 = take((size_t)far_cap_of(c) * 16);
+    L.far1 = take((size_t)far_cap_of(c) * 16);
+    L.code0 = take(cap);
+    L.code1 = 0;
     L.nbar = take(nc * 8);
     L.sigcmax = take(nc * 8);
     L.rem = take(nc * 8);
@@ -226,7 +229,7 @@ Layout make_layout(const dsmc_config &c)
     L.mark = take(nc * 4);
     L.prm = take(nc * 12 * 8);
     L.nnew = take(nc * 4);
-    L.perm = take(cap * 8);  // permutation and per-particle cell ids of an adopted set
+    L.perm = take(cap * 8);  // adoption: permutation + cell ids; steps: source slots of oversized tiles
     L.ctr = take(sizeof(Counters));
     L.total = o;
     return L;
@@ -243,15 +246,22 @@ struct dsmc_ctx {
     dsmc_config cfg;
     double *st[2][5];
     int32_t *cs[2];
-    int32_t *cnt, *base, *countnew, *farcnt, *blocksum, *far, *mark, *nnew, *perm;
+    int32_t *cnt, *base, *countnew, *farcnt, *blocksum, *far[2], *mark, *nnew, *perm;
+    uint8_t *code;  // direction code per particle of the current state
     double *nbar, *sigcmax, *rem, *mom, *prm;
     Counters *ctr;
     int ncells, nblk, far_cap;
     double K, s_th;
     Geometry G;
     int cur;
+    int tc;  // cells per pass-1 tile
     int64_t step, nsamples, reseed_events;
-    bool pending_sample;
+    // Inside a dsmc_step call the state between steps is kept already moved
+    // for the coming step (with its codes, counts and long-jump list); at
+    // the end of every call it is settled (moved particles sorted into
+    // their cells, collided and sampled).  `classified` is true only inside
+    // a call.
+    bool classified;
     hipStream_t last;
     bool prof;
     std::vector<ProfRec> recs;
@@ -296,7 +306,7 @@ int launch(dsmc_ctx *x, int kid, hipStream_t s, F &&f)
 inline unsigned grid_cells_wave(int ncells) { return (unsigned)((ncells + 3) / 4); }
 inline unsigned grid_threads(size_t n) { return (unsigned)((n + 255) / 256); }
 
-MoveParams move_params(const dsmc_ctx *x)
+MoveParams move_params(const dsmc_ctx *x, int64_t step)
 {
     MoveParams M;
     M.dt = x->cfg.dt;
@@ -304,22 +314,20 @@ MoveParams move_params(const dsmc_ctx *x)
     M.s_th = x->s_th;
     M.k0 = (uint32_t)x->cfg.seed;
     M.k1 = (uint32_t)(x->cfg.seed >> 32);
-    M.step = (uint32_t)x->step;
+    M.step = (uint32_t)step;
     return M;
 }
 
-// take the pending sample of the current state (post-collision state of the
-// last step) if the last dsmc_step left one
-int flush_sample(dsmc_ctx *x, hipStream_t s)
+NtcParams ntc_params(const dsmc_ctx *x, int64_t step)
 {
-    if (!x->pending_sample) return DSMC_OK;
-    SampleArgs a;
-    for (int k = 0; k < 3; ++k) a.v[k] = x->st[x->cur][2 + k];
-    a.cs = x->cs[x->cur];
-    a.mom = x->mom;
-    a.ncells = x->ncells;
-    x->pending_sample = false;
-    return launch(x, DSMC_K_SAMPLE, s, [&] { k_sample<<<grid_cells_wave(x->ncells), 256, 0, s>>>(a); });
+    NtcParams N;
+    N.K = x->K;
+    N.dt = x->cfg.dt;
+    N.k0 = (uint32_t)x->cfg.seed;
+    N.k1 = (uint32_t)(x->cfg.seed >> 32);
+    N.step = (uint32_t)step;
+    N.nbar_mode = x->cfg.nbar_mode;
+    return N;
 }
 
 int fill_f64(double *p, size_t n, double v, hipStream_t s)
@@ -340,7 +348,7 @@ int fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t s)
 int scan_counts(dsmc_ctx *x, const int32_t *counts, int32_t *cs, hipStream_t s)
 {
     k_block_sums<<<x->nblk, 256, 0, s>>>(counts, x->ncells, x->blocksum);
-    k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, cs, x->ncells);
+    k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, cs, x->ncells, x->ctr, -1);
     k_block_scan<<<x->nblk, 256, 0, s>>>(counts, x->ncells, x->blocksum, cs);
     return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
 }
@@ -427,7 +435,9 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
     x->countnew = (int32_t *)(w + L.countnew);
     x->farcnt = (int32_t *)(w + L.farcnt);
     x->blocksum = (int32_t *)(w + L.blocksum);
-    x->far = (int32_t *)(w + L.far);
+    x->far[0] = (int32_t *)(w + L.far0);
+    x->far[1] = (int32_t *)(w + L.far1);
+    x->code = (uint8_t *)(w + L.code0);
     x->nbar = (double *)(w + L.nbar);
     x->sigcmax = (double *)(w + L.sigcmax);
     x->rem = (double *)(w + L.rem);
@@ -452,7 +462,9 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
     x->step = 0;
     x->nsamples = 0;
     x->reseed_events = 0;
-    x->pending_sample = false;
+    x->classified = false;
+    // tile of cells per pass-1 workgroup: ~800 particles, within the LDS stage
+    x->tc = (16 * cfg->ppc <= 800) ? 16 : ((8 * cfg->ppc <= 800) ? 8 : 4);
     x->prof = false;
     hipStream_t s = S(stream);
     x->last = s;
@@ -529,33 +541,36 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
     hipStream_t s = S(stream);
     x->last = s;
     const int nc = x->ncells;
+    if (nsteps > 0 && !x->classified) {
+        // moves of the coming step for a state set or changed from outside
+        const int fs = (int)(x->step & 1);
+        TRY(fill_i32(x->farcnt, (size_t)nc, 0, s));
+        k_far_reset<<<1, 64, 0, s>>>(x->ctr, fs);
+        ClassifyArgs ca;
+        for (int k = 0; k < 5; ++k) ca.st[k] = x->st[x->cur][k];
+        ca.cs = x->cs[x->cur];
+        ca.code = x->code;
+        ca.cnt = x->cnt;
+        ca.farcnt = x->farcnt;
+        ca.far = x->far[fs];
+        ca.ctr = x->ctr;
+        ca.G = x->G;
+        ca.M = move_params(x, x->step);
+        ca.ncells = nc;
+        ca.far_cap = x->far_cap;
+        ca.far_slot = fs;
+        TRY(launch(x, DSMC_K_CLASSIFY, s, [&] { k_classify<<<grid_cells_wave(nc), 256, 0, s>>>(ca); }));
+        x->classified = true;
+    }
     for (int32_t it = 0; it < nsteps; ++it) {
         const int cur = x->cur, nxt = 1 - cur;
-        PassArgs p;
-        for (int k = 0; k < 5; ++k) {
-            p.in[k] = x->st[cur][k];
-            p.out[k] = x->st[nxt][k];
-        }
-        p.cs = x->cs[cur];
-        p.cnt = x->cnt;
-        p.base = x->base;
-        p.farcnt = x->farcnt;
-        p.far = x->far;
-        p.ctr = x->ctr;
-        p.mom = x->mom;
-        p.G = x->G;
-        p.M = move_params(x);
-        p.ncells = nc;
-        p.far_cap = x->far_cap;
-        p.sample = x->pending_sample ? 1 : 0;
-        x->pending_sample = false;
-        TRY(launch(x, DSMC_K_PASS_COUNT, s, [&] { k_pass<false><<<grid_cells_wave(nc), 256, 0, s>>>(p); }));
-
+        const int fs = (int)(x->step & 1);
         CellArgs c;
+        c.from = x->perm;
         c.cnt = x->cnt;
         c.base = x->base;
         c.farcnt = x->farcnt;
-        c.far = x->far;
+        c.far = x->far[fs];
         c.countnew = x->countnew;
         c.blocksum = x->blocksum;
         c.cs_new = x->cs[nxt];
@@ -564,36 +579,61 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
         c.ny = x->cfg.ny;
         c.ncells = nc;
         c.far_cap = x->far_cap;
+        c.far_slot = fs;
         TRY(launch(x, DSMC_K_CELL_COUNT, s, [&] { k_cell_count<<<x->nblk, 256, 0, s>>>(c); }));
-        TRY(launch(x, DSMC_K_SCAN, s,
-                   [&] { k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, x->cs[nxt], nc); }));
+        TRY(launch(x, DSMC_K_SCAN, s, [&] {
+            k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, x->cs[nxt], nc, x->ctr, fs ^ 1);
+        }));
         TRY(launch(x, DSMC_K_CELL_FINAL, s, [&] { k_cell_final<<<x->nblk, 256, 0, s>>>(c); }));
+        InvertArgs iv;
+        iv.cs = x->cs[cur];
+        iv.code = x->code;
+        iv.base = x->base;
+        iv.from = x->perm;
+        iv.ctr = x->ctr;
+        iv.ncells = nc;
+        TRY(launch(x, DSMC_K_INVERT, s, [&] { k_invert<<<grid_cells_wave(nc), 256, 0, s>>>(iv); }));
 
-        p.sample = 0;
-        TRY(launch(x, DSMC_K_PASS_SCATTER, s, [&] { k_pass<true><<<grid_cells_wave(nc), 256, 0, s>>>(p); }));
-        x->cur = nxt;
-
-        CollideArgs ca;
-        for (int k = 0; k < 3; ++k) ca.v[k] = x->st[nxt][2 + k];
-        ca.cs = x->cs[nxt];
-        ca.nbar = x->nbar;
-        ca.sigcmax = x->sigcmax;
-        ca.rem = x->rem;
-        ca.ctr = x->ctr;
-        ca.ncells = nc;
-        ca.nbar_mode = x->cfg.nbar_mode;
-        ca.K = x->K;
-        ca.dt = x->cfg.dt;
-        ca.k0 = (uint32_t)x->cfg.seed;
-        ca.k1 = (uint32_t)(x->cfg.seed >> 32);
-        ca.step = (uint32_t)x->step;
-        TRY(launch(x, DSMC_K_COLLIDE, s, [&] { k_collide<<<grid_threads((size_t)nc), 256, 0, s>>>(ca); }));
-        if (sample_every > 0 && ((x->step + 1) % sample_every) == 0) {
-            x->pending_sample = true;
-            x->nsamples += 1;
+        const bool sample = sample_every > 0 && ((x->step + 1) % sample_every) == 0;
+        StepArgs a;
+        for (int k = 0; k < 5; ++k) {
+            a.in[k] = x->st[cur][k];
+            a.out[k] = x->st[nxt][k];
         }
+        a.cs_old = x->cs[cur];
+        a.cs_new = x->cs[nxt];
+        a.from = x->perm;
+        a.code_out = x->code;
+        a.far_out = x->far[fs ^ 1];
+        a.cnt = x->cnt;
+        a.farcnt = x->farcnt;
+        a.ctr = x->ctr;
+        a.mom = x->mom;
+        a.nbar = x->nbar;
+        a.sigcmax = x->sigcmax;
+        a.rem = x->rem;
+        a.G = x->G;
+        a.M1 = move_params(x, x->step + 1);
+        a.N = ntc_params(x, x->step);
+        a.ncells = nc;
+        a.far_cap = x->far_cap;
+        a.far_slot = fs;
+        a.sample = sample ? 1 : 0;
+        a.classify = (it + 1 < nsteps) ? 1 : 0;  // the call's last step leaves the state settled
+        const unsigned ntiles = (unsigned)((nc + x->tc - 1) / x->tc);
+        TRY(launch(x, DSMC_K_STEP, s, [&] {
+            if (x->tc == 16)
+                k_step<16><<<ntiles, 256, 0, s>>>(a);
+            else if (x->tc == 8)
+                k_step<8><<<ntiles, 256, 0, s>>>(a);
+            else
+                k_step<4><<<ntiles, 256, 0, s>>>(a);
+        }));
+        x->cur = nxt;
+        if (sample) x->nsamples += 1;
         x->step += 1;
     }
+    x->classified = false;
     return DSMC_OK;
 }
 
@@ -602,7 +642,6 @@ int dsmc_sample_moments(dsmc_ctx *x, double *out, int32_t reset, void *stream)
     if (!x) return DSMC_EINVAL;
     hipStream_t s = S(stream);
     x->last = s;
-    TRY(flush_sample(x, s));
     if (out) {
         if (x->nsamples <= 0) return DSMC_ESTATE;
         const size_t n = (size_t)NMOM * x->ncells;
@@ -639,7 +678,6 @@ int map_dsmc_to_lbm(dsmc_ctx *x, int32_t lattice, int32_t order, double *f_out, 
     if (!lattice_of(lattice) || order < 0 || order > 3 || !f_out) return DSMC_EINVAL;
     hipStream_t s = S(stream);
     x->last = s;
-    TRY(flush_sample(x, s));
     if (x->nsamples <= 0) return DSMC_ESTATE;
     return project(x, x->mom, (double)x->nsamples, x->ncells, x->cfg.ppc, x->cfg.kT_over_m, lattice, order, f_out, s);
 }
@@ -660,7 +698,6 @@ int map_lbm_to_dsmc(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f
     if (nsel > x->ncells) return DSMC_EINVAL;
     hipStream_t s = S(stream);
     x->last = s;
-    TRY(flush_sample(x, s));
     const uint32_t event = (uint32_t)x->reseed_events;
     x->reseed_events += 1;
     const int cur = x->cur, nxt = 1 - cur;
@@ -695,13 +732,15 @@ int map_lbm_to_dsmc(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f
     TRY(launch(x, DSMC_K_RESEED, s, [&] {
         if (nsel > 0) k_reseed_prep<<<gsel, 256, 0, s>>>(a);
         k_reseed_count<<<x->nblk, 256, 0, s>>>(a);
-        k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, x->cs[nxt], x->ncells);
+        k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, x->cs[nxt], x->ncells, x->ctr, -1);
         k_block_scan<<<x->nblk, 256, 0, s>>>(x->countnew, x->ncells, x->blocksum, x->cs[nxt]);
         k_reseed_check<<<1, 64, 0, s>>>(a);
-        k_reseed_scatter<<<grid_cells_wave(x->ncells), 256, 0, s>>>(a);
+        k_reseed_copy<<<(unsigned)((x->ncells + RC_TILE - 1) / RC_TILE), 256, 0, s>>>(a);
+        if (nsel > 0) k_reseed_gen<<<grid_cells_wave(nsel), 256, 0, s>>>(a);
         k_reseed_unmark<<<gsel, 256, 0, s>>>(a);
     }));
     x->cur = nxt;
+    x->classified = false;
     return DSMC_OK;
 }
 
@@ -762,7 +801,7 @@ int dsmc_read_status(dsmc_ctx *x, dsmc_status *out, int32_t clear, void *stream)
     out->ncoll = h.ncoll;
     out->ncand = h.ncand;
     out->nwall = h.nwall;
-    out->nfar = h.nfar_total + h.nfar;
+    out->nfar = h.nfar_total + h.nfar[0] + h.nfar[1];
     if (clear) {
         k_clear_status<<<1, 64, 0, s>>>(x->ctr);
         if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
@@ -773,7 +812,6 @@ int dsmc_read_status(dsmc_ctx *x, dsmc_status *out, int32_t clear, void *stream)
 int dsmc_get_views(dsmc_ctx *x, dsmc_views *out)
 {
     if (!x || !out) return DSMC_EINVAL;
-    TRY(flush_sample(x, x->last));
     out->current = x->cur;
     out->cell_start = x->cs[x->cur];
     out->nbar = x->nbar;

@@ -32,15 +32,15 @@ constexpr uint32_t ST_AR_LIMIT = 0x8u;
 constexpr uint32_t ST_NONFINITE = 0x10u;
 constexpr uint32_t ST_NNEW_LIMIT = 0x20u;
 constexpr uint32_t ST_BAD_CELL = 0x40u;
+constexpr uint32_t ST_INTERNAL = 0x80u;
 
 constexpr double TWO_PI = 6.283185307179586;
 
 // Counters shared by all kernels of a context (device memory).
 struct Counters {
     uint32_t status;
-    uint32_t nfar;        // long jumps recorded in the current step
     uint32_t reseed_err;  // per-reseed error flags (cleared at each reseed)
-    uint32_t pad;
+    uint32_t nfar[2];     // long jumps of the step, double-buffered by step parity
     unsigned long long ncoll, ncand, nwall, nfar_total;
     unsigned long long reseed_new, reseed_removed;  // particle totals of the reseed in progress
 };
@@ -86,13 +86,102 @@ __device__ __forceinline__ double u53(uint32_t a, uint32_t b)
     return (double)m * (1.0 / 9007199254740992.0);
 }
 
+// ---- elementary functions on the ranges this library needs -------------------
+// The general-purpose FP64 sin/cos/log handle every argument and cost
+// thousands of instructions; here the arguments are restricted, so short
+// exact reductions and Taylor series suffice (a few ulp).
+
+// cos(2 pi r) and sin(2 pi r) for r in [0, 1).  8r = k + f splits the turn
+// into octants exactly (scaling by 8 and subtracting the integer part are
+// exact); on each octant the angle is reduced to theta = g pi/4 with g in
+// [0, 1] (g = f on even octants, 1 - f on odd ones, both exact), where the
+// Taylor series of sin and cos to degree 19 / 20 are exact to rounding
+// (remainder below 1e-21).
+__device__ __forceinline__ void sincos_turn(double r, double &s, double &c)
+{
+    const double t = r * 8.0;
+    const int k = (int)t;
+    const double f = t - (double)k;
+    const double g = (k & 1) ? 1.0 - f : f;
+    const double th = g * 0.78539816339744830962;  // pi/4
+    const double q = th * th;
+    // sin(th) = th (1 - q/3! + q^2/5! - ... - q^9/19!)
+    double ps = -1.0 / 121645100408832000.0;  // -1/19!
+    ps = fma(ps, q, 1.0 / 355687428096000.0);
+    ps = fma(ps, q, -1.0 / 1307674368000.0);
+    ps = fma(ps, q, 1.0 / 6227020800.0);
+    ps = fma(ps, q, -1.0 / 39916800.0);
+    ps = fma(ps, q, 1.0 / 362880.0);
+    ps = fma(ps, q, -1.0 / 5040.0);
+    ps = fma(ps, q, 1.0 / 120.0);
+    ps = fma(ps, q, -1.0 / 6.0);
+    const double sn = fma(th * q, ps, th);
+    // cos(th) = 1 - q/2! + q^2/4! - ... + q^10/20!
+    double pc = 1.0 / 2432902008176640000.0;  // 1/20!
+    pc = fma(pc, q, -1.0 / 6402373705728000.0);
+    pc = fma(pc, q, 1.0 / 20922789888000.0);
+    pc = fma(pc, q, -1.0 / 87178291200.0);
+    pc = fma(pc, q, 1.0 / 479001600.0);
+    pc = fma(pc, q, -1.0 / 3628800.0);
+    pc = fma(pc, q, 1.0 / 40320.0);
+    pc = fma(pc, q, -1.0 / 720.0);
+    pc = fma(pc, q, 1.0 / 24.0);
+    pc = fma(pc, q, -0.5);
+    const double cs = fma(q, pc, 1.0);
+    // angle = (k + f) pi/4 -> quadrant identities
+    switch (k & 7) {
+        case 0: c = cs; s = sn; break;    // theta
+        case 1: c = sn; s = cs; break;    // pi/2 - theta
+        case 2: c = -sn; s = cs; break;   // pi/2 + theta
+        case 3: c = -cs; s = sn; break;   // pi - theta
+        case 4: c = -cs; s = -sn; break;  // pi + theta
+        case 5: c = -sn; s = -cs; break;  // 3pi/2 - theta
+        case 6: c = sn; s = -cs; break;   // 3pi/2 + theta
+        default: c = cs; s = -sn; break;  // 2pi - theta
+    }
+}
+
+// natural log of x in (0, 1] (a normal double): x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), log m = 2 atanh(s), s = (m-1)/(m+1), |s| < 0.1716,
+// atanh by its odd series to s^27 (remainder below 1e-22); e ln 2 with ln 2
+// split in a short high part and a correction.
+__device__ __forceinline__ double log_unit(double x)
+{
+    const long long bits = __double_as_longlong(x);
+    int e = (int)((bits >> 52) & 0x7ff) - 1023;
+    double m = __longlong_as_double((bits & 0x000fffffffffffffLL) | 0x3ff0000000000000LL);  // [1, 2)
+    if (m > 1.4142135623730951) {
+        m = m * 0.5;
+        e += 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double q = s * s;
+    double p = 1.0 / 27.0;
+    p = fma(p, q, 1.0 / 25.0);
+    p = fma(p, q, 1.0 / 23.0);
+    p = fma(p, q, 1.0 / 21.0);
+    p = fma(p, q, 1.0 / 19.0);
+    p = fma(p, q, 1.0 / 17.0);
+    p = fma(p, q, 1.0 / 15.0);
+    p = fma(p, q, 1.0 / 13.0);
+    p = fma(p, q, 1.0 / 11.0);
+    p = fma(p, q, 1.0 / 9.0);
+    p = fma(p, q, 1.0 / 7.0);
+    p = fma(p, q, 1.0 / 5.0);
+    p = fma(p, q, 1.0 / 3.0);
+    const double lm = 2.0 * fma(s * q, p, s);
+    const double ln2_hi = 6.93147180369123816490e-01, ln2_lo = 1.90821492927058770002e-10;
+    return fma((double)e, ln2_hi, fma((double)e, ln2_lo, lm));
+}
+
 // Box-Muller pair from two uniforms; 1 - r1 is in (0, 1]
 __device__ __forceinline__ void box_muller(double r1, double r2, double &z0, double &z1)
 {
-    const double rad = sqrt(-2.0 * log(1.0 - r1));
-    const double ang = TWO_PI * r2;
-    z0 = rad * cos(ang);
-    z1 = rad * sin(ang);
+    const double rad = sqrt(-2.0 * log_unit(1.0 - r1));
+    double s, c;
+    sincos_turn(r2, s, c);
+    z0 = rad * c;
+    z1 = rad * s;
 }
 
 // uniform coordinate inside cell i: a sum that rounds up to the far edge is
@@ -146,7 +235,7 @@ __device__ __forceinline__ int move_particle(const Geometry &G, const MoveParams
             y = wall;
             const U4 a = draw(M.k0, M.k1, (uint32_t)(2 * b), p, M.step, TAG_WALL, 0u);
             const U4 c = draw(M.k0, M.k1, (uint32_t)(2 * b + 1), p, M.step, TAG_WALL, 0u);
-            const double vn = M.s_th * sqrt(-2.0 * log(1.0 - u53(a.x, a.y)));
+            const double vn = M.s_th * sqrt(-2.0 * log_unit(1.0 - u53(a.x, a.y)));
             double z0, z1;
             box_muller(u53(a.z, a.w), u53(c.x, c.y), z0, z1);
             vx = M.s_th * z0;
@@ -235,6 +324,58 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Sum of 16 per-lane values over a team of T lanes (T = 16, 32 or 64, teams
+// aligned inside the wave), returned "scattered": afterwards lane lt of the
+// team holds the team total of value (lt / (T/16)) & 15.  Four exchange
+// steps halve the values each lane carries (17 shuffles for 16 values
+// instead of 16 * log2(T)); the remaining steps are plain butterflies.
+// Additions happen in a fixed order, so results are deterministic.
+template <int T>
+__device__ __forceinline__ double team_reduce_scatter16(double *v, int lt)
+{
+    double a[8], b[4], c[2], d;
+    {
+        constexpr int off = T / 2;
+        const bool hi = (lt & off) != 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const double keep = hi ? v[8 + i] : v[i];
+            const double send = hi ? v[i] : v[8 + i];
+            a[i] = keep + __shfl_xor(send, off, 64);
+        }
+    }
+    {
+        constexpr int off = T / 4;
+        const bool hi = (lt & off) != 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double keep = hi ? a[4 + i] : a[i];
+            const double send = hi ? a[i] : a[4 + i];
+            b[i] = keep + __shfl_xor(send, off, 64);
+        }
+    }
+    {
+        constexpr int off = T / 8;
+        const bool hi = (lt & off) != 0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const double keep = hi ? b[2 + i] : b[i];
+            const double send = hi ? b[i] : b[2 + i];
+            c[i] = keep + __shfl_xor(send, off, 64);
+        }
+    }
+    {
+        constexpr int off = T / 16;
+        const bool hi = (lt & off) != 0;
+        const double keep = hi ? c[1] : c[0];
+        const double send = hi ? c[0] : c[1];
+        d = keep + __shfl_xor(send, off, 64);
+    }
+#pragma unroll
+    for (int off = T / 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+    return d;
 }
 
 // ---- lattices ----------------------------------------------------------------

@@ -232,39 +232,56 @@ __global__ void k_reseed_check(ReseedArgs a)
     }
 }
 
-// one wave per cell: copy a kept cell's particles in order, or generate the
-// listed cell's new particles (Table 1 steps 4-6); when the reseed was
-// rejected every cell is copied unchanged
-__global__ __launch_bounds__(256) void k_reseed_scatter(ReseedArgs a)
+// Kept cells: one workgroup per tile of RC_TILE cells streams the tile's
+// old particles and copies those of unlisted cells to their new slots (the
+// identity when the reseed was rejected, in which case cell_start is
+// restored as well).
+constexpr int RC_TILE = 64;
+
+__global__ __launch_bounds__(256) void k_reseed_copy(ReseedArgs a)
+{
+    __shared__ int s_old[RC_TILE + 1], s_new[RC_TILE + 1], s_keep[RC_TILE];
+    const int tid = threadIdx.x;
+    const int c0 = blockIdx.x * RC_TILE;
+    const int nt = min(RC_TILE, a.ncells - c0);
+    const bool err = a.ctr->reseed_err != 0u;
+    if (tid <= RC_TILE) {
+        const int c = min(c0 + tid, a.ncells);
+        s_old[tid] = a.cs_old[c];
+        s_new[tid] = err ? a.cs_old[c] : a.cs_new[c];
+    }
+    if (tid < RC_TILE) s_keep[tid] = (tid < nt) && (err || a.mark[c0 + tid] == 0);
+    __syncthreads();
+    if (err) {
+        if (tid < nt) a.cs_new[c0 + tid] = s_old[tid];
+        if (c0 + nt == a.ncells && tid == 0) a.cs_new[a.ncells] = s_old[nt];
+    }
+    const int P0 = s_old[0], P1 = s_old[nt];
+    for (int p = P0 + tid; p < P1; p += 256) {
+        int lo = 0, hi = nt;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_old[mid] <= p) lo = mid;
+            else hi = mid;
+        }
+        if (!s_keep[lo]) continue;
+        const int q = s_new[lo] + (p - s_old[lo]);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) a.out[k][q] = a.in[k][p];
+    }
+}
+
+// Listed cells: one wave per listed cell generates its new particles
+// (Table 1 steps 4-6) into the cell's new slots.
+__global__ __launch_bounds__(256) void k_reseed_gen(ReseedArgs a)
 {
     const int lane = threadIdx.x & 63;
-    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (c >= a.ncells) return;
-    const bool err = a.ctr->reseed_err != 0u;
-    const int s0 = a.cs_old[c], e0 = a.cs_old[c + 1];
-    if (err) {
-        if (lane == 0) {
-            a.cs_new[c] = s0;
-            if (c == a.ncells - 1) a.cs_new[a.ncells] = e0;
-        }
-        for (int p = s0 + lane; p < e0; p += 64) {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) a.out[k][p] = a.in[k][p];
-        }
-        return;
-    }
-    const int d0 = a.cs_new[c];
-    const int mk = a.mark[c];
-    if (mk == 0) {
-        for (int p = s0 + lane; p < e0; p += 64) {
-            const int q = d0 + (p - s0);
-#pragma unroll
-            for (int k = 0; k < 5; ++k) a.out[k][q] = a.in[k][p];
-        }
-        return;
-    }
-    const int i = mk - 1;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= a.nsel) return;
+    if (a.ctr->reseed_err != 0u) return;
+    const int c = a.cells[i];
     const int nn = a.nnew[i];
+    const int d0 = a.cs_new[c];
     double prm[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) prm[k] = a.prm[(size_t)i * 12 + k];
