@@ -217,15 +217,14 @@ int dsmc_get_views(dsmc_ctx *ctx, dsmc_views *out);
  * starts (enable = 1) or stops recording; dsmc_profile_read synchronises and
  * returns, for kernel id k (DSMC_K_*), the summed duration in ms and the
  * number of timed launches, then clears the records of that kernel. */
-#define DSMC_K_CLASSIFY 0   /* moves of a state set from outside (first step after init or a reseed) */
+#define DSMC_K_CLASSIFY 0   /* moves of a settled state for the coming step (first step of a dsmc_step call) */
 #define DSMC_K_CELL_COUNT 1 /* particles arriving per cell */
 #define DSMC_K_SCAN 2       /* scan of the block sums */
-#define DSMC_K_CELL_FINAL 3 /* new cell_start and group destinations */
-#define DSMC_K_STEP 4       /* gather + move + collide + sample + write + next classification */
+#define DSMC_K_CELL_FINAL 3 /* new cell_start */
+#define DSMC_K_STEP 4       /* gather + collide + sample + next move + partitioned write */
 #define DSMC_K_PROJECT 5    /* DSMC2LB projection */
 #define DSMC_K_RESEED 6     /* LB2DSMC reseed (all of its kernels) */
-#define DSMC_K_INVERT 7     /* source slot of every new slot */
-#define DSMC_K_COUNT 8
+#define DSMC_K_COUNT 7
 int dsmc_profile_enable(dsmc_ctx *ctx, int32_t enable);
 int dsmc_profile_read(dsmc_ctx *ctx, int32_t kernel, double *ms_total, int64_t *launches);
 

@@ -15,7 +15,7 @@ ST_WALL_LIMIT, ST_FAR_OVERFLOW, ST_CAPACITY, ST_AR_LIMIT = 0x1, 0x2, 0x4, 0x8
 ST_NONFINITE, ST_NNEW_LIMIT, ST_BAD_CELL, ST_INTERNAL = 0x10, 0x20, 0x40, 0x80
 NMOM = 11
 K_CLASSIFY, K_CELL_COUNT, K_SCAN, K_CELL_FINAL, K_STEP, K_PROJECT, K_RESEED, K_INVERT = range(8)
-KERNEL_NAMES = ("classify", "cell_count", "scan", "cell_final", "step", "project", "reseed", "invert")
+KERNEL_NAMES = ("classify", "cell_count", "scan", "cell_final", "step", "project", "reseed")
 
 # every symbol include/dsmc.h declares
 EXPORTS = ("dsmc_query_sizes", "dsmc_init", "dsmc_step", "dsmc_sample_moments", "map_dsmc_to_lbm",

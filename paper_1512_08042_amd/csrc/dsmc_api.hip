@@ -195,8 +195,8 @@ int far_cap_of(const dsmc_config &c)
 }
 
 struct Layout {
-    size_t cs0, cs1, cnt, base, countnew, farcnt, blocksum, far0, far1, code0, code1, nbar, sigcmax, rem, mom, mark, prm,
-        nnew, perm, ctr, total;
+    size_t cs0, cs1, grp0, grp1, countnew, farcnt, blocksum, far0, far1, nbar, sigcmax, rem, mom, mark, prm, nnew, perm,
+        tstat, ctr, total;
 };
 
 Layout make_layout(const dsmc_config &c)
@@ -213,15 +213,13 @@ Layout make_layout(const dsmc_config &c)
     };
     L.cs0 = take((nc + 1) * 4);
     L.cs1 = take((nc + 1) * 4);
-    L.cnt = take(NDIR * nc * 4);
-    L.base = take(NDIR * nc * 4);
+    L.grp0 = take(NGRP * nc * 4);
+    L.grp1 = take(NGRP * nc * 4);
     L.countnew = take(nc * 4);
-    L.farcnt = take(nc * 4);
+    L.farcnt = take(2 * nc * 4);
     L.blocksum = take(nblk * 4);
     L.far0 = take((size_t)far_cap_of(c) * 16);
     L.far1 = take((size_t)far_cap_of(c) * 16);
-    L.code0 = take(cap);
-    L.code1 = 0;
     L.nbar = take(nc * 8);
     L.sigcmax = take(nc * 8);
     L.rem = take(nc * 8);
@@ -229,7 +227,8 @@ Layout make_layout(const dsmc_config &c)
     L.mark = take(nc * 4);
     L.prm = take(nc * 12 * 8);
     L.nnew = take(nc * 4);
-    L.perm = take(cap * 8);  // adoption: permutation + cell ids; steps: source slots of oversized tiles
+    L.perm = take(cap * 12);  // adoption: permutation + cell ids; steps: scratch of oversized tiles
+    L.tstat = take(3 * nc * 8);  // per step tile (at most one tile per cell)
     L.ctr = take(sizeof(Counters));
     L.total = o;
     return L;
@@ -246,19 +245,20 @@ struct dsmc_ctx {
     dsmc_config cfg;
     double *st[2][5];
     int32_t *cs[2];
-    int32_t *cnt, *base, *countnew, *farcnt, *blocksum, *far[2], *mark, *nnew, *perm;
-    uint8_t *code;  // direction code per particle of the current state
+    int32_t *grp[2], *countnew, *farcnt, *blocksum, *far[2], *mark, *nnew, *perm;
     double *nbar, *sigcmax, *rem, *mom, *prm;
     Counters *ctr;
-    int ncells, nblk, far_cap;
+    unsigned long long *tstat;
+    int ncells, nblk, far_cap, ntiles;
     double K, s_th;
     Geometry G;
     int cur;
-    int tc;  // cells per pass-1 tile
+    int tc, ch;  // cells per step tile, 64-slot chunks of its LDS stage
     int64_t step, nsamples, reseed_events;
     // Inside a dsmc_step call the state between steps is kept already moved
-    // for the coming step (with its codes, counts and long-jump list); at
-    // the end of every call it is settled (moved particles sorted into
+    // for the coming step and partitioned by direction inside every cell
+    // (with its group sizes and long-jump list, buffers of parity step & 1);
+    // at the end of every call it is settled (moved particles sorted into
     // their cells, collided and sampled).  `classified` is true only inside
     // a call.
     bool classified;
@@ -328,6 +328,54 @@ NtcParams ntc_params(const dsmc_ctx *x, int64_t step)
     N.step = (uint32_t)step;
     N.nbar_mode = x->cfg.nbar_mode;
     return N;
+}
+
+// the arguments every step-kernel launch shares; the caller fills in the
+// state, cell_start, group and long-jump buffers of its launch
+StepArgs step_args(const dsmc_ctx *x, int p)
+{
+    StepArgs a{};
+    a.grp_in = x->grp[p];
+    a.far_in = x->far[p];
+    a.farcnt_in = x->farcnt + (size_t)p * x->ncells;
+    a.far_in_slot = p;
+    a.scr = (double *)x->perm;
+    a.scr_i = (int32_t *)((char *)x->perm + (size_t)x->cfg.capacity * 8);
+    a.ctr = x->ctr;
+    a.tstat = x->tstat;
+    a.mom = x->mom;
+    a.nbar = x->nbar;
+    a.sigcmax = x->sigcmax;
+    a.rem = x->rem;
+    a.G = x->G;
+    a.N = ntc_params(x, x->step);
+    a.ncells = x->ncells;
+    a.far_cap = x->far_cap;
+    a.sample = 0;
+    return a;
+}
+
+// one launch of the tile kernels: kind 0 = k_classify, 1 = k_step
+void launch_tiles(const dsmc_ctx *x, int kind, bool move, unsigned ntiles, hipStream_t s, const StepArgs &a)
+{
+#define DSMC_LAUNCH(TC, CH)                                          \
+    do {                                                             \
+        if (kind == 0)                                               \
+            k_classify<TC, CH><<<ntiles, 64, 0, s>>>(a);             \
+        else if (move)                                               \
+            k_step<TC, CH, true><<<ntiles, 64, 0, s>>>(a);           \
+        else                                                         \
+            k_step<TC, CH, false><<<ntiles, 64, 0, s>>>(a);          \
+    } while (0)
+    if (x->tc == 4)
+        DSMC_LAUNCH(4, 4);
+    else if (x->tc == 2)
+        DSMC_LAUNCH(2, 4);
+    else if (x->ch == 4)
+        DSMC_LAUNCH(1, 4);
+    else
+        DSMC_LAUNCH(1, 8);
+#undef DSMC_LAUNCH
 }
 
 int fill_f64(double *p, size_t n, double v, hipStream_t s)
@@ -430,14 +478,13 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
         for (int k = 0; k < 5; ++k) x->st[b][k] = buf->state[b][k];
     x->cs[0] = (int32_t *)(w + L.cs0);
     x->cs[1] = (int32_t *)(w + L.cs1);
-    x->cnt = (int32_t *)(w + L.cnt);
-    x->base = (int32_t *)(w + L.base);
+    x->grp[0] = (int32_t *)(w + L.grp0);
+    x->grp[1] = (int32_t *)(w + L.grp1);
     x->countnew = (int32_t *)(w + L.countnew);
     x->farcnt = (int32_t *)(w + L.farcnt);
     x->blocksum = (int32_t *)(w + L.blocksum);
     x->far[0] = (int32_t *)(w + L.far0);
     x->far[1] = (int32_t *)(w + L.far1);
-    x->code = (uint8_t *)(w + L.code0);
     x->nbar = (double *)(w + L.nbar);
     x->sigcmax = (double *)(w + L.sigcmax);
     x->rem = (double *)(w + L.rem);
@@ -447,6 +494,7 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
     x->nnew = (int32_t *)(w + L.nnew);
     x->perm = (int32_t *)(w + L.perm);
     x->ctr = (Counters *)(w + L.ctr);
+    x->tstat = (unsigned long long *)(w + L.tstat);
     x->ncells = (int)ncells;
     x->nblk = (int)((ncells + 255) / 256);
     x->far_cap = far_cap_of(*cfg);
@@ -463,8 +511,11 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
     x->nsamples = 0;
     x->reseed_events = 0;
     x->classified = false;
-    // tile of cells per pass-1 workgroup: ~800 particles, within the LDS stage
-    x->tc = (16 * cfg->ppc <= 800) ? 16 : ((8 * cfg->ppc <= 800) ? 8 : 4);
+    // step tiles of about 200 particles (one wave each) inside an LDS stage
+    // of 256 slots; denser gases get single-cell tiles with 512 slots
+    x->tc = cfg->ppc <= 50 ? 4 : (cfg->ppc <= 100 ? 2 : 1);
+    x->ch = cfg->ppc <= 200 ? 4 : 8;
+    x->ntiles = (int)((ncells + x->tc - 1) / x->tc);
     x->prof = false;
     hipStream_t s = S(stream);
     x->last = s;
@@ -473,8 +524,9 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
     k_zero_counters<<<1, 64, 0, s>>>(x->ctr);
     if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
     if (rc == DSMC_OK) rc = fill_f64(x->mom, (size_t)NMOM * ncells, 0.0, s);
-    if (rc == DSMC_OK) rc = fill_i32(x->farcnt, (size_t)ncells, 0, s);
+    if (rc == DSMC_OK) rc = fill_i32(x->farcnt, 2 * (size_t)ncells, 0, s);
     if (rc == DSMC_OK) rc = fill_i32(x->mark, (size_t)ncells, 0, s);
+    if (rc == DSMC_OK) rc = fill_i32((int32_t *)x->tstat, 6 * (size_t)x->ntiles, 0, s);
     if (rc == DSMC_OK && mode == 0) {
         InitArgs a;
         for (int k = 0; k < 5; ++k) a.st[k] = x->st[0][k];
@@ -541,94 +593,67 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
     hipStream_t s = S(stream);
     x->last = s;
     const int nc = x->ncells;
+    const unsigned ntiles = (unsigned)x->ntiles;
     if (nsteps > 0 && !x->classified) {
         // moves of the coming step for a state set or changed from outside
-        const int fs = (int)(x->step & 1);
-        TRY(fill_i32(x->farcnt, (size_t)nc, 0, s));
-        k_far_reset<<<1, 64, 0, s>>>(x->ctr, fs);
-        ClassifyArgs ca;
-        for (int k = 0; k < 5; ++k) ca.st[k] = x->st[x->cur][k];
-        ca.cs = x->cs[x->cur];
-        ca.code = x->code;
-        ca.cnt = x->cnt;
-        ca.farcnt = x->farcnt;
-        ca.far = x->far[fs];
-        ca.ctr = x->ctr;
-        ca.G = x->G;
-        ca.M = move_params(x, x->step);
-        ca.ncells = nc;
-        ca.far_cap = x->far_cap;
-        ca.far_slot = fs;
-        TRY(launch(x, DSMC_K_CLASSIFY, s, [&] { k_classify<<<grid_cells_wave(nc), 256, 0, s>>>(ca); }));
+        const int p = (int)(x->step & 1);
+        TRY(fill_i32(x->farcnt, 2 * (size_t)nc, 0, s));
+        k_far_reset<<<1, 64, 0, s>>>(x->ctr, p);
+        StepArgs a = step_args(x, p);
+        for (int k = 0; k < 5; ++k) {
+            a.in[k] = x->st[x->cur][k];
+            a.out[k] = x->st[x->cur][k];
+        }
+        a.cs_old = x->cs[x->cur];
+        a.cs_new = x->cs[x->cur];
+        a.grp_out = x->grp[p];
+        a.far_out = x->far[p];
+        a.farcnt_out = x->farcnt + (size_t)p * nc;
+        a.far_out_slot = p;
+        a.M1 = move_params(x, x->step);
+        TRY(launch(x, DSMC_K_CLASSIFY, s, [&] { launch_tiles(x, 0, true, ntiles, s, a); }));
         x->classified = true;
     }
     for (int32_t it = 0; it < nsteps; ++it) {
         const int cur = x->cur, nxt = 1 - cur;
-        const int fs = (int)(x->step & 1);
+        const int p = (int)(x->step & 1);
         CellArgs c;
-        c.from = x->perm;
-        c.cnt = x->cnt;
-        c.base = x->base;
-        c.farcnt = x->farcnt;
-        c.far = x->far[fs];
+        c.grp = x->grp[p];
+        c.farcnt = x->farcnt + (size_t)p * nc;
         c.countnew = x->countnew;
         c.blocksum = x->blocksum;
-        c.cs_new = x->cs[nxt];
-        c.ctr = x->ctr;
         c.nx = x->cfg.nx;
         c.ny = x->cfg.ny;
         c.ncells = nc;
-        c.far_cap = x->far_cap;
-        c.far_slot = fs;
         TRY(launch(x, DSMC_K_CELL_COUNT, s, [&] { k_cell_count<<<x->nblk, 256, 0, s>>>(c); }));
         TRY(launch(x, DSMC_K_SCAN, s, [&] {
-            k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, x->cs[nxt], nc, x->ctr, fs ^ 1);
+            k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, x->cs[nxt], nc, x->ctr, p ^ 1);
         }));
-        TRY(launch(x, DSMC_K_CELL_FINAL, s, [&] { k_cell_final<<<x->nblk, 256, 0, s>>>(c); }));
-        InvertArgs iv;
-        iv.cs = x->cs[cur];
-        iv.code = x->code;
-        iv.base = x->base;
-        iv.from = x->perm;
-        iv.ctr = x->ctr;
-        iv.ncells = nc;
-        TRY(launch(x, DSMC_K_INVERT, s, [&] { k_invert<<<grid_cells_wave(nc), 256, 0, s>>>(iv); }));
+        TRY(launch(x, DSMC_K_CELL_FINAL, s, [&] {
+            k_block_scan<<<x->nblk, 256, 0, s>>>(x->countnew, nc, x->blocksum, x->cs[nxt]);
+        }));
 
         const bool sample = sample_every > 0 && ((x->step + 1) % sample_every) == 0;
-        StepArgs a;
+        const bool move = it + 1 < nsteps;  // the call's last step leaves the state settled
+        StepArgs a = step_args(x, p);
         for (int k = 0; k < 5; ++k) {
             a.in[k] = x->st[cur][k];
             a.out[k] = x->st[nxt][k];
         }
         a.cs_old = x->cs[cur];
         a.cs_new = x->cs[nxt];
-        a.from = x->perm;
-        a.code_out = x->code;
-        a.far_out = x->far[fs ^ 1];
-        a.cnt = x->cnt;
-        a.farcnt = x->farcnt;
-        a.ctr = x->ctr;
-        a.mom = x->mom;
-        a.nbar = x->nbar;
-        a.sigcmax = x->sigcmax;
-        a.rem = x->rem;
-        a.G = x->G;
+        a.grp_in = x->grp[p];
+        a.grp_out = x->grp[p ^ 1];
+        a.far_in = x->far[p];
+        a.farcnt_in = x->farcnt + (size_t)p * nc;
+        a.far_in_slot = p;
+        a.far_out = x->far[p ^ 1];
+        a.farcnt_out = x->farcnt + (size_t)(p ^ 1) * nc;
+        a.far_out_slot = p ^ 1;
         a.M1 = move_params(x, x->step + 1);
         a.N = ntc_params(x, x->step);
-        a.ncells = nc;
-        a.far_cap = x->far_cap;
-        a.far_slot = fs;
         a.sample = sample ? 1 : 0;
-        a.classify = (it + 1 < nsteps) ? 1 : 0;  // the call's last step leaves the state settled
-        const unsigned ntiles = (unsigned)((nc + x->tc - 1) / x->tc);
-        TRY(launch(x, DSMC_K_STEP, s, [&] {
-            if (x->tc == 16)
-                k_step<16><<<ntiles, 256, 0, s>>>(a);
-            else if (x->tc == 8)
-                k_step<8><<<ntiles, 256, 0, s>>>(a);
-            else
-                k_step<4><<<ntiles, 256, 0, s>>>(a);
-        }));
+        TRY(launch(x, DSMC_K_STEP, s, [&] { launch_tiles(x, 1, move, ntiles, s, a); }));
         x->cur = nxt;
         if (sample) x->nsamples += 1;
         x->step += 1;
@@ -791,6 +816,8 @@ int dsmc_read_status(dsmc_ctx *x, dsmc_status *out, int32_t clear, void *stream)
     hipStream_t s = S(stream);
     Counters h;
     int32_t n = 0;
+    k_tile_stats<<<1, 1024, 0, s>>>(x->tstat, x->ntiles, x->ctr);
+    if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
     if (hipMemcpyAsync(&h, x->ctr, sizeof(Counters), hipMemcpyDeviceToHost, s) != hipSuccess) return DSMC_EHIP;
     if (hipMemcpyAsync(&n, x->cs[x->cur] + x->ncells, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
         return DSMC_EHIP;

@@ -1,24 +1,22 @@
 // DSMC particle step on gfx950: move + wall + cell index, deterministic
 // stable counting sort, NTC hard-sphere collisions, moment sampling.
 //
-// Design.  The particles are sorted by cell at the start of a step and move
-// at most one cell per step in all but rare cases, so the destination of a
-// particle is fixed by its (old cell o, direction d) group, d one of the 9
-// moves inside the 3x3 neighbourhood: a stable order inside a new cell c is
-// "groups in increasing old-cell order, and slot order inside a group".
-// Every particle's direction code for the coming step is known before the
-// step starts (k_step writes it for the state it produces; k_classify
-// computes it for a state set from outside).  One step is then
-//   cell kernels  (one thread per new cell) sum the groups that arrive in c,
-//                 scan, and give every group its first destination slot;
-//   k_step        (one workgroup per tile of new cells) gather the tile's
-//                 particles from its neighbour cells, redo their move (the
-//                 random numbers are counter-based, so it is bit-identical),
-//                 run the NTC collisions and the moment sample on the staged
-//                 tile, write it out contiguously, and classify the next
-//                 step's moves.
-// The state is read once and written once per step, plus one code byte per
-// particle; nothing depends on the order of atomic operations.
+// Design.  Particles move at most one cell per step in all but rare cases,
+// so the stable sort by new cell is fixed by the (old cell, direction)
+// groups, direction d one of the 9 moves inside the 3x3 neighbourhood (or a
+// long jump): inside new cell c the order is "arriving groups by old cell,
+// each group in old-slot order".  Between two steps of a call the state is
+// kept moved for the coming step and partitioned by direction inside every
+// old cell, with the group sizes beside it, so that each group is one
+// contiguous run.  One step is then
+//   cell kernels  (one thread per new cell) sum the groups arriving in c and
+//                 scan the counts into the new cell_start;
+//   k_step        (one wave per tile of TC cells) gathers the tile's groups,
+//                 runs the NTC collisions and the moment sample on the
+//                 staged tile, moves it for the next step and writes it out
+//                 partitioned by the next step's directions.
+// The state is read once and written once per step; nothing depends on the
+// order of atomic operations.
 #include "dsmc_device.hpp"
 #include "step_kernels.hpp"
 
@@ -124,7 +122,7 @@ __device__ __forceinline__ int block_exscan_256(int v, int *lds)
     return woff + inc - v;
 }
 
-// append a long jump of the particle in slot q (old cell o, new cell nc)
+// append a long jump of the particle written to slot q (old cell o, new cell nc)
 __device__ __forceinline__ void record_far(int32_t *far, int32_t *farcnt, Counters *ctr, int slot, int far_cap, int q,
                                            int o, int nc)
 {
@@ -140,265 +138,622 @@ __device__ __forceinline__ void record_far(int32_t *far, int32_t *farcnt, Counte
     }
 }
 
-// ---- the move of a settled state (one wave per cell) --------------------------
-// Free flight (with walls) of every particle of the current, cell-sorted
-// state over the coming step, written back in place, with its direction
-// code, the per-cell counts of the 9 (cell, direction) groups and the
-// long-jump list.  Runs for the first step of every dsmc_step call;
-// inside a call k_step moves the state it writes.
-__global__ __launch_bounds__(256) void k_classify(ClassifyArgs a)
-{
-    const int lane = threadIdx.x & 63;
-    const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (o >= a.ncells) return;  // wave-uniform
-    const int start = a.cs[o], end = a.cs[o + 1];
-    const int nx = a.G.nx;
-    const int oix = o % nx, oiy = o / nx;
-    int run[NDIR];
-#pragma unroll
-    for (int d = 0; d < NDIR; ++d) run[d] = 0;
-    bool limit = false;
-    int walls = 0;
-    for (int p0 = start; p0 < end; p0 += 64) {
-        const int p = p0 + lane;
-        int d = DIR_NONE, nc = 0;
-        if (p < end) {
-            double x = a.st[0][p], y = a.st[1][p], vx = a.st[2][p], vy = a.st[3][p], vz = a.st[4][p];
-            walls += move_particle(a.G, a.M, (uint32_t)p, x, y, vx, vy, vz, limit);
-            a.st[0][p] = x;
-            a.st[1][p] = y;
-            a.st[2][p] = vx;
-            a.st[3][p] = vy;
-            a.st[4][p] = vz;
-            int nix, niy;
-            cell_xy(a.G, x, y, nix, niy);
-            d = direction(nx, oix, oiy, nix, niy);
-            nc = niy * nx + nix;
-        }
-#pragma unroll
-        for (int dd = 0; dd < NDIR; ++dd) run[dd] += __popcll(ballot64(d == dd));
-        if (p < end) {
-            a.code[p] = (uint8_t)d;
-            if (d == DIR_FAR) record_far(a.far, a.farcnt, a.ctr, a.far_slot, a.far_cap, p, o, nc);
-        }
-    }
-    if (lane < NDIR) {
-        int v = 0;
-#pragma unroll
-        for (int dd = 0; dd < NDIR; ++dd)
-            if (lane == dd) v = run[dd];
-        a.cnt[(size_t)lane * a.ncells + o] = v;
-    }
-    const unsigned long long wsum = wave_sum_u64((unsigned long long)walls);
-    if (lane == 0 && wsum) atomicAdd(&a.ctr->nwall, wsum);
-    if (ballot64(limit) != 0 && lane == 0) atomicOr(&a.ctr->status, ST_WALL_LIMIT);
-}
+// ---- tiles of cells, one wave each ------------------------------------------------
+constexpr int NTC_ROUND = 32;  // NTC candidates drawn per round (all cells of a tile)
 
-// ---- inverse of the new sort: source slot of every new slot -----------------
-// One wave per old cell, in slot order: a particle of group (o, d) goes to
-// new slot base[d][o] + (number of earlier particles of o with the same d),
-// counted with one ballot per direction.  (Long jumps get theirs in
-// k_cell_final.)
-__global__ __launch_bounds__(256) void k_invert(InvertArgs a)
-{
-    const int lane = threadIdx.x & 63;
-    const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (o >= a.ncells) return;
-    const int start = a.cs[o], end = a.cs[o + 1];
-    const int n = a.cs[a.ncells];
-    int b[NDIR];
-#pragma unroll
-    for (int d = 0; d < NDIR; ++d) b[d] = a.base[(size_t)d * a.ncells + o];
-    for (int p0 = start; p0 < end; p0 += 64) {
-        const int p = p0 + lane;
-        const int d = p < end ? (int)a.code[p] : DIR_NONE;
-        int q = -1;
-#pragma unroll
-        for (int dd = 0; dd < NDIR; ++dd) {
-            const uint64_t m = ballot64(d == dd);
-            if (d == dd) q = b[dd] + rank_below(m);
-            b[dd] += __popcll(m);
-        }
-        if (d < NDIR) {
-            if (q >= 0 && q < n) a.from[q] = p;
-            else atomicOr(&a.ctr->status, ST_INTERNAL);
-        }
-    }
-}
-
-// ---- the DSMC step, organised by destination tile --------------------------------
-// The state it reads has already been moved (by k_classify or by the
-// previous k_step) and carries each particle's direction code and rank.
-// One workgroup per tile of TC consecutive new cells (their particles are
-// the contiguous new slots [D0, D0 + nt)):
-//   1. gather: copy every new slot's particle from its source slot (from
-//      k_invert), positions to the new buffer, velocities to the stage;
-//   2. NTC collisions of the step, one lane per new cell, on the stage;
-//   3. a team of 256/TC lanes per cell: moment sample (when due), then
-//      either the settled state out (last step of a call) or the next
-//      step's move of every particle, written out with its direction code;
-//      the (cell, direction) counts are summed in LDS.
-constexpr int ST_PMAX = 896;  // tile particles that fit the LDS stage
-constexpr int ST_PER_THREAD = (ST_PMAX + 255) / 256;
-
-template <int TC>
-struct StepLds {
-    double v[5][ST_PMAX];  // x, y, vx, vy, vz of the tile's particles
-    int32_t csn[TC + 1];
-    int32_t cnt[TC * NDIR];
+template <int TC, int CH>
+struct TileLds {
+    static constexpr int CAP = 64 * CH;
+    double v[5][CAP];              // x, y, vx, vy, vz of the tile's particles, in new-slot order
+    int32_t kr[CAP];               // next-step group (low 6 bits) and rank inside it, per slot
+    double dr[5][NTC_ROUND];       // one round of NTC draws: R, cos(theta), sin(theta), cos(phi), sin(phi)
+    int32_t di[2][NTC_ROUND];      // ... and the candidate pairs (i, j)
+    long long mc[TC];              // NTC candidates of each cell this step
+    int32_t csn[TC + 1];           // cell starts of the tile after the sort
+    int32_t tix[TC], tiy[TC];      // cell coordinates
+    int32_t anyfar;                // long jumps arrive in some cell of the tile
+    int32_t ng[TC];                // near groups arriving in each cell
+    int32_t gkey[TC][NDIR];        // their source cells, ascending
+    int32_t gsrc[TC][NDIR];        // their first source slots
+    int32_t gn[TC][NDIR];          // their sizes
+    int32_t gstart[TC][NDIR];      // their first slots inside the cell
+    int32_t raw[3][TC * NDIR];     // near groups before ordering: source cell, size, first source slot
+    int32_t run[TC * NGRP];        // sizes of the next step's groups of the tile's cells ...
+    int32_t excl[TC * NGRP];       // ... and their offsets inside each cell
 };
 
-template <int TC, bool STAGE>
-__device__ __forceinline__ void step_tile(const StepArgs &a, StepLds<TC> &L, int c0, int ntc, int D0, int nt)
+// cell (0 .. ntc-1) of tile slot i
+template <int TC, int CH>
+__device__ __forceinline__ int tile_cell(const TileLds<TC, CH> &L, int ntc, int D0, int i)
 {
-    constexpr int T = 256 / TC;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nx = a.G.nx, nc = a.ncells;
-    double *const ovx = a.out[2] + D0, *const ovy = a.out[3] + D0, *const ovz = a.out[4] + D0;
-    double *const ox = a.out[0] + D0, *const oy = a.out[1] + D0;
-    double *const sx = STAGE ? L.v[0] : ox;
-    double *const sy = STAGE ? L.v[1] : oy;
-    double *const svx = STAGE ? L.v[2] : ovx;
-    double *const svy = STAGE ? L.v[3] : ovy;
-    double *const svz = STAGE ? L.v[4] : ovz;
-    const int n_old = a.cs_old[nc];
+    int t = 0;
+#pragma unroll
+    for (int u = 1; u < TC; ++u) t += (u < ntc && i >= L.csn[u] - D0) ? 1 : 0;
+    return t;
+}
+
+// source slot of the particle that the sort puts at offset r of tile cell t
+// when a near group holds that offset; -1 otherwise (a long jump's slot)
+template <int TC, int CH>
+__device__ __forceinline__ int tile_source(const TileLds<TC, CH> &L, int t, int r)
+{
+    const int ng = L.ng[t];
+    int k = 0;
+#pragma unroll
+    for (int u = 1; u < NDIR; ++u) k += (u < ng && r >= L.gstart[t][u]) ? 1 : 0;
+    const int off = r - L.gstart[t][k];
+    return (ng > 0 && off >= 0 && off < L.gn[t][k]) ? L.gsrc[t][k] + off : -1;
+}
+
+// Long jumps arriving in tile cell t (rare): every near group is preceded
+// in the sort by the long jumps from smaller source cells; counts them and
+// shifts the group starts.
+template <int TC, int CH>
+__device__ void tile_far_shift(const StepArgs &a, TileLds<TC, CH> &L, int t, int c, int nfin)
+{
+    const uint32_t nf = min(a.ctr->nfar[a.far_in_slot], (uint32_t)a.far_cap);
+    const int ng = L.ng[t];
+    int shift[NDIR];
+#pragma unroll
+    for (int k = 0; k < NDIR; ++k) shift[k] = 0;
+    int found = 0;
+    for (uint32_t e = 0; e < nf; ++e) {
+        if (a.far_in[4 * (size_t)e + 2] != c) continue;
+        ++found;
+        const int o = a.far_in[4 * (size_t)e + 1];
+#pragma unroll
+        for (int k = 0; k < NDIR; ++k)
+            if (k < ng && o < L.gkey[t][k]) shift[k] += 1;
+    }
+#pragma unroll
+    for (int k = 0; k < NDIR; ++k)
+        if (k < ng) L.gstart[t][k] += shift[k];
+    if (found != nfin) atomicOr(&a.ctr->status, ST_INTERNAL);
+    a.farcnt_in[c] = 0;
+}
+
+// Stages the long jumps arriving in the tile at their sorted slots: after
+// the near groups of smaller source cells and the long jumps of smaller
+// (source cell, source slot).  s[k] address the tile's stage.
+template <int TC, int CH>
+__device__ void tile_far_gather(const StepArgs &a, const TileLds<TC, CH> &L, double *const *s, int c0, int ntc,
+                                int n_old)
+{
+    const uint32_t nf = min(a.ctr->nfar[a.far_in_slot], (uint32_t)a.far_cap);
+    const int D0 = L.csn[0];
+    for (uint32_t e = threadIdx.x; e < nf; e += 64) {
+        const int nc = a.far_in[4 * (size_t)e + 2];
+        if (nc < c0 || nc >= c0 + ntc) continue;
+        const int t = nc - c0;
+        const int q = a.far_in[4 * (size_t)e], o = a.far_in[4 * (size_t)e + 1];
+        int r = 0;
+        for (int k = 0; k < L.ng[t]; ++k)
+            if (L.gkey[t][k] < o) r += L.gn[t][k];
+        for (uint32_t f = 0; f < nf; ++f) {
+            if (a.far_in[4 * (size_t)f + 2] != nc) continue;
+            const int o2 = a.far_in[4 * (size_t)f + 1], q2 = a.far_in[4 * (size_t)f];
+            if (o2 < o || (o2 == o && q2 < q)) ++r;
+        }
+        const int slot = L.csn[t] - D0 + r;
+        if (q < 0 || q >= n_old || slot >= L.csn[t + 1] - D0) {
+            atomicOr(&a.ctr->status, ST_INTERNAL);
+            continue;
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) s[k][slot] = a.in[k][q];
+    }
+}
+
+// The groups arriving in every cell of the tile, in the order of the stable
+// sort: by source cell, each group in source-slot order.  The state read
+// here keeps every old cell's particles partitioned by move direction, so a
+// near group (source cell s, direction d) is the contiguous run that starts
+// after the groups 0 .. d-1 of s.
+template <int TC, int CH>
+__device__ void tile_groups(const StepArgs &a, TileLds<TC, CH> &L, int ntc, int nfin)
+{
+    const int lane = threadIdx.x, nx = a.G.nx;
+    if (lane < TC * NDIR) {
+        const int t = lane / NDIR, d = lane - t * NDIR;
+        int s = -1, n = 0, src = 0;
+        if (t < ntc) {
+            const int sc = source_cell(nx, a.G.ny, L.tix[t], L.tiy[t], d);
+            if (sc >= 0) {
+                // all ten group sizes of the source cell in one round of loads
+                const int32_t *g = a.grp_in + (size_t)sc * NGRP;
+                int gv[NGRP];
+#pragma unroll
+                for (int e = 0; e < NGRP; ++e) gv[e] = g[e];
+                int before = 0;
+#pragma unroll
+                for (int e = 0; e < NDIR; ++e) {
+                    if (e < d) before += gv[e];
+                    if (e == d) n = gv[e];
+                }
+                src = a.cs_old[sc] + before;
+                if (n > 0) s = sc;
+            }
+        }
+        L.raw[0][lane] = s;
+        L.raw[1][lane] = n;
+        L.raw[2][lane] = src;
+    }
+    __syncthreads();
+    if (lane < TC * NDIR) {
+        const int t = lane / NDIR;
+        const int s = L.raw[0][lane];
+        if (s >= 0) {
+            int rank = 0, pre = 0;
+            for (int e = 0; e < NDIR; ++e) {
+                const int se = L.raw[0][t * NDIR + e];
+                if (se >= 0 && se < s) {
+                    ++rank;
+                    pre += L.raw[1][t * NDIR + e];
+                }
+            }
+            L.gkey[t][rank] = s;
+            L.gn[t][rank] = L.raw[1][lane];
+            L.gsrc[t][rank] = L.raw[2][lane];
+            L.gstart[t][rank] = pre;
+        }
+    }
+    if (lane < TC) {
+        int ng = 0, tot = 0;
+        for (int e = 0; e < NDIR; ++e) {
+            if (L.raw[0][lane * NDIR + e] >= 0) {
+                ++ng;
+                tot += L.raw[1][lane * NDIR + e];
+            }
+        }
+        L.ng[lane] = ng;
+        if (ng == 0) {
+            L.gstart[lane][0] = 0;
+            L.gn[lane][0] = 0;
+        }
+        if (lane < ntc && tot + nfin != L.csn[lane + 1] - L.csn[lane]) atomicOr(&a.ctr->status, ST_INTERNAL);
+    }
+    if (lane == 0) L.anyfar = 0;
+    __syncthreads();
+    if (lane < ntc && nfin > 0) {
+        L.anyfar = 1;
+        tile_far_shift<TC, CH>(a, L, lane, L.tiy[lane] * nx + L.tix[lane], nfin);
+    }
+    __syncthreads();
+}
+
+// ---- NTC collisions of the tile (Eq. (collisionnumber)) ---------------------------
+// Per cell: update the running mean of N, form the candidate count
+// 1/2 N Nbar K sigcmax dt + rem (K = F_N sigma_T / V_c), draw candidate pairs
+// uniformly (i != j), accept with probability c_r / sigcmax (hard spheres)
+// and scatter isotropically in the centre-of-mass frame.  Candidate k of
+// cell c at step s draws from counters (2k, c, s, COLL) and (2k+1, c, s,
+// COLL).  The draws do not depend on the velocities, so a round of up to
+// NTC_ROUND/TC candidates per cell is drawn by the lanes of the wave at
+// once; one lane per cell then runs its candidates in order.
+template <int TC, int CH>
+__device__ __forceinline__ void ntc_draws(TileLds<TC, CH> &L, const NtcParams &P, int c0, int ntc, long long k0)
+{
+    constexpr int KC = NTC_ROUND / TC;
+    const int lane = threadIdx.x;
+    const int t = lane / KC;
+    const long long k = k0 + (lane - t * KC);
+    if (lane < NTC_ROUND && t < ntc && k < L.mc[t]) {
+        const uint32_t N = (uint32_t)(L.csn[t + 1] - L.csn[t]);
+        const uint32_t c = (uint32_t)(c0 + t);
+        const U4 u = draw(P.k0, P.k1, (uint32_t)(2 * k), c, P.step, TAG_COLL, 0u);
+        const uint32_t i = (uint32_t)(((uint64_t)u.x * (uint64_t)N) >> 32);
+        uint32_t j = (uint32_t)(((uint64_t)u.y * (uint64_t)(N - 1)) >> 32);
+        if (j >= i) j += 1;
+        const U4 w = draw(P.k0, P.k1, (uint32_t)(2 * k + 1), c, P.step, TAG_COLL, 0u);
+        const double cth = 2.0 * u53(w.x, w.y) - 1.0;
+        double sphi, cphi;
+        sincos_turn(u53(w.z, w.w), sphi, cphi);  // phi = 2 pi R
+        L.di[0][lane] = (int32_t)i;
+        L.di[1][lane] = (int32_t)j;
+        L.dr[0][lane] = u53(u.z, u.w);
+        L.dr[1][lane] = cth;
+        L.dr[2][lane] = sqrt(1.0 - cth * cth);
+        L.dr[3][lane] = cphi;
+        L.dr[4][lane] = sphi;
+    }
+}
+
+template <int TC, int CH>
+__device__ __forceinline__ void ntc_chain(double *vx, double *vy, double *vz, const TileLds<TC, CH> &L, int e0,
+                                          int n, double &sig, unsigned long long &ncoll)
+{
+    for (int e = e0; e < e0 + n; ++e) {
+        const int i = L.di[0][e], j = L.di[1][e];
+        const double vxi = vx[i], vyi = vy[i], vzi = vz[i];
+        const double vxj = vx[j], vyj = vy[j], vzj = vz[j];
+        const double dx = vxi - vxj, dy = vyi - vyj, dz = vzi - vzj;
+        const double cr = sqrt(dx * dx + dy * dy + dz * dz);
+        if (cr > sig) sig = cr;
+        if (cr / sig > L.dr[0][e]) {
+            const double cth = L.dr[1][e], sth = L.dr[2][e], cphi = L.dr[3][e], sphi = L.dr[4][e];
+            const double rx = cr * cth;
+            const double ry = cr * sth * cphi;
+            const double rz = cr * sth * sphi;
+            const double mx = 0.5 * (vxi + vxj);
+            const double my = 0.5 * (vyi + vyj);
+            const double mz = 0.5 * (vzi + vzj);
+            vx[i] = mx + 0.5 * rx, vy[i] = my + 0.5 * ry, vz[i] = mz + 0.5 * rz;
+            vx[j] = mx - 0.5 * rx, vy[j] = my - 0.5 * ry, vz[j] = mz - 0.5 * rz;
+            ncoll += 1;
+        }
+    }
+}
+
+// v* address the tile's velocities (LDS or global), slot 0 = first of the tile
+template <int TC, int CH>
+__device__ __forceinline__ void tile_ntc(double *vx, double *vy, double *vz, TileLds<TC, CH> &L,
+                                         const NtcParams &P, int c0, int ntc, double &nbar, double &sig,
+                                         double &rem, unsigned long long &ncoll, unsigned long long &ncand)
+{
+    constexpr int KC = NTC_ROUND / TC;
+    const int lane = threadIdx.x;
+    const int D0 = L.csn[0];
+    long long M = 0;
+    int s0 = 0;
+    if (lane < ntc) {
+        const int N = L.csn[lane + 1] - L.csn[lane];
+        s0 = L.csn[lane] - D0;
+        const double Nd = (double)N;
+        nbar = nbar + (Nd - nbar) / (double)(P.step + 1);
+        const double pairf = (P.nbar_mode == 1) ? (Nd - 1.0) : nbar;
+        double X = 0.5 * Nd * pairf * P.K * sig * P.dt + rem;
+        if (!(X > 0.0)) X = 0.0;
+        const double Mf = floor(X);
+        rem = X - Mf;
+        M = N < 2 ? 0 : (long long)Mf;
+        L.mc[lane] = M;
+    }
+    __syncthreads();
+    for (long long k0 = 0; ballot64(lane < ntc && M > k0) != 0; k0 += KC) {
+        ntc_draws<TC, CH>(L, P, c0, ntc, k0);
+        __syncthreads();
+        if (lane < ntc && M > k0) {
+            const int n = (int)min(M - k0, (long long)KC);
+            ntc_chain<TC, CH>(vx + s0, vy + s0, vz + s0, L, lane * KC, n, sig, ncoll);
+            ncand += (unsigned long long)n;
+        }
+        __syncthreads();
+    }
+}
+
+// moment sample: a team of 64/TC lanes per cell; the lane that owns sum m of
+// cell t (see tile_kernel) adds the team total to the running sum
+template <int TC, int CH>
+__device__ __forceinline__ void tile_sample(const double *vx, const double *vy, const double *vz,
+                                            const TileLds<TC, CH> &L, int ntc, bool mown, double mprev,
+                                            double *mdst)
+{
+    constexpr int T = 64 / TC;
+    const int lane = threadIdx.x, team = lane / T, lt = lane - team * T;
+    const int D0 = L.csn[0];
+    double acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+    if (team < ntc) {
+        const int s0 = L.csn[team] - D0, e0 = L.csn[team + 1] - D0;
+        for (int i = s0 + lt; i < e0; i += T) add_moments(acc, vx[i], vy[i], vz[i]);
+    }
+    const double tot = team_reduce_scatter16<T>(acc, lt);
+    if (mown) *mdst = mprev + tot;
+}
+
+// ---- the move and the grouping of the moved particles ---------------------------
+// free flight (with walls) of a particle of tile cell t over the coming
+// step, and its direction code
+template <int TC, int CH>
+__device__ __forceinline__ int move_code(const StepArgs &a, const TileLds<TC, CH> &L, int t, uint32_t slot,
+                                         double &x, double &y, double &vx, double &vy, double &vz, int &walls,
+                                         bool &limit)
+{
+    walls += move_particle(a.G, a.M1, slot, x, y, vx, vy, vz, limit);
+    int nix, niy;
+    cell_xy(a.G, x, y, nix, niy);
+    return direction(a.G.nx, L.tix[t], L.tiy[t], nix, niy);
+}
+
+// Moves the particles of one 64-slot chunk (slots b0 .. b0+63 of the tile)
+// in place and gives each its next-step group key t * NGRP + d and its
+// stable rank inside the group (ranks continue from earlier chunks: lane k
+// of `run` holds the size of group k so far).  One ballot per direction,
+// masked to the lanes of the particle's own cell, ranks all 64 lanes at once.
+template <int TC, int CH>
+__device__ __forceinline__ void move_chunk(const StepArgs &a, const TileLds<TC, CH> &L, double *const *s,
+                                           int32_t *kr, int ntc, int nt, int b0, int &run, int &walls, bool &limit)
+{
+    const int lane = threadIdx.x;
+    const int D0 = L.csn[0];
+    const int i = b0 + lane;
+    const bool act = i < nt;
+    int t = 0, d = 0;
+    if (act) {
+        t = tile_cell<TC, CH>(L, ntc, D0, i);
+        double x = s[0][i], y = s[1][i], vx = s[2][i], vy = s[3][i], vz = s[4][i];
+        d = move_code<TC, CH>(a, L, t, (uint32_t)(D0 + i), x, y, vx, vy, vz, walls, limit);
+        s[0][i] = x;
+        s[1][i] = y;
+        s[2][i] = vx;
+        s[3][i] = vy;
+        s[4][i] = vz;
+    }
+    uint64_t bd[NGRP];
+#pragma unroll
+    for (int e = 0; e < NGRP; ++e) bd[e] = ballot64(act && d == e);
+    uint64_t mine = 0;
+#pragma unroll
+    for (int e = 0; e < NGRP; ++e)
+        if (d == e) mine = bd[e];
+    // lanes [lo, hi) of this chunk hold cell u
+    auto lanes_of = [&](int u) -> uint64_t {
+        const int lo = min(max(L.csn[u] - D0 - b0, 0), 64), hi = min(max(L.csn[u + 1] - D0 - b0, 0), 64);
+        const uint64_t below_hi = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+        const uint64_t below_lo = lo >= 64 ? ~0ull : ((1ull << lo) - 1ull);
+        return below_hi & ~below_lo;
+    };
+    const int key = t * NGRP + d;
+    const int before = __shfl(run, key, 64);
+    if (act) {
+        const uint64_t same = mine & lanes_of(t);
+        kr[i] = ((before + rank_below(same)) << 6) | key;
+    }
+    if (lane < ntc * NGRP) {
+        const int u = lane / NGRP, e = lane - u * NGRP;
+        uint64_t m = 0;
+#pragma unroll
+        for (int f = 0; f < NGRP; ++f)
+            if (e == f) m = bd[f];
+        run += __popcll(m & lanes_of(u));
+    }
+}
+
+// sizes of the tile cells' next-step groups (held by lane t * NGRP + d)
+// published, and their offsets inside each cell
+template <int TC, int CH>
+__device__ __forceinline__ void tile_group_offsets(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc, int run)
+{
+    const int lane = threadIdx.x;
+    if (lane < TC * NGRP) L.run[lane] = run;
+    __syncthreads();
+    if (lane < ntc * NGRP) {
+        const int t = lane / NGRP, d = lane - t * NGRP;
+        int ex = 0;
+        for (int e = 0; e < d; ++e) ex += L.run[t * NGRP + e];
+        L.excl[lane] = ex;
+        a.grp_out[(size_t)c0 * NGRP + lane] = run;
+    }
+    __syncthreads();
+}
+
+// ---- the step kernel ------------------------------------------------------------------
+// One wave per tile of TC consecutive cells.
+//   GATHER (a DSMC step): the particles that the step's sort puts in the
+//     tile's cells are gathered group by group from the moved, partitioned
+//     state, collided (NTC) and sampled; with MOVE they are then moved for
+//     the next step, partitioned by direction inside their cells and
+//     written out with the next step's group sizes; without MOVE (the last
+//     step of a call) they are written out in sorted order.
+//   no GATHER (k_classify): a settled state is moved for the coming step
+//     and partitioned in place.
+// STAGED tiles (at most 64*CH particles) are staged in LDS; larger ones run
+// the same steps on the tile's destination range in global memory.
+template <int TC, int CH, bool GATHER, bool MOVE, bool STAGED>
+__device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc, int nt, int n_old, double &nbar,
+                          double &sig, double &rem, bool mown, double mprev, double *mdst,
+                          unsigned long long &ncoll, unsigned long long &ncand, int &walls, bool &limit)
+{
+    const int lane = threadIdx.x;
+    const int D0 = L.csn[0];
+    double *s[5];
+    int32_t *kr;
+    if (STAGED) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) s[k] = L.v[k];
+        kr = L.kr;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) s[k] = a.out[k] + D0;  // k_classify: out == in (in place)
+        kr = a.scr_i + D0;
+    }
 
     // 1. gather
-    for (int r0 = 0; r0 < nt; r0 += 256 * ST_PER_THREAD) {
-        double x[ST_PER_THREAD], y[ST_PER_THREAD], vx[ST_PER_THREAD], vy[ST_PER_THREAD], vz[ST_PER_THREAD];
-        int pp[ST_PER_THREAD];
+    if (STAGED) {
+        // every load of the tile in flight at once
+        double g[CH][5];
+        bool g_ok[CH];
 #pragma unroll
-        for (int r = 0; r < ST_PER_THREAD; ++r) {
-            const int slot = r0 + tid + 256 * r;
-            pp[r] = slot < nt ? a.from[D0 + slot] : -1;
-            if (pp[r] >= n_old) pp[r] = -1;
+        for (int b = 0; b < CH; ++b) {
+            const int i = 64 * b + lane;
+            int src = -1;
+            if (i < nt) {
+                if (GATHER) {
+                    const int t = tile_cell<TC, CH>(L, ntc, D0, i);
+                    src = tile_source<TC, CH>(L, t, i - (L.csn[t] - D0));
+                    if (src >= n_old) {
+                        src = -1;
+                        atomicOr(&a.ctr->status, ST_INTERNAL);
+                    }
+                } else {
+                    src = D0 + i;
+                }
+            }
+            g_ok[b] = src >= 0;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) g[b][k] = src >= 0 ? a.in[k][src] : 0.0;
         }
 #pragma unroll
-        for (int r = 0; r < ST_PER_THREAD; ++r) {
-            if (pp[r] >= 0) {
-                x[r] = a.in[0][pp[r]];
-                y[r] = a.in[1][pp[r]];
-                vx[r] = a.in[2][pp[r]];
-                vy[r] = a.in[3][pp[r]];
-                vz[r] = a.in[4][pp[r]];
+        for (int b = 0; b < CH; ++b) {
+            const int i = 64 * b + lane;
+            if (i < nt && g_ok[b]) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) L.v[k][i] = g[b][k];
             }
         }
-#pragma unroll
-        for (int r = 0; r < ST_PER_THREAD; ++r) {
-            const int slot = r0 + tid + 256 * r;
-            if (slot >= nt) continue;
-            if (pp[r] < 0) {
-                atomicOr(&a.ctr->status, ST_INTERNAL);
-                continue;
-            }
-            sx[slot] = x[r];
-            sy[slot] = y[r];
-            svx[slot] = vx[r];
-            svy[slot] = vy[r];
-            svz[slot] = vz[r];
+        if (GATHER && L.anyfar) {
+            __syncthreads();
+            tile_far_gather<TC, CH>(a, L, s, c0, ntc, n_old);
         }
+        __syncthreads();
+    } else if (GATHER) {
+        for (int i = lane; i < nt; i += 64) {
+            const int t = tile_cell<TC, CH>(L, ntc, D0, i);
+            const int src = tile_source<TC, CH>(L, t, i - (L.csn[t] - D0));
+            if (src >= n_old) atomicOr(&a.ctr->status, ST_INTERNAL);
+            if (src < 0 || src >= n_old) continue;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) s[k][i] = a.in[k][src];
+        }
+        if (L.anyfar) tile_far_gather<TC, CH>(a, L, s, c0, ntc, n_old);
+        __threadfence();
+        __syncthreads();
     }
-    __threadfence_block();
-    __syncthreads();
 
-    // 2. NTC collisions of this step, one lane per new cell
-    {
-        unsigned long long ncoll = 0, ncand = 0;
-        if (tid < ntc) {
-            const int c = c0 + tid;
-            const int s0 = L.csn[tid] - D0, N = L.csn[tid + 1] - L.csn[tid];
-            double nbar = a.nbar[c], sig = a.sigcmax[c], rem = a.rem[c];
-            ntc_cell(svx + s0, svy + s0, svz + s0, N, (uint32_t)c, a.N, nbar, sig, rem, ncoll, ncand);
-            a.nbar[c] = nbar;
-            a.sigcmax[c] = sig;
-            a.rem[c] = rem;
-        }
-        if (wave == 0) {
-            ncoll = wave_sum_u64(ncoll);
-            ncand = wave_sum_u64(ncand);
-            if (lane == 0 && ncoll) atomicAdd(&a.ctr->ncoll, ncoll);
-            if (lane == 0 && ncand) atomicAdd(&a.ctr->ncand, ncand);
-        }
+    // 2. collisions and 3. sample
+    if (GATHER) {
+        tile_ntc<TC, CH>(s[2], s[3], s[4], L, a.N, c0, ntc, nbar, sig, rem, ncoll, ncand);
+        if (!STAGED) __threadfence();
+        __syncthreads();
+        if (a.sample) tile_sample<TC, CH>(s[2], s[3], s[4], L, ntc, mown, mprev, mdst);
     }
-    if (!STAGE) __threadfence_block();
-    __syncthreads();
 
-    // 3. one team per cell: sample, then move (or settle) and write out
-    int walls = 0;
-    bool limit = false;
-    {
-        const int team = tid / T, lt = tid % T;
-        double acc[16];
+    if (!MOVE) {
+        if (STAGED) {
+            for (int i = lane; i < nt; i += 64) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-        const bool live = team < ntc;
-        const int o = c0 + (live ? team : 0);
-        const int oix = o % nx, oiy = o / nx;
-        const int s0 = live ? L.csn[team] - D0 : 0, e0 = live ? L.csn[team + 1] - D0 : 0;
-        if (a.sample) {
-            for (int i = s0 + lt; i < e0; i += T) add_moments(acc, svx[i], svy[i], svz[i]);
-            const double tot = team_reduce_scatter16<T>(acc, lt);
-            constexpr int SPAN = T / 16;
-            const int slot = (lt / SPAN) & 15;
-            if (live && (lt % SPAN) == 0 && slot < NMOM) a.mom[(size_t)slot * nc + o] += tot;
-        }
-        for (int i = s0 + lt; i < e0; i += T) {
-            double x = sx[i], y = sy[i], vx = svx[i], vy = svy[i], vz = svz[i];
-            if (a.classify) {
-                walls += move_particle(a.G, a.M1, (uint32_t)(D0 + i), x, y, vx, vy, vz, limit);
-                int nix, niy;
-                cell_xy(a.G, x, y, nix, niy);
-                const int d = direction(nx, oix, oiy, nix, niy);
-                a.code_out[D0 + i] = (uint8_t)d;
-                if (d == DIR_FAR)
-                    record_far(a.far_out, a.farcnt, a.ctr, a.far_slot ^ 1, a.far_cap, D0 + i, o, niy * nx + nix);
-                else
-                    atomicAdd(&L.cnt[team * NDIR + d], 1);
-            }
-            if (STAGE || a.classify) {
-                ox[i] = x;
-                oy[i] = y;
-                ovx[i] = vx;
-                ovy[i] = vy;
-                ovz[i] = vz;
+                for (int k = 0; k < 5; ++k) a.out[k][D0 + i] = L.v[k][i];
             }
         }
+        return;  // unstaged: already in place, in sorted order
     }
-    __syncthreads();
-    if (a.classify) {
-        for (int k = tid; k < ntc * NDIR; k += 256) {
-            const int cl = k / NDIR, d = k - cl * NDIR;
-            a.cnt[(size_t)d * nc + c0 + cl] = L.cnt[k];
+
+    // 4. move for the next step, grouped by (cell, direction) in slot order
+    int run = 0;
+    for (int b0 = 0; b0 < nt; b0 += 64) move_chunk<TC, CH>(a, L, s, kr, ntc, nt, b0, run, walls, limit);
+    tile_group_offsets<TC, CH>(a, L, c0, ntc, run);
+
+    // 5. write out, partitioned by group inside each cell
+    if (STAGED) {
+        for (int i = lane; i < nt; i += 64) {
+            const int k6 = kr[i], key = k6 & 63, t = key / NGRP;
+            const int q = L.csn[t] + L.excl[key] + (k6 >> 6);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) a.out[k][q] = L.v[k][i];
+        }
+    } else {
+        __threadfence();
+        __syncthreads();
+        for (int k = 0; k < 5; ++k) {
+            for (int i = lane; i < nt; i += 64) a.scr[D0 + i] = s[k][i];
+            __threadfence();
+            __syncthreads();
+            for (int i = lane; i < nt; i += 64) {
+                const int k6 = kr[i], key = k6 & 63, t = key / NGRP;
+                a.out[k][L.csn[t] + L.excl[key] + (k6 >> 6)] = a.scr[D0 + i];
+            }
+            __threadfence();
+            __syncthreads();
         }
     }
-    const unsigned long long wsum = wave_sum_u64((unsigned long long)walls);
-    if (lane == 0 && wsum) atomicAdd(&a.ctr->nwall, wsum);
-    if (ballot64(limit) != 0 && lane == 0) atomicOr(&a.ctr->status, ST_WALL_LIMIT);
+    for (int i = lane; i < nt; i += 64) {
+        const int k6 = kr[i], key = k6 & 63, t = key / NGRP;
+        if (key - t * NGRP != DIR_FAR) continue;
+        const int q = L.csn[t] + L.excl[key] + (k6 >> 6);
+        int nix, niy;
+        cell_xy(a.G, STAGED ? L.v[0][i] : a.out[0][q], STAGED ? L.v[1][i] : a.out[1][q], nix, niy);
+        record_far(a.far_out, a.farcnt_out, a.ctr, a.far_out_slot, a.far_cap, q, c0 + t, niy * a.G.nx + nix);
+    }
 }
 
-template <int TC>
-__global__ __launch_bounds__(256) void k_step(StepArgs a)
+template <int TC, int CH, bool GATHER, bool MOVE>
+__device__ __forceinline__ void tile_kernel(const StepArgs &a)
 {
-    __shared__ StepLds<TC> L;
-    const int tid = threadIdx.x;
+    static_assert(TC == 1 || TC == 2 || TC == 4, "tile sizes with teams of >= 16 lanes");
+    static_assert(TC * NGRP <= 64 && NTC_ROUND <= 64, "");
+    static_assert(GATHER || MOVE, "");
+    __shared__ TileLds<TC, CH> L;
+    constexpr int T = 64 / TC, SPAN = T / 16;
+    const int lane = threadIdx.x;
+    const int nc = a.ncells, nx = a.G.nx;
     const int c0 = blockIdx.x * TC;
-    const int ntc = min(TC, a.ncells - c0);
-    if (tid <= TC) L.csn[tid] = a.cs_new[min(c0 + tid, a.ncells)];
-    if (tid < TC * NDIR) L.cnt[tid] = 0;
+    const int ntc = min(TC, nc - c0);
+
+    // set-up: every per-cell quantity of the tile is loaded in one round
+    if (lane <= TC) L.csn[lane] = a.cs_new[min(c0 + lane, nc)];
+    if (lane < TC) {
+        const int c = min(c0 + lane, nc - 1);
+        L.tiy[lane] = c / nx;
+        L.tix[lane] = c - (c / nx) * nx;
+    }
+    double nbar = 0.0, sig = 0.0, rem = 0.0;
+    int nfin = 0;
+    if (GATHER && lane < ntc) {
+        nbar = a.nbar[c0 + lane];
+        sig = a.sigcmax[c0 + lane];
+        rem = a.rem[c0 + lane];
+        nfin = a.farcnt_in[c0 + lane];
+    }
+    const int team = lane / T, lt = lane - team * T, mslot = lt / SPAN;
+    const bool mown = GATHER && a.sample && team < ntc && (lt % SPAN) == 0 && mslot < NMOM;
+    double *const mdst = a.mom + (size_t)(mown ? mslot : 0) * nc + c0 + (mown ? team : 0);
+    double mprev = 0.0;
+    if (mown) mprev = *mdst;
+    const int n_old = GATHER ? a.cs_old[nc] : 0;
+    unsigned long long *const tst = a.tstat + 3 * (size_t)blockIdx.x + (lane < 3 ? lane : 0);
+    const unsigned long long tprev = lane < 3 ? *tst : 0ull;
     __syncthreads();
+    if (GATHER) tile_groups<TC, CH>(a, L, ntc, nfin);
     const int D0 = L.csn[0];
     const int nt = L.csn[ntc] - D0;
-    if (nt <= ST_PMAX)
-        step_tile<TC, true>(a, L, c0, ntc, D0, nt);
+
+    unsigned long long ncoll = 0, ncand = 0;
+    int walls = 0;
+    bool limit = false;
+    if (nt <= TileLds<TC, CH>::CAP)
+        tile_body<TC, CH, GATHER, MOVE, true>(a, L, c0, ntc, nt, n_old, nbar, sig, rem, mown, mprev, mdst, ncoll,
+                                              ncand, walls, limit);
     else
-        step_tile<TC, false>(a, L, c0, ntc, D0, nt);
+        tile_body<TC, CH, GATHER, MOVE, false>(a, L, c0, ntc, nt, n_old, nbar, sig, rem, mown, mprev, mdst, ncoll,
+                                               ncand, walls, limit);
+
+    if (GATHER && lane < ntc) {
+        a.nbar[c0 + lane] = nbar;
+        a.sigcmax[c0 + lane] = sig;
+        a.rem[c0 + lane] = rem;
+    }
+    // the tile's running counters (no atomics: every tile owns its entry)
+    ncoll = wave_sum_u64(ncoll);
+    ncand = wave_sum_u64(ncand);
+    const unsigned long long wsum = wave_sum_u64((unsigned long long)walls);
+    if (lane < 3) *tst = tprev + (lane == 0 ? ncoll : (lane == 1 ? ncand : wsum));
+    if (MOVE && ballot64(limit) != 0 && lane == 0) atomicOr(&a.ctr->status, ST_WALL_LIMIT);
 }
 
-template __global__ void k_step<4>(StepArgs);
-template __global__ void k_step<8>(StepArgs);
-template __global__ void k_step<16>(StepArgs);
+template <int TC, int CH>
+__global__ __launch_bounds__(64) void k_classify(StepArgs a)
+{
+    tile_kernel<TC, CH, false, true>(a);
+}
 
-// counts arriving in every cell of the new sort, and their block sums
+template <int TC, int CH, bool MOVE>
+__global__ __launch_bounds__(64) void k_step(StepArgs a)
+{
+    tile_kernel<TC, CH, true, MOVE>(a);
+}
+
+#define DSMC_TILE_INSTANCES(TC, CH)                              \
+    template __global__ void k_classify<TC, CH>(StepArgs);       \
+    template __global__ void k_step<TC, CH, true>(StepArgs);     \
+    template __global__ void k_step<TC, CH, false>(StepArgs);
+DSMC_TILE_INSTANCES(4, 4)
+DSMC_TILE_INSTANCES(2, 4)
+DSMC_TILE_INSTANCES(1, 4)
+DSMC_TILE_INSTANCES(1, 8)
+#undef DSMC_TILE_INSTANCES
+
+// particles arriving in every cell with the step's sort, and their block sums
 __global__ __launch_bounds__(256) void k_cell_count(CellArgs a)
 {
     __shared__ int lds[4];
@@ -409,7 +764,7 @@ __global__ __launch_bounds__(256) void k_cell_count(CellArgs a)
 #pragma unroll
         for (int d = 0; d < NDIR; ++d) {
             const int src = source_cell(a.nx, a.ny, cix, ciy, d);
-            if (src >= 0) total += a.cnt[(size_t)d * a.ncells + src];
+            if (src >= 0) total += a.grp[(size_t)src * NGRP + d];
         }
         total += a.farcnt[c];
         a.countnew[c] = total;
@@ -454,73 +809,6 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int32_t *blocksum, int nbl
         __syncthreads();
     }
     if (threadIdx.x == 0) cs_out[ncells] = carry_s;
-}
-
-// new cell_start, first destination slot of every arriving group, and the
-// destinations of long jumps into the cell
-__global__ __launch_bounds__(256) void k_cell_final(CellArgs a)
-{
-    __shared__ int lds[4];
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    const int v = c < a.ncells ? a.countnew[c] : 0;
-    const int ex = block_exscan_256(v, lds);
-    if (c >= a.ncells) return;
-    const int cs = a.blocksum[blockIdx.x] + ex;
-    a.cs_new[c] = cs;
-
-    const int cix = c % a.nx, ciy = c / a.nx;
-    int srcs[NDIR], dirs[NDIR], cnts[NDIR];
-    int ns = 0;
-#pragma unroll
-    for (int d = 0; d < NDIR; ++d) {
-        const int src = source_cell(a.nx, a.ny, cix, ciy, d);
-        if (src >= 0) {
-            srcs[ns] = src;
-            dirs[ns] = d;
-            cnts[ns] = a.cnt[(size_t)d * a.ncells + src];
-            ++ns;
-        }
-    }
-    // order the arriving groups by old cell (insertion sort of <= 9)
-    for (int i = 1; i < ns; ++i) {
-        const int s = srcs[i], d = dirs[i], n = cnts[i];
-        int j = i - 1;
-        while (j >= 0 && srcs[j] > s) {
-            srcs[j + 1] = srcs[j];
-            dirs[j + 1] = dirs[j];
-            cnts[j + 1] = cnts[j];
-            --j;
-        }
-        srcs[j + 1] = s;
-        dirs[j + 1] = d;
-        cnts[j + 1] = n;
-    }
-    const int nfar_in = a.farcnt[c];
-    const uint32_t nf = min(a.ctr->nfar[a.far_slot], (uint32_t)a.far_cap);
-    int acc = 0;
-    for (int i = 0; i < ns; ++i) {
-        int before_far = 0;
-        if (nfar_in > 0) {
-            for (uint32_t e = 0; e < nf; ++e)
-                if (a.far[4 * (size_t)e + 2] == c && a.far[4 * (size_t)e + 1] < srcs[i]) ++before_far;
-        }
-        a.base[(size_t)dirs[i] * a.ncells + srcs[i]] = cs + acc + before_far;
-        acc += cnts[i];
-    }
-    if (nfar_in > 0) {
-        for (uint32_t e = 0; e < nf; ++e) {
-            if (a.far[4 * (size_t)e + 2] != c) continue;
-            const int po = a.far[4 * (size_t)e + 1], pp = a.far[4 * (size_t)e];
-            int rank = 0;
-            for (int i = 0; i < ns; ++i)
-                if (srcs[i] < po) rank += cnts[i];
-            for (uint32_t f = 0; f < nf; ++f)
-                if (a.far[4 * (size_t)f + 2] == c && a.far[4 * (size_t)f] < pp) ++rank;
-            a.far[4 * (size_t)e + 3] = cs + rank;
-            a.from[cs + rank] = pp;
-        }
-        a.farcnt[c] = 0;
-    }
 }
 
 // averages = sums / S
@@ -660,6 +948,33 @@ __global__ void k_far_reset(Counters *c, int slot)
 __global__ void k_clear_status(Counters *c)
 {
     if (threadIdx.x == 0) c->status = 0u;
+}
+
+// totals of the per-tile counters (one workgroup of 1024)
+__global__ __launch_bounds__(1024) void k_tile_stats(const unsigned long long *tstat, int ntiles, Counters *c)
+{
+    __shared__ unsigned long long part[3][16];
+    unsigned long long v[3] = {0ull, 0ull, 0ull};
+    for (int t = threadIdx.x; t < ntiles; t += 1024) {
+        v[0] += tstat[3 * (size_t)t];
+        v[1] += tstat[3 * (size_t)t + 1];
+        v[2] += tstat[3 * (size_t)t + 2];
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[k] = wave_sum_u64(v[k]);
+        if (lane == 0) part[k][w] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot[3] = {0ull, 0ull, 0ull};
+        for (int k = 0; k < 3; ++k)
+            for (int i = 0; i < 16; ++i) tot[k] += part[k][i];
+        c->ncoll = tot[0];
+        c->ncand = tot[1];
+        c->nwall = tot[2];
+    }
 }
 
 }  // namespace dsmc

@@ -14,58 +14,40 @@ struct NtcParams {
     int nbar_mode;
 };
 
-struct ClassifyArgs {
-    double *st[5];        // current sorted state, moved in place
-    const int32_t *cs;    // its cell_start
-    uint8_t *code;        // direction code per particle
-    int32_t *cnt;         // [9][ncells] group counts
-    int32_t *farcnt;      // [ncells] long jumps arriving per cell
-    int32_t *far;         // long-jump list of the step's parity
-    Counters *ctr;
-    Geometry G;
-    MoveParams M;         // the coming step
-    int ncells, far_cap, far_slot;
-};
-
-struct InvertArgs {
-    const int32_t *cs;      // current cell_start
-    const uint8_t *code;    // direction code per particle
-    const int32_t *base;    // [9][ncells] first new slot of every group
-    int32_t *from;          // source slot of every new slot
-    Counters *ctr;
-    int ncells;
-};
+// Per-cell partition of a moved state: inside every old cell's slot range
+// the particles are grouped by direction code 0..9 (the 9 near moves, then
+// long jumps), each group in slot order; grp[c][d] holds the group sizes.
+constexpr int NGRP = NDIR + 1;
 
 struct StepArgs {
-    const double *in[5];    // current sorted state
-    double *out[5];         // the state after the step, sorted by the new cells
-    const int32_t *cs_old;  // current cell_start
-    const int32_t *cs_new;  // cell_start after the step
-    const int32_t *from;    // source slot of every new slot
-    uint8_t *code_out;      // direction codes of the new state for the next step
-    int32_t *far_out;       // the next step's long jumps
-    int32_t *cnt;           // [9][ncells] the next step's group counts
-    int32_t *farcnt;        // [ncells] the next step's long jumps per arrival cell
+    const double *in[5];     // state of the step: moved and partitioned (k_step), or settled (k_classify)
+    double *out[5];          // the state written (k_classify: the same arrays as in)
+    const int32_t *cs_old;   // cell_start of in
+    const int32_t *cs_new;   // cell_start after the step's sort (k_classify: cs_old)
+    const int32_t *grp_in;   // [ncells][NGRP] group sizes of in
+    int32_t *grp_out;        // [ncells][NGRP] group sizes of the next step's partition
+    const int32_t *far_in;   // the step's long jumps (slot, old cell, new cell, -)
+    int32_t *farcnt_in;      // [ncells] long jumps arriving per cell (read and cleared)
+    int32_t *far_out;        // the next step's long jumps
+    int32_t *farcnt_out;     // [ncells] the next step's long jumps per arrival cell
+    double *scr;             // [capacity] scratch of oversized tiles
+    int32_t *scr_i;          // [capacity] scratch of oversized tiles
     Counters *ctr;
-    double *mom;            // [11][ncells] sums
+    unsigned long long *tstat;  // [tiles][3] running collisions, candidates and wall hits of every tile
+    double *mom;             // [11][ncells] sums
     double *nbar, *sigcmax, *rem;
     Geometry G;
-    MoveParams M1;          // the next step (its move is done here unless this is the call's last step)
-    NtcParams N;            // this step's collisions
-    int ncells, far_cap, far_slot, sample, classify;
+    MoveParams M1;           // the move done here: the next step's (k_step), the coming step's (k_classify)
+    NtcParams N;             // this step's collisions
+    int ncells, far_cap, far_in_slot, far_out_slot, sample;
 };
 
 struct CellArgs {
-    int32_t *from;  // inverse map, filled here for long jumps
-    const int32_t *cnt;
-    int32_t *base;
-    int32_t *farcnt;
-    int32_t *far;
+    const int32_t *grp;      // [ncells][NGRP] group sizes of the moved state
+    const int32_t *farcnt;   // [ncells] long jumps arriving per cell
     int32_t *countnew;
     int32_t *blocksum;
-    int32_t *cs_new;
-    Counters *ctr;
-    int nx, ny, ncells, far_cap, far_slot;
+    int nx, ny, ncells;
 };
 
 struct InitArgs {
@@ -125,14 +107,14 @@ struct LbmArgs {
     double tau, gx;
 };
 
-__global__ void k_classify(ClassifyArgs a);
-__global__ void k_invert(InvertArgs a);
-template <int TC>
+// TC cells per tile (one wave); tiles of up to 64*CH particles are staged in LDS
+template <int TC, int CH>
+__global__ void k_classify(StepArgs a);
+template <int TC, int CH, bool MOVE>
 __global__ void k_step(StepArgs a);
 __global__ void k_cell_count(CellArgs a);
 __global__ void k_scan_blocks(int32_t *blocksum, int nblk, int32_t *cs_out, int ncells, Counters *ctr,
                               int reset_slot);
-__global__ void k_cell_final(CellArgs a);
 __global__ void k_average(const double *mom, double *out, size_t n, double S);
 __global__ void k_init_maxwell(InitArgs a);
 __global__ void k_adopt_count(AdoptArgs a);
@@ -145,6 +127,7 @@ __global__ void k_fill_f64(double *p, size_t n, double v);
 __global__ void k_fill_i32(int32_t *p, size_t n, int32_t v);
 __global__ void k_zero_counters(Counters *c);
 __global__ void k_clear_status(Counters *c);
+__global__ void k_tile_stats(const unsigned long long *tstat, int ntiles, Counters *c);
 __global__ void k_far_reset(Counters *c, int slot);
 
 __global__ void k_project(ProjectArgs a);
