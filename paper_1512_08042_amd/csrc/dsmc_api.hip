@@ -196,7 +196,7 @@ int far_cap_of(const dsmc_config &c)
 
 struct Layout {
     size_t cs0, cs1, grp0, grp1, countnew, farcnt, blocksum, far0, far1, nbar, sigcmax, rem, mom, mark, prm, nnew, perm,
-        tstat, ctr, total;
+        tstat, kc, ctr, total;
 };
 
 Layout make_layout(const dsmc_config &c)
@@ -229,6 +229,7 @@ Layout make_layout(const dsmc_config &c)
     L.nnew = take(nc * 4);
     L.perm = take(cap * 12);  // adoption: permutation + cell ids; steps: scratch of oversized tiles
     L.tstat = take(3 * nc * 8);  // per step tile (at most one tile per cell)
+    L.kc = take(sizeof(TileConst));
     L.ctr = take(sizeof(Counters));
     L.total = o;
     return L;
@@ -249,6 +250,8 @@ struct dsmc_ctx {
     double *nbar, *sigcmax, *rem, *mom, *prm;
     Counters *ctr;
     unsigned long long *tstat;
+    TileConst *kc;       // device copy of kc_host
+    TileConst kc_host;
     int ncells, nblk, far_cap, ntiles;
     double K, s_th;
     Geometry G;
@@ -330,29 +333,47 @@ NtcParams ntc_params(const dsmc_ctx *x, int64_t step)
     return N;
 }
 
-// the arguments every step-kernel launch shares; the caller fills in the
-// state, cell_start, group and long-jump buffers of its launch
-StepArgs step_args(const dsmc_ctx *x, int p)
+StepArgs step_args(const dsmc_ctx *x, int32_t cur, int64_t step, bool sample, bool classify)
 {
-    StepArgs a{};
-    a.grp_in = x->grp[p];
-    a.far_in = x->far[p];
-    a.farcnt_in = x->farcnt + (size_t)p * x->ncells;
-    a.far_in_slot = p;
-    a.scr = (double *)x->perm;
-    a.scr_i = (int32_t *)((char *)x->perm + (size_t)x->cfg.capacity * 8);
-    a.ctr = x->ctr;
-    a.tstat = x->tstat;
-    a.mom = x->mom;
-    a.nbar = x->nbar;
-    a.sigcmax = x->sigcmax;
-    a.rem = x->rem;
-    a.G = x->G;
-    a.N = ntc_params(x, x->step);
-    a.ncells = x->ncells;
-    a.far_cap = x->far_cap;
-    a.sample = 0;
+    StepArgs a;
+    a.kc = x->kc;
+    a.step = (uint32_t)step;
+    a.cur = cur;
+    a.sample = sample ? 1 : 0;
+    a.classify = classify ? 1 : 0;
     return a;
+}
+
+// the fixed part of every step-kernel launch, copied to the workspace
+int upload_tile_const(dsmc_ctx *x, hipStream_t s)
+{
+    TileConst &k = x->kc_host;
+    for (int b = 0; b < 2; ++b) {
+        for (int j = 0; j < 5; ++j) k.st[b][j] = x->st[b][j];
+        k.cs[b] = x->cs[b];
+        k.grp[b] = x->grp[b];
+        k.far[b] = x->far[b];
+        k.farcnt[b] = x->farcnt + (size_t)b * x->ncells;
+    }
+    k.scr = (double *)x->perm;
+    k.scr_i = (int32_t *)((char *)x->perm + (size_t)x->cfg.capacity * 8);
+    k.ctr = x->ctr;
+    k.tstat = x->tstat;
+    k.mom = x->mom;
+    k.nbar = x->nbar;
+    k.sigcmax = x->sigcmax;
+    k.rem = x->rem;
+    k.G = x->G;
+    k.dt = x->cfg.dt;
+    k.g = x->cfg.body_force_x;
+    k.s_th = x->s_th;
+    k.K = x->K;
+    k.k0 = (uint32_t)x->cfg.seed;
+    k.k1 = (uint32_t)(x->cfg.seed >> 32);
+    k.nbar_mode = x->cfg.nbar_mode;
+    k.ncells = x->ncells;
+    k.far_cap = x->far_cap;
+    return hipMemcpyAsync(x->kc, &k, sizeof(TileConst), hipMemcpyHostToDevice, s) == hipSuccess ? DSMC_OK : DSMC_EHIP;
 }
 
 // one launch of the tile kernels: kind 0 = k_classify, 1 = k_step
@@ -495,6 +516,7 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
     x->perm = (int32_t *)(w + L.perm);
     x->ctr = (Counters *)(w + L.ctr);
     x->tstat = (unsigned long long *)(w + L.tstat);
+    x->kc = (TileConst *)(w + L.kc);
     x->ncells = (int)ncells;
     x->nblk = (int)((ncells + 255) / 256);
     x->far_cap = far_cap_of(*cfg);
@@ -527,6 +549,7 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
     if (rc == DSMC_OK) rc = fill_i32(x->farcnt, 2 * (size_t)ncells, 0, s);
     if (rc == DSMC_OK) rc = fill_i32(x->mark, (size_t)ncells, 0, s);
     if (rc == DSMC_OK) rc = fill_i32((int32_t *)x->tstat, 6 * (size_t)x->ntiles, 0, s);
+    if (rc == DSMC_OK) rc = upload_tile_const(x, s);
     if (rc == DSMC_OK && mode == 0) {
         InitArgs a;
         for (int k = 0; k < 5; ++k) a.st[k] = x->st[0][k];
@@ -599,18 +622,7 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
         const int p = (int)(x->step & 1);
         TRY(fill_i32(x->farcnt, 2 * (size_t)nc, 0, s));
         k_far_reset<<<1, 64, 0, s>>>(x->ctr, p);
-        StepArgs a = step_args(x, p);
-        for (int k = 0; k < 5; ++k) {
-            a.in[k] = x->st[x->cur][k];
-            a.out[k] = x->st[x->cur][k];
-        }
-        a.cs_old = x->cs[x->cur];
-        a.cs_new = x->cs[x->cur];
-        a.grp_out = x->grp[p];
-        a.far_out = x->far[p];
-        a.farcnt_out = x->farcnt + (size_t)p * nc;
-        a.far_out_slot = p;
-        a.M1 = move_params(x, x->step);
+        const StepArgs a = step_args(x, x->cur, x->step, false, true);
         TRY(launch(x, DSMC_K_CLASSIFY, s, [&] { launch_tiles(x, 0, true, ntiles, s, a); }));
         x->classified = true;
     }
@@ -635,24 +647,7 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
 
         const bool sample = sample_every > 0 && ((x->step + 1) % sample_every) == 0;
         const bool move = it + 1 < nsteps;  // the call's last step leaves the state settled
-        StepArgs a = step_args(x, p);
-        for (int k = 0; k < 5; ++k) {
-            a.in[k] = x->st[cur][k];
-            a.out[k] = x->st[nxt][k];
-        }
-        a.cs_old = x->cs[cur];
-        a.cs_new = x->cs[nxt];
-        a.grp_in = x->grp[p];
-        a.grp_out = x->grp[p ^ 1];
-        a.far_in = x->far[p];
-        a.farcnt_in = x->farcnt + (size_t)p * nc;
-        a.far_in_slot = p;
-        a.far_out = x->far[p ^ 1];
-        a.farcnt_out = x->farcnt + (size_t)(p ^ 1) * nc;
-        a.far_out_slot = p ^ 1;
-        a.M1 = move_params(x, x->step + 1);
-        a.N = ntc_params(x, x->step);
-        a.sample = sample ? 1 : 0;
+        const StepArgs a = step_args(x, cur, x->step, sample, false);
         TRY(launch(x, DSMC_K_STEP, s, [&] { launch_tiles(x, 1, move, ntiles, s, a); }));
         x->cur = nxt;
         if (sample) x->nsamples += 1;

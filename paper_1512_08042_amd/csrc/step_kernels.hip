@@ -191,16 +191,16 @@ __device__ __forceinline__ int tile_source(const TileLds<TC, CH> &L, int t, int 
 template <int TC, int CH>
 __device__ void tile_far_shift(const StepArgs &a, TileLds<TC, CH> &L, int t, int c, int nfin)
 {
-    const uint32_t nf = min(a.ctr->nfar[a.far_in_slot], (uint32_t)a.far_cap);
+    const uint32_t nf = min(a.K().ctr->nfar[a.far_in_slot()], (uint32_t)a.K().far_cap);
     const int ng = L.ng[t];
     int shift[NDIR];
 #pragma unroll
     for (int k = 0; k < NDIR; ++k) shift[k] = 0;
     int found = 0;
     for (uint32_t e = 0; e < nf; ++e) {
-        if (a.far_in[4 * (size_t)e + 2] != c) continue;
+        if (a.far_in()[4 * (size_t)e + 2] != c) continue;
         ++found;
-        const int o = a.far_in[4 * (size_t)e + 1];
+        const int o = a.far_in()[4 * (size_t)e + 1];
 #pragma unroll
         for (int k = 0; k < NDIR; ++k)
             if (k < ng && o < L.gkey[t][k]) shift[k] += 1;
@@ -208,8 +208,8 @@ __device__ void tile_far_shift(const StepArgs &a, TileLds<TC, CH> &L, int t, int
 #pragma unroll
     for (int k = 0; k < NDIR; ++k)
         if (k < ng) L.gstart[t][k] += shift[k];
-    if (found != nfin) atomicOr(&a.ctr->status, ST_INTERNAL);
-    a.farcnt_in[c] = 0;
+    if (found != nfin) atomicOr(&a.K().ctr->status, ST_INTERNAL);
+    a.farcnt_in()[c] = 0;
 }
 
 // Stages the long jumps arriving in the tile at their sorted slots: after
@@ -219,28 +219,28 @@ template <int TC, int CH>
 __device__ void tile_far_gather(const StepArgs &a, const TileLds<TC, CH> &L, double *const *s, int c0, int ntc,
                                 int n_old)
 {
-    const uint32_t nf = min(a.ctr->nfar[a.far_in_slot], (uint32_t)a.far_cap);
+    const uint32_t nf = min(a.K().ctr->nfar[a.far_in_slot()], (uint32_t)a.K().far_cap);
     const int D0 = L.csn[0];
     for (uint32_t e = threadIdx.x; e < nf; e += 64) {
-        const int nc = a.far_in[4 * (size_t)e + 2];
+        const int nc = a.far_in()[4 * (size_t)e + 2];
         if (nc < c0 || nc >= c0 + ntc) continue;
         const int t = nc - c0;
-        const int q = a.far_in[4 * (size_t)e], o = a.far_in[4 * (size_t)e + 1];
+        const int q = a.far_in()[4 * (size_t)e], o = a.far_in()[4 * (size_t)e + 1];
         int r = 0;
         for (int k = 0; k < L.ng[t]; ++k)
             if (L.gkey[t][k] < o) r += L.gn[t][k];
         for (uint32_t f = 0; f < nf; ++f) {
-            if (a.far_in[4 * (size_t)f + 2] != nc) continue;
-            const int o2 = a.far_in[4 * (size_t)f + 1], q2 = a.far_in[4 * (size_t)f];
+            if (a.far_in()[4 * (size_t)f + 2] != nc) continue;
+            const int o2 = a.far_in()[4 * (size_t)f + 1], q2 = a.far_in()[4 * (size_t)f];
             if (o2 < o || (o2 == o && q2 < q)) ++r;
         }
         const int slot = L.csn[t] - D0 + r;
         if (q < 0 || q >= n_old || slot >= L.csn[t + 1] - D0) {
-            atomicOr(&a.ctr->status, ST_INTERNAL);
+            atomicOr(&a.K().ctr->status, ST_INTERNAL);
             continue;
         }
 #pragma unroll
-        for (int k = 0; k < 5; ++k) s[k][slot] = a.in[k][q];
+        for (int k = 0; k < 5; ++k) s[k][slot] = a.in(k)[q];
     }
 }
 
@@ -252,15 +252,15 @@ __device__ void tile_far_gather(const StepArgs &a, const TileLds<TC, CH> &L, dou
 template <int TC, int CH>
 __device__ void tile_groups(const StepArgs &a, TileLds<TC, CH> &L, int ntc, int nfin)
 {
-    const int lane = threadIdx.x, nx = a.G.nx;
+    const int lane = threadIdx.x, nx = a.geo().nx;
     if (lane < TC * NDIR) {
         const int t = lane / NDIR, d = lane - t * NDIR;
         int s = -1, n = 0, src = 0;
         if (t < ntc) {
-            const int sc = source_cell(nx, a.G.ny, L.tix[t], L.tiy[t], d);
+            const int sc = source_cell(nx, a.geo().ny, L.tix[t], L.tiy[t], d);
             if (sc >= 0) {
                 // all ten group sizes of the source cell in one round of loads
-                const int32_t *g = a.grp_in + (size_t)sc * NGRP;
+                const int32_t *g = a.grp_in() + (size_t)sc * NGRP;
                 int gv[NGRP];
 #pragma unroll
                 for (int e = 0; e < NGRP; ++e) gv[e] = g[e];
@@ -270,7 +270,7 @@ __device__ void tile_groups(const StepArgs &a, TileLds<TC, CH> &L, int ntc, int 
                     if (e < d) before += gv[e];
                     if (e == d) n = gv[e];
                 }
-                src = a.cs_old[sc] + before;
+                src = a.cs_old()[sc] + before;
                 if (n > 0) s = sc;
             }
         }
@@ -310,7 +310,7 @@ __device__ void tile_groups(const StepArgs &a, TileLds<TC, CH> &L, int ntc, int 
             L.gstart[lane][0] = 0;
             L.gn[lane][0] = 0;
         }
-        if (lane < ntc && tot + nfin != L.csn[lane + 1] - L.csn[lane]) atomicOr(&a.ctr->status, ST_INTERNAL);
+        if (lane < ntc && tot + nfin != L.csn[lane + 1] - L.csn[lane]) atomicOr(&a.K().ctr->status, ST_INTERNAL);
     }
     if (lane == 0) L.anyfar = 0;
     __syncthreads();
@@ -450,10 +450,10 @@ __device__ __forceinline__ int move_code(const StepArgs &a, const TileLds<TC, CH
                                          double &x, double &y, double &vx, double &vy, double &vz, int &walls,
                                          bool &limit)
 {
-    walls += move_particle(a.G, a.M1, slot, x, y, vx, vy, vz, limit);
+    walls += move_particle(a.geo(), a.M1(), slot, x, y, vx, vy, vz, limit);
     int nix, niy;
-    cell_xy(a.G, x, y, nix, niy);
-    return direction(a.G.nx, L.tix[t], L.tiy[t], nix, niy);
+    cell_xy(a.geo(), x, y, nix, niy);
+    return direction(a.geo().nx, L.tix[t], L.tiy[t], nix, niy);
 }
 
 // Moves the particles of one 64-slot chunk (slots b0 .. b0+63 of the tile)
@@ -463,11 +463,11 @@ __device__ __forceinline__ int move_code(const StepArgs &a, const TileLds<TC, CH
 // masked to the lanes of the particle's own cell, ranks all 64 lanes at once.
 template <int TC, int CH>
 __device__ __forceinline__ void move_chunk(const StepArgs &a, const TileLds<TC, CH> &L, double *const *s,
-                                           int32_t *kr, int ntc, int nt, int b0, int &run, int &walls, bool &limit)
+                                           int32_t *kr, int ntc, int nt, int b0i, int &run, int &walls, bool &limit)
 {
     const int lane = threadIdx.x;
     const int D0 = L.csn[0];
-    const int i = b0 + lane;
+    const int i = b0i + lane;
     const bool act = i < nt;
     int t = 0, d = 0;
     if (act) {
@@ -480,33 +480,30 @@ __device__ __forceinline__ void move_chunk(const StepArgs &a, const TileLds<TC, 
         s[3][i] = vy;
         s[4][i] = vz;
     }
-    uint64_t bd[NGRP];
-#pragma unroll
-    for (int e = 0; e < NGRP; ++e) bd[e] = ballot64(act && d == e);
-    uint64_t mine = 0;
-#pragma unroll
-    for (int e = 0; e < NGRP; ++e)
-        if (d == e) mine = bd[e];
-    // lanes [lo, hi) of this chunk hold cell u
-    auto lanes_of = [&](int u) -> uint64_t {
-        const int lo = min(max(L.csn[u] - D0 - b0, 0), 64), hi = min(max(L.csn[u + 1] - D0 - b0, 0), 64);
-        const uint64_t below_hi = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
-        const uint64_t below_lo = lo >= 64 ? ~0ull : ((1ull << lo) - 1ull);
-        return below_hi & ~below_lo;
+    // lanes of this chunk with direction code e (0..9): from one ballot per
+    // bit of the code
+    const uint64_t actm = ballot64(act);
+    const uint64_t b0 = ballot64(act && (d & 1)), b1 = ballot64(act && (d & 2));
+    const uint64_t b2 = ballot64(act && (d & 4)), b3 = ballot64(act && (d & 8));
+    auto with_code = [&](int e) -> uint64_t {
+        uint64_t m = actm;
+        m &= (e & 1) ? b0 : ~b0;
+        m &= (e & 2) ? b1 : ~b1;
+        m &= (e & 4) ? b2 : ~b2;
+        m &= (e & 8) ? b3 : ~b3;
+        return m;
+    };
+    // lanes of this chunk from the first lane of tile cell u on
+    auto from_cell = [&](int u) -> uint64_t {
+        const int lo = min(max(L.csn[u] - D0 - b0i, 0), 64);
+        return lo >= 64 ? 0ull : (~0ull << lo);
     };
     const int key = t * NGRP + d;
     const int before = __shfl(run, key, 64);
-    if (act) {
-        const uint64_t same = mine & lanes_of(t);
-        kr[i] = ((before + rank_below(same)) << 6) | key;
-    }
+    if (act) kr[i] = ((before + rank_below(with_code(d) & from_cell(t))) << 6) | key;
     if (lane < ntc * NGRP) {
         const int u = lane / NGRP, e = lane - u * NGRP;
-        uint64_t m = 0;
-#pragma unroll
-        for (int f = 0; f < NGRP; ++f)
-            if (e == f) m = bd[f];
-        run += __popcll(m & lanes_of(u));
+        run += __popcll(with_code(e) & from_cell(u) & ~from_cell(u + 1));
     }
 }
 
@@ -523,7 +520,7 @@ __device__ __forceinline__ void tile_group_offsets(const StepArgs &a, TileLds<TC
         int ex = 0;
         for (int e = 0; e < d; ++e) ex += L.run[t * NGRP + e];
         L.excl[lane] = ex;
-        a.grp_out[(size_t)c0 * NGRP + lane] = run;
+        a.grp_out()[(size_t)c0 * NGRP + lane] = run;
     }
     __syncthreads();
 }
@@ -555,8 +552,8 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
         kr = L.kr;
     } else {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) s[k] = a.out[k] + D0;  // k_classify: out == in (in place)
-        kr = a.scr_i + D0;
+        for (int k = 0; k < 5; ++k) s[k] = a.out(k) + D0;  // k_classify: out == in (in place)
+        kr = a.K().scr_i + D0;
     }
 
     // 1. gather
@@ -574,7 +571,7 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
                     src = tile_source<TC, CH>(L, t, i - (L.csn[t] - D0));
                     if (src >= n_old) {
                         src = -1;
-                        atomicOr(&a.ctr->status, ST_INTERNAL);
+                        atomicOr(&a.K().ctr->status, ST_INTERNAL);
                     }
                 } else {
                     src = D0 + i;
@@ -582,7 +579,7 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
             }
             g_ok[b] = src >= 0;
 #pragma unroll
-            for (int k = 0; k < 5; ++k) g[b][k] = src >= 0 ? a.in[k][src] : 0.0;
+            for (int k = 0; k < 5; ++k) g[b][k] = src >= 0 ? a.in(k)[src] : 0.0;
         }
 #pragma unroll
         for (int b = 0; b < CH; ++b) {
@@ -601,10 +598,10 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
         for (int i = lane; i < nt; i += 64) {
             const int t = tile_cell<TC, CH>(L, ntc, D0, i);
             const int src = tile_source<TC, CH>(L, t, i - (L.csn[t] - D0));
-            if (src >= n_old) atomicOr(&a.ctr->status, ST_INTERNAL);
+            if (src >= n_old) atomicOr(&a.K().ctr->status, ST_INTERNAL);
             if (src < 0 || src >= n_old) continue;
 #pragma unroll
-            for (int k = 0; k < 5; ++k) s[k][i] = a.in[k][src];
+            for (int k = 0; k < 5; ++k) s[k][i] = a.in(k)[src];
         }
         if (L.anyfar) tile_far_gather<TC, CH>(a, L, s, c0, ntc, n_old);
         __threadfence();
@@ -613,7 +610,7 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
 
     // 2. collisions and 3. sample
     if (GATHER) {
-        tile_ntc<TC, CH>(s[2], s[3], s[4], L, a.N, c0, ntc, nbar, sig, rem, ncoll, ncand);
+        tile_ntc<TC, CH>(s[2], s[3], s[4], L, a.N(), c0, ntc, nbar, sig, rem, ncoll, ncand);
         if (!STAGED) __threadfence();
         __syncthreads();
         if (a.sample) tile_sample<TC, CH>(s[2], s[3], s[4], L, ntc, mown, mprev, mdst);
@@ -623,7 +620,7 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
         if (STAGED) {
             for (int i = lane; i < nt; i += 64) {
 #pragma unroll
-                for (int k = 0; k < 5; ++k) a.out[k][D0 + i] = L.v[k][i];
+                for (int k = 0; k < 5; ++k) a.out(k)[D0 + i] = L.v[k][i];
             }
         }
         return;  // unstaged: already in place, in sorted order
@@ -640,18 +637,18 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
             const int k6 = kr[i], key = k6 & 63, t = key / NGRP;
             const int q = L.csn[t] + L.excl[key] + (k6 >> 6);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) a.out[k][q] = L.v[k][i];
+            for (int k = 0; k < 5; ++k) a.out(k)[q] = L.v[k][i];
         }
     } else {
         __threadfence();
         __syncthreads();
         for (int k = 0; k < 5; ++k) {
-            for (int i = lane; i < nt; i += 64) a.scr[D0 + i] = s[k][i];
+            for (int i = lane; i < nt; i += 64) a.K().scr[D0 + i] = s[k][i];
             __threadfence();
             __syncthreads();
             for (int i = lane; i < nt; i += 64) {
                 const int k6 = kr[i], key = k6 & 63, t = key / NGRP;
-                a.out[k][L.csn[t] + L.excl[key] + (k6 >> 6)] = a.scr[D0 + i];
+                a.out(k)[L.csn[t] + L.excl[key] + (k6 >> 6)] = a.K().scr[D0 + i];
             }
             __threadfence();
             __syncthreads();
@@ -662,8 +659,8 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
         if (key - t * NGRP != DIR_FAR) continue;
         const int q = L.csn[t] + L.excl[key] + (k6 >> 6);
         int nix, niy;
-        cell_xy(a.G, STAGED ? L.v[0][i] : a.out[0][q], STAGED ? L.v[1][i] : a.out[1][q], nix, niy);
-        record_far(a.far_out, a.farcnt_out, a.ctr, a.far_out_slot, a.far_cap, q, c0 + t, niy * a.G.nx + nix);
+        cell_xy(a.geo(), STAGED ? L.v[0][i] : a.out(0)[q], STAGED ? L.v[1][i] : a.out(1)[q], nix, niy);
+        record_far(a.far_out(), a.farcnt_out(), a.K().ctr, a.far_out_slot(), a.K().far_cap, q, c0 + t, niy * a.geo().nx + nix);
     }
 }
 
@@ -676,12 +673,12 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a)
     __shared__ TileLds<TC, CH> L;
     constexpr int T = 64 / TC, SPAN = T / 16;
     const int lane = threadIdx.x;
-    const int nc = a.ncells, nx = a.G.nx;
+    const int nc = a.K().ncells, nx = a.geo().nx;
     const int c0 = blockIdx.x * TC;
     const int ntc = min(TC, nc - c0);
 
     // set-up: every per-cell quantity of the tile is loaded in one round
-    if (lane <= TC) L.csn[lane] = a.cs_new[min(c0 + lane, nc)];
+    if (lane <= TC) L.csn[lane] = a.cs_new()[min(c0 + lane, nc)];
     if (lane < TC) {
         const int c = min(c0 + lane, nc - 1);
         L.tiy[lane] = c / nx;
@@ -690,18 +687,18 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a)
     double nbar = 0.0, sig = 0.0, rem = 0.0;
     int nfin = 0;
     if (GATHER && lane < ntc) {
-        nbar = a.nbar[c0 + lane];
-        sig = a.sigcmax[c0 + lane];
-        rem = a.rem[c0 + lane];
-        nfin = a.farcnt_in[c0 + lane];
+        nbar = a.K().nbar[c0 + lane];
+        sig = a.K().sigcmax[c0 + lane];
+        rem = a.K().rem[c0 + lane];
+        nfin = a.farcnt_in()[c0 + lane];
     }
     const int team = lane / T, lt = lane - team * T, mslot = lt / SPAN;
     const bool mown = GATHER && a.sample && team < ntc && (lt % SPAN) == 0 && mslot < NMOM;
-    double *const mdst = a.mom + (size_t)(mown ? mslot : 0) * nc + c0 + (mown ? team : 0);
+    double *const mdst = a.K().mom + (size_t)(mown ? mslot : 0) * nc + c0 + (mown ? team : 0);
     double mprev = 0.0;
     if (mown) mprev = *mdst;
-    const int n_old = GATHER ? a.cs_old[nc] : 0;
-    unsigned long long *const tst = a.tstat + 3 * (size_t)blockIdx.x + (lane < 3 ? lane : 0);
+    const int n_old = GATHER ? a.cs_old()[nc] : 0;
+    unsigned long long *const tst = a.K().tstat + 3 * (size_t)blockIdx.x + (lane < 3 ? lane : 0);
     const unsigned long long tprev = lane < 3 ? *tst : 0ull;
     __syncthreads();
     if (GATHER) tile_groups<TC, CH>(a, L, ntc, nfin);
@@ -719,16 +716,16 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a)
                                                ncand, walls, limit);
 
     if (GATHER && lane < ntc) {
-        a.nbar[c0 + lane] = nbar;
-        a.sigcmax[c0 + lane] = sig;
-        a.rem[c0 + lane] = rem;
+        a.K().nbar[c0 + lane] = nbar;
+        a.K().sigcmax[c0 + lane] = sig;
+        a.K().rem[c0 + lane] = rem;
     }
     // the tile's running counters (no atomics: every tile owns its entry)
     ncoll = wave_sum_u64(ncoll);
     ncand = wave_sum_u64(ncand);
     const unsigned long long wsum = wave_sum_u64((unsigned long long)walls);
     if (lane < 3) *tst = tprev + (lane == 0 ? ncoll : (lane == 1 ? ncand : wsum));
-    if (MOVE && ballot64(limit) != 0 && lane == 0) atomicOr(&a.ctr->status, ST_WALL_LIMIT);
+    if (MOVE && ballot64(limit) != 0 && lane == 0) atomicOr(&a.K().ctr->status, ST_WALL_LIMIT);
 }
 
 template <int TC, int CH>

@@ -19,17 +19,15 @@ struct NtcParams {
 // long jumps), each group in slot order; grp[c][d] holds the group sizes.
 constexpr int NGRP = NDIR + 1;
 
-struct StepArgs {
-    const double *in[5];     // state of the step: moved and partitioned (k_step), or settled (k_classify)
-    double *out[5];          // the state written (k_classify: the same arrays as in)
-    const int32_t *cs_old;   // cell_start of in
-    const int32_t *cs_new;   // cell_start after the step's sort (k_classify: cs_old)
-    const int32_t *grp_in;   // [ncells][NGRP] group sizes of in
-    int32_t *grp_out;        // [ncells][NGRP] group sizes of the next step's partition
-    const int32_t *far_in;   // the step's long jumps (slot, old cell, new cell, -)
-    int32_t *farcnt_in;      // [ncells] long jumps arriving per cell (read and cleared)
-    int32_t *far_out;        // the next step's long jumps
-    int32_t *farcnt_out;     // [ncells] the next step's long jumps per arrival cell
+// Everything the step kernels need that stays fixed for a context; kept in
+// device memory (inside the workspace) so that a launch passes a pointer
+// and a few words instead of a large argument block.
+struct TileConst {
+    double *st[2][5];        // the two state buffers (x, y, vx, vy, vz)
+    int32_t *cs[2];          // their cell_start
+    int32_t *grp[2];         // [ncells][NGRP] group sizes, by step parity
+    int32_t *far[2];         // long-jump lists, by step parity
+    int32_t *farcnt[2];      // [ncells] long jumps arriving per cell, by step parity
     double *scr;             // [capacity] scratch of oversized tiles
     int32_t *scr_i;          // [capacity] scratch of oversized tiles
     Counters *ctr;
@@ -37,9 +35,72 @@ struct StepArgs {
     double *mom;             // [11][ncells] sums
     double *nbar, *sigcmax, *rem;
     Geometry G;
-    MoveParams M1;           // the move done here: the next step's (k_step), the coming step's (k_classify)
-    NtcParams N;             // this step's collisions
-    int ncells, far_cap, far_in_slot, far_out_slot, sample;
+    double dt, g, s_th, K;   // time step, acceleration, sqrt(kT/m), F_N sigma_T / V_c
+    uint32_t k0, k1;         // Philox key
+    int nbar_mode, ncells, far_cap;
+};
+
+// One launch of a step kernel.  k_step: the DSMC step `step` (collisions
+// of that step, then the move of step + 1), reading buffer cur and writing
+// 1 - cur.  k_classify (classify = 1): the move of step `step` for the
+// settled state in buffer cur, in place.  Buffers of parity step & 1 hold
+// the partition read by the step's sort.
+struct StepArgs {
+    const TileConst *kc;
+    uint32_t step;
+    int cur, sample, classify;
+
+    // the block is read through the constant address space: it does not
+    // change while a kernel runs, so its fields come in by scalar loads
+    __device__ const __attribute__((address_space(4))) TileConst &K() const
+    {
+        return *(const __attribute__((address_space(4))) TileConst *)kc;
+    }
+
+    __device__ Geometry geo() const
+    {
+        Geometry g;
+        g.nx = K().G.nx;
+        g.ny = K().G.ny;
+        g.Lx = K().G.Lx;
+        g.H = K().G.H;
+        return g;
+    }
+    __device__ int po() const { return classify ? (int)(step & 1u) : (int)((step + 1u) & 1u); }
+    __device__ const double *in(int k) const { return K().st[cur][k]; }
+    __device__ double *out(int k) const { return K().st[classify ? cur : 1 - cur][k]; }
+    __device__ const int32_t *cs_old() const { return K().cs[cur]; }
+    __device__ const int32_t *cs_new() const { return K().cs[classify ? cur : 1 - cur]; }
+    __device__ const int32_t *grp_in() const { return K().grp[step & 1u]; }
+    __device__ int32_t *grp_out() const { return K().grp[po()]; }
+    __device__ const int32_t *far_in() const { return K().far[step & 1u]; }
+    __device__ int32_t *farcnt_in() const { return K().farcnt[step & 1u]; }
+    __device__ int far_in_slot() const { return (int)(step & 1u); }
+    __device__ int32_t *far_out() const { return K().far[po()]; }
+    __device__ int32_t *farcnt_out() const { return K().farcnt[po()]; }
+    __device__ int far_out_slot() const { return po(); }
+    __device__ MoveParams M1() const
+    {
+        MoveParams M;
+        M.dt = K().dt;
+        M.g = K().g;
+        M.s_th = K().s_th;
+        M.k0 = K().k0;
+        M.k1 = K().k1;
+        M.step = classify ? step : step + 1u;
+        return M;
+    }
+    __device__ NtcParams N() const
+    {
+        NtcParams P;
+        P.K = K().K;
+        P.dt = K().dt;
+        P.k0 = K().k0;
+        P.k1 = K().k1;
+        P.step = step;
+        P.nbar_mode = K().nbar_mode;
+        return P;
+    }
 };
 
 struct CellArgs {
