@@ -17,6 +17,8 @@
 //                 partitioned by the next step's directions.
 // The state is read once and written once per step; nothing depends on the
 // order of atomic operations.
+#include <climits>
+
 #include "dsmc_device.hpp"
 #include "step_kernels.hpp"
 
@@ -162,13 +164,13 @@ struct TileLds {
     int32_t excl[TC * NGRP];       // ... and their offsets inside each cell
 };
 
-// cell (0 .. ntc-1) of tile slot i
+// cell (0 .. ntc-1) of tile slot i (0 <= i < nt)
 template <int TC, int CH>
 __device__ __forceinline__ int tile_cell(const TileLds<TC, CH> &L, int ntc, int D0, int i)
 {
     int t = 0;
 #pragma unroll
-    for (int u = 1; u < TC; ++u) t += (u < ntc && i >= L.csn[u] - D0) ? 1 : 0;
+    for (int u = 1; u < TC; ++u) t += (i >= L.csn[u] - D0) ? 1 : 0;  // csn[u] = tile end for u > ntc
     return t;
 }
 
@@ -177,12 +179,12 @@ __device__ __forceinline__ int tile_cell(const TileLds<TC, CH> &L, int ntc, int 
 template <int TC, int CH>
 __device__ __forceinline__ int tile_source(const TileLds<TC, CH> &L, int t, int r)
 {
-    const int ng = L.ng[t];
+    // entries ng .. NDIR-1 of the table are padding (start INT_MAX, size 0)
     int k = 0;
 #pragma unroll
-    for (int u = 1; u < NDIR; ++u) k += (u < ng && r >= L.gstart[t][u]) ? 1 : 0;
+    for (int u = 1; u < NDIR; ++u) k += (r >= L.gstart[t][u]) ? 1 : 0;
     const int off = r - L.gstart[t][k];
-    return (ng > 0 && off >= 0 && off < L.gn[t][k]) ? L.gsrc[t][k] + off : -1;
+    return (off >= 0 && off < L.gn[t][k]) ? L.gsrc[t][k] + off : -1;
 }
 
 // Long jumps arriving in tile cell t (rare): every near group is preceded
@@ -280,21 +282,28 @@ __device__ void tile_groups(const StepArgs &a, TileLds<TC, CH> &L, int ntc, int 
     }
     __syncthreads();
     if (lane < TC * NDIR) {
-        const int t = lane / NDIR;
+        const int t = lane / NDIR, d = lane - t * NDIR;
         const int s = L.raw[0][lane];
+        int rank = 0, pre = 0, ng = 0;
+#pragma unroll
+        for (int e = 0; e < NDIR; ++e) {
+            const int se = L.raw[0][t * NDIR + e];
+            const bool before = se >= 0 && se < s;
+            ng += se >= 0 ? 1 : 0;
+            rank += before ? 1 : 0;
+            pre += before ? L.raw[1][t * NDIR + e] : 0;
+        }
         if (s >= 0) {
-            int rank = 0, pre = 0;
-            for (int e = 0; e < NDIR; ++e) {
-                const int se = L.raw[0][t * NDIR + e];
-                if (se >= 0 && se < s) {
-                    ++rank;
-                    pre += L.raw[1][t * NDIR + e];
-                }
-            }
             L.gkey[t][rank] = s;
             L.gn[t][rank] = L.raw[1][lane];
             L.gsrc[t][rank] = L.raw[2][lane];
             L.gstart[t][rank] = pre;
+        }
+        if (d >= ng) {  // padding; position 0 of a cell without groups too
+            L.gkey[t][d] = INT_MAX;
+            L.gn[t][d] = 0;
+            L.gsrc[t][d] = 0;
+            L.gstart[t][d] = d == 0 ? 0 : INT_MAX;
         }
     }
     if (lane < TC) {
@@ -306,10 +315,6 @@ __device__ void tile_groups(const StepArgs &a, TileLds<TC, CH> &L, int ntc, int 
             }
         }
         L.ng[lane] = ng;
-        if (ng == 0) {
-            L.gstart[lane][0] = 0;
-            L.gn[lane][0] = 0;
-        }
         if (lane < ntc && tot + nfin != L.csn[lane + 1] - L.csn[lane]) atomicOr(&a.K().ctr->status, ST_INTERNAL);
     }
     if (lane == 0) L.anyfar = 0;
@@ -443,62 +448,104 @@ __device__ __forceinline__ void tile_sample(const double *vx, const double *vy, 
 }
 
 // ---- the move and the grouping of the moved particles ---------------------------
-// free flight (with walls) of a particle of tile cell t over the coming
-// step, and its direction code
+constexpr int KEY_WALL = 63;  // marks a particle whose move crosses a wall (done in a second pass)
+
+// direction code of a particle of tile cell t now at (x, y)
 template <int TC, int CH>
-__device__ __forceinline__ int move_code(const StepArgs &a, const TileLds<TC, CH> &L, int t, uint32_t slot,
-                                         double &x, double &y, double &vx, double &vy, double &vz, int &walls,
-                                         bool &limit)
+__device__ __forceinline__ int tile_dir(const StepArgs &a, const TileLds<TC, CH> &L, int t, double x, double y)
 {
-    walls += move_particle(a.geo(), a.M1(), slot, x, y, vx, vy, vz, limit);
     int nix, niy;
     cell_xy(a.geo(), x, y, nix, niy);
     return direction(a.geo().nx, L.tix[t], L.tiy[t], nix, niy);
 }
 
-// Moves the particles of one 64-slot chunk (slots b0 .. b0+63 of the tile)
-// in place and gives each its next-step group key t * NGRP + d and its
-// stable rank inside the group (ranks continue from earlier chunks: lane k
-// of `run` holds the size of group k so far).  One ballot per direction,
-// masked to the lanes of the particle's own cell, ranks all 64 lanes at once.
+// Free flight over the coming step of the particles of one 64-slot chunk
+// (slots b0 .. b0+63 of the tile) that do not reach a wall, in place; their
+// direction codes go to kr.  A particle that would cross a wall is left as
+// it is and marked KEY_WALL.  Returns whether the chunk has such particles.
 template <int TC, int CH>
-__device__ __forceinline__ void move_chunk(const StepArgs &a, const TileLds<TC, CH> &L, double *const *s,
-                                           int32_t *kr, int ntc, int nt, int b0i, int &run, int &walls, bool &limit)
+__device__ __forceinline__ bool move_chunk_free(const StepArgs &a, const TileLds<TC, CH> &L, double *const *s,
+                                                int32_t *kr, int ntc, int nt, int b0)
 {
-    const int lane = threadIdx.x;
-    const int D0 = L.csn[0];
-    const int i = b0i + lane;
-    const bool act = i < nt;
-    int t = 0, d = 0;
-    if (act) {
-        t = tile_cell<TC, CH>(L, ntc, D0, i);
+    const int i = b0 + (int)threadIdx.x;
+    bool wall = false;
+    if (i < nt) {
+        const int t = tile_cell<TC, CH>(L, ntc, L.csn[0], i);
+        const double dt = a.K().dt, g = a.K().g, H = a.K().G.H, Lx = a.K().G.Lx;
+        double x = s[0][i], vx = s[2][i];
+        const double y = s[1][i], vy = s[3][i];
+        // the no-wall branch of move_particle, written out
+        const double yn = y + vy * dt;
+        if (yn < 0.0 || yn > H) {
+            wall = true;
+            kr[i] = KEY_WALL;
+        } else {
+            x = x + vx * dt + 0.5 * g * dt * dt;
+            vx = vx + g * dt;
+            // periodic wrap; inside (0, Lx) floor(x / Lx) is 0 and x stays as it is
+            if (!(x > 0.0 && x < Lx)) {
+                double xw = x - Lx * floor(x / Lx);
+                if (xw < 0.0) xw = xw + Lx;
+                if (xw >= Lx) xw = 0.0;
+                x = xw;
+            }
+            s[0][i] = x;
+            s[1][i] = yn;
+            s[2][i] = vx;
+            kr[i] = t * NGRP + tile_dir<TC, CH>(a, L, t, x, yn);
+        }
+    }
+    return ballot64(wall) != 0;
+}
+
+// the particles of one chunk marked KEY_WALL: the full move with walls
+template <int TC, int CH>
+__device__ void move_chunk_walls(const StepArgs &a, const TileLds<TC, CH> &L, double *const *s, int32_t *kr,
+                                 int ntc, int nt, int b0, int &walls, bool &limit)
+{
+    const int i = b0 + (int)threadIdx.x;
+    if (i < nt && kr[i] == KEY_WALL) {
+        const int t = tile_cell<TC, CH>(L, ntc, L.csn[0], i);
         double x = s[0][i], y = s[1][i], vx = s[2][i], vy = s[3][i], vz = s[4][i];
-        d = move_code<TC, CH>(a, L, t, (uint32_t)(D0 + i), x, y, vx, vy, vz, walls, limit);
+        walls += move_particle(a.geo(), a.M1(), (uint32_t)(L.csn[0] + i), x, y, vx, vy, vz, limit);
         s[0][i] = x;
         s[1][i] = y;
         s[2][i] = vx;
         s[3][i] = vy;
         s[4][i] = vz;
+        kr[i] = t * NGRP + tile_dir<TC, CH>(a, L, t, x, y);
     }
-    // lanes of this chunk with direction code e (0..9): from one ballot per
-    // bit of the code
+}
+
+// Stable rank of every particle of one chunk inside its next-step group
+// (key t * NGRP + d, in kr), continuing from earlier chunks: lane k of `run`
+// holds the size of group k so far.  One ballot per bit of the direction
+// code, masked to the lanes of the particle's own cell, ranks all lanes.
+template <int TC, int CH>
+__device__ __forceinline__ void rank_chunk(const TileLds<TC, CH> &L, int32_t *kr, int ntc, int nt, int b0, int &run)
+{
+    const int lane = threadIdx.x;
+    const int D0 = L.csn[0];
+    const int i = b0 + lane;
+    const bool act = i < nt;
+    const int key = act ? kr[i] : 0;
+    const int t = key / NGRP, d = key - t * NGRP;
     const uint64_t actm = ballot64(act);
-    const uint64_t b0 = ballot64(act && (d & 1)), b1 = ballot64(act && (d & 2));
-    const uint64_t b2 = ballot64(act && (d & 4)), b3 = ballot64(act && (d & 8));
+    const uint64_t b0m = ballot64(act && (d & 1)), b1m = ballot64(act && (d & 2));
+    const uint64_t b2m = ballot64(act && (d & 4)), b3m = ballot64(act && (d & 8));
     auto with_code = [&](int e) -> uint64_t {
         uint64_t m = actm;
-        m &= (e & 1) ? b0 : ~b0;
-        m &= (e & 2) ? b1 : ~b1;
-        m &= (e & 4) ? b2 : ~b2;
-        m &= (e & 8) ? b3 : ~b3;
+        m &= (e & 1) ? b0m : ~b0m;
+        m &= (e & 2) ? b1m : ~b1m;
+        m &= (e & 4) ? b2m : ~b2m;
+        m &= (e & 8) ? b3m : ~b3m;
         return m;
     };
     // lanes of this chunk from the first lane of tile cell u on
     auto from_cell = [&](int u) -> uint64_t {
-        const int lo = min(max(L.csn[u] - D0 - b0i, 0), 64);
+        const int lo = min(max(L.csn[u] - D0 - b0, 0), 64);
         return lo >= 64 ? 0ull : (~0ull << lo);
     };
-    const int key = t * NGRP + d;
     const int before = __shfl(run, key, 64);
     if (act) kr[i] = ((before + rank_below(with_code(d) & from_cell(t))) << 6) | key;
     if (lane < ntc * NGRP) {
@@ -626,9 +673,19 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
         return;  // unstaged: already in place, in sorted order
     }
 
-    // 4. move for the next step, grouped by (cell, direction) in slot order
+    // 4. move for the next step (walls in a second pass), grouped by (cell,
+    // direction) in slot order
+    bool anywall = false;
+    for (int b0 = 0; b0 < nt; b0 += 64) anywall |= move_chunk_free<TC, CH>(a, L, s, kr, ntc, nt, b0);
+    if (!STAGED) __threadfence();
+    __syncthreads();
+    if (anywall) {
+        for (int b0 = 0; b0 < nt; b0 += 64) move_chunk_walls<TC, CH>(a, L, s, kr, ntc, nt, b0, walls, limit);
+        if (!STAGED) __threadfence();
+        __syncthreads();
+    }
     int run = 0;
-    for (int b0 = 0; b0 < nt; b0 += 64) move_chunk<TC, CH>(a, L, s, kr, ntc, nt, b0, run, walls, limit);
+    for (int b0 = 0; b0 < nt; b0 += 64) rank_chunk<TC, CH>(L, kr, ntc, nt, b0, run);
     tile_group_offsets<TC, CH>(a, L, c0, ntc, run);
 
     // 5. write out, partitioned by group inside each cell
