@@ -15,13 +15,20 @@ second (projected plus reseeded cells) is reported beside it.
 Printed JSON line: metric, value, ..., plus
   roofline: the dominant kernel's algorithmic bytes per launch divided by
             its mean launch time (HIP events on its launch stream), against
-            the 8 TB/s HBM peak;
+            the 8 TB/s HBM peak; traffic = the HBM bytes per launch that
+            rocprofv3 counted for the same kernel (FETCH_SIZE and WRITE_SIZE,
+            scaled by what the counters read for a plain 1 GiB copy), taken
+            from the committed summary under profiles/ while the kernel
+            sources are unchanged since it was made, else null;
   cpu_baseline: the FP64 oracle timed on this host on one cycle of the same
             workload (single-threaded).
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -36,14 +43,133 @@ STEPS_PER_CYCLE, STRIP = 10, 16
 
 # algorithmic bytes per unit (FP64): a particle is 5 doubles = 40 B
 BYTES = {
-    # one DSMC step: read the cell-sorted state and write it sorted by the
-    # new cells (80 B per particle); per cell the cell_start pair (8 B), the
-    # NTC state nbar/sigcmax/rem read + written (48 B) and the 11 moment sums
-    # read + written (176 B, sampling every step)
-    "step": (80.0, 8 + 48 + 176),
-    # classification of a state set from outside: read x, y, vx, vy
-    "classify": (32.0, 8 + 9 * 4),
+    # one DSMC step: read the moved state once and write it once (80 B per
+    # particle); per cell the cell_start pair (8 B), the group sizes read and
+    # written (40 + 40 B), the NTC state nbar/sigcmax/rem read + written
+    # (48 B) and the 11 moment sums read + written (176 B, sampling every step)
+    "step": (80.0, 8 + 80 + 48 + 176),
+    # the move of a settled state, in place: read + write the state, write
+    # the group sizes
+    "classify": (80.0, 4 + 40),
 }
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_512x256x100_fp64_traffic.md")
+TRACE_SUMMARY = os.path.join(ROOT, "profiles", "dsmc_cycle_512x256x100_fp64_kernel_trace.md")
+# the commands whose output the summaries condense (run from the repository root)
+TRACE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace -o trace -- "
+             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline")
+PMC_CMDS = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- "
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration")
+# kernel-name prefixes of the library's kernels, by profiling id
+KERNEL_PREFIX = {"step": "void dsmc::k_step<", "classify": "void dsmc::k_classify<"}
+
+
+def source_hash() -> str:
+    """sha256 over the library's kernel sources and its C header."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1512_08042_amd", "csrc", "*.hip")) +
+                   glob.glob(os.path.join(ROOT, "paper_1512_08042_amd", "csrc", "*.hpp")))
+    files.append(os.path.join(ROOT, "include", "dsmc.h"))
+    for p in files:
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the summary is missing or the sources changed since."""
+    try:
+        with open(TRAFFIC_SUMMARY) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    got, src = None, None
+    for ln in lines:
+        if ln.startswith("source_sha256:"):
+            src = ln.split(":", 1)[1].strip()
+        if ln.startswith("traffic_bytes_per_launch %s:" % kernel):
+            got = float(ln.split(":", 1)[1].strip())
+    return got if (src == source_hash() and got is not None) else None
+
+
+def _counter_rows(path):
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize(trace_dir, fetch_dir, write_dir):
+    """Writes the two summaries under profiles/ from rocprofv3 output."""
+    # kernel trace statistics
+    stats = _counter_rows(glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))[0])
+    out = ["# Kernel trace: coupling cycle, 512x256 cells x 100 particles/cell, FP64", "",
+           "Command (from the repository root, on one MI355X):", "", "    " + TRACE_CMD, "",
+           "Each bench cycle: 10 DSMC steps (k_classify once, then cell kernels + k_step per step), the D2Q37",
+           "projection, one BGK step and the strip reseed.  Timed and profiled cycles both appear.", "",
+           "| kernel | calls | mean us | total % |", "|---|---|---|---|"]
+    for r in stats:
+        name = r["Name"]
+        if "dsmc::" not in name and "copyBuffer" not in name:
+            continue
+        out.append("| `%s` | %s | %.1f | %s |" % (name.replace("|", "/"), r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                 r["Percentage"]))
+    out.append("")
+    out.append("Mean duration per profiling id (all template variants, weighted by calls), the figure bench.py's")
+    out.append("HIP-event timing reports as kernels_us_per_launch:")
+    out.append("")
+    for kid, pre in sorted(KERNEL_PREFIX.items()):
+        calls = [(float(r["Calls"]), float(r["AverageNs"])) for r in stats if r["Name"].startswith(pre)]
+        if calls:
+            n = sum(c for c, _ in calls)
+            out.append("mean_us %s: %.1f" % (kid, sum(c * a for c, a in calls) / n / 1e3))
+    with open(TRACE_SUMMARY, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+
+    # HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), calibrated on
+    # the three 1 GiB device copies bench.py --copy-calibration makes
+    def per_kernel(rows):
+        agg = {}
+        for r in rows:
+            agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return agg
+    fetch = per_kernel(_counter_rows(glob.glob(os.path.join(fetch_dir, "*counter_collection.csv"))[0]))
+    write = per_kernel(_counter_rows(glob.glob(os.path.join(write_dir, "*counter_collection.csv"))[0]))
+    gib_kib = float(1 << 20)
+    cf = [v for v in fetch.get("__amd_rocclr_copyBuffer", []) if v > 0.25 * gib_kib]
+    cw = [v for v in write.get("__amd_rocclr_copyBuffer", []) if v > 0.5 * gib_kib]
+    f_fetch = gib_kib / (sum(cf) / len(cf))
+    f_write = gib_kib / (sum(cw) / len(cw))
+    out = ["# HBM traffic per launch: coupling cycle, 512x256 cells x 100 particles/cell, FP64", "",
+           "Commands (from the repository root, on one MI355X), one counter per run:", "",
+           "    " + PMC_CMDS[0], "    " + PMC_CMDS[1], "",
+           "Calibration: a 1 GiB device-to-device copy reads FETCH_SIZE = %.0f KiB and WRITE_SIZE = %.0f KiB, so"
+           % (gib_kib / f_fetch, gib_kib / f_write),
+           "bytes = %.3f x FETCH_SIZE + %.3f x WRITE_SIZE (KiB -> bytes x 1024)." % (f_fetch, f_write), "",
+           "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB per launch |", "|---|---|---|---|---|"]
+    per_id = {}
+    for name in sorted(fetch):
+        if not name.startswith(("void dsmc::", "dsmc::")) or name not in write:
+            continue
+        mf = sum(fetch[name]) / len(fetch[name])
+        mw = sum(write[name]) / len(write[name])
+        mb = (mf * f_fetch + mw * f_write) * 1024 / 1e6
+        out.append("| `%s` | %d | %.0f | %.0f | %.1f |" % (name, len(fetch[name]), mf, mw, mb))
+        for kid, pre in KERNEL_PREFIX.items():
+            if name.startswith(pre):
+                per_id.setdefault(kid, []).extend(
+                    [(a * f_fetch + b * f_write) * 1024 for a, b in zip(fetch[name], write[name])])
+    out.append("")
+    out.append("Per profiling id (all template variants, averaged over dispatches):")
+    out.append("")
+    for kid, v in sorted(per_id.items()):
+        out.append("traffic_bytes_per_launch %s: %.0f" % (kid, sum(v) / len(v)))
+    out.append("")
+    out.append("source_sha256: " + source_hash())
+    with open(TRAFFIC_SUMMARY, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("wrote", TRACE_SUMMARY, TRAFFIC_SUMMARY)
 
 
 def _parse():
@@ -52,9 +178,11 @@ def _parse():
     ap.add_argument("--steps", type=int, default=20, help="timed coupling cycles")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=4, help="coupling cycles the CPU oracle is timed on")
+    ap.add_argument("--cpu-cycles", type=int, default=8, help="coupling cycles the CPU oracle is timed on")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three plain 1 GiB device copies (reference for HBM byte counters)")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write the profiles/ summaries from rocprofv3 output directories and exit")
     return ap.parse_args()
 
 
@@ -89,6 +217,9 @@ def cpu_baseline(strip, cycles):
 
 def main():
     args = _parse()
+    if args.summarize:
+        summarize(*args.summarize)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the hot path here is a single-GPU build "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -163,7 +294,7 @@ def main():
         nb = per_p * st["n"] + per_c * ncells
         achieved = nb / (kernels[dom]["us_mean"] * 1e-6) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": stored_traffic(dom), "kernel": dom,
                 "bytes_per_launch": nb}
     step_bytes = 80.0 * value  # algorithmic floor of a particle step (read + write the state once)
     out = {
