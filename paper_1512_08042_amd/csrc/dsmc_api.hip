@@ -213,8 +213,8 @@ Layout make_layout(const dsmc_config &c)
     };
     L.cs0 = take((nc + 1) * 4);
     L.cs1 = take((nc + 1) * 4);
-    L.grp0 = take(NGRP * nc * 4);
-    L.grp1 = take(NGRP * nc * 4);
+    L.grp0 = take(GSTRIDE * nc * 4);
+    L.grp1 = take(GSTRIDE * nc * 4);
     L.countnew = take(nc * 4);
     L.farcnt = take(2 * nc * 4);
     L.blocksum = take(nblk * 4);

@@ -261,18 +261,9 @@ __device__ void tile_groups(const StepArgs &a, TileLds<TC, CH> &L, int ntc, int 
         if (t < ntc) {
             const int sc = source_cell(nx, a.geo().ny, L.tix[t], L.tiy[t], d);
             if (sc >= 0) {
-                // all ten group sizes of the source cell in one round of loads
-                const int32_t *g = a.grp_in() + (size_t)sc * NGRP;
-                int gv[NGRP];
-#pragma unroll
-                for (int e = 0; e < NGRP; ++e) gv[e] = g[e];
-                int before = 0;
-#pragma unroll
-                for (int e = 0; e < NDIR; ++e) {
-                    if (e < d) before += gv[e];
-                    if (e == d) n = gv[e];
-                }
-                src = a.cs_old()[sc] + before;
+                const int32_t *g = a.grp_in() + (size_t)sc * GSTRIDE + d;
+                src = g[0];
+                n = g[1] - g[0];
                 if (n > 0) s = sc;
             }
         }
@@ -392,15 +383,17 @@ __device__ __forceinline__ void ntc_chain(double *vx, double *vy, double *vz, co
 // v* address the tile's velocities (LDS or global), slot 0 = first of the tile
 template <int TC, int CH>
 __device__ __forceinline__ void tile_ntc(double *vx, double *vy, double *vz, TileLds<TC, CH> &L,
-                                         const NtcParams &P, int c0, int ntc, double &nbar, double &sig,
-                                         double &rem, unsigned long long &ncoll, unsigned long long &ncand)
+                                         const NtcParams &P, int c0, int ntc, bool own, double &nbar,
+                                         double &sig, double &rem, unsigned long long &ncoll,
+                                         unsigned long long &ncand)
 {
     constexpr int KC = NTC_ROUND / TC;
     const int lane = threadIdx.x;
     const int D0 = L.csn[0];
     long long M = 0;
     int s0 = 0;
-    if (lane < ntc) {
+    if (lane < TC) L.mc[lane] = 0;
+    if (own) {
         const int N = L.csn[lane + 1] - L.csn[lane];
         s0 = L.csn[lane] - D0;
         const double Nd = (double)N;
@@ -554,8 +547,8 @@ __device__ __forceinline__ void rank_chunk(const TileLds<TC, CH> &L, int32_t *kr
     }
 }
 
-// sizes of the tile cells' next-step groups (held by lane t * NGRP + d)
-// published, and their offsets inside each cell
+// offsets of the tile cells' next-step groups inside each cell (sizes held
+// by lane t * NGRP + d), published as absolute first slots with the cell end
 template <int TC, int CH>
 __device__ __forceinline__ void tile_group_offsets(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc, int run)
 {
@@ -567,8 +560,9 @@ __device__ __forceinline__ void tile_group_offsets(const StepArgs &a, TileLds<TC
         int ex = 0;
         for (int e = 0; e < d; ++e) ex += L.run[t * NGRP + e];
         L.excl[lane] = ex;
-        a.grp_out()[(size_t)c0 * NGRP + lane] = run;
+        a.grp_out()[(size_t)(c0 + t) * GSTRIDE + d] = L.csn[t] + ex;
     }
+    if (lane < ntc) a.grp_out()[(size_t)(c0 + lane) * GSTRIDE + NGRP] = L.csn[lane + 1];
     __syncthreads();
 }
 
@@ -585,8 +579,8 @@ __device__ __forceinline__ void tile_group_offsets(const StepArgs &a, TileLds<TC
 // STAGED tiles (at most 64*CH particles) are staged in LDS; larger ones run
 // the same steps on the tile's destination range in global memory.
 template <int TC, int CH, bool GATHER, bool MOVE, bool STAGED>
-__device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc, int nt, int n_old, double &nbar,
-                          double &sig, double &rem, bool mown, double mprev, double *mdst,
+__device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc, int nt, int n_old, bool own_ntc,
+                          double &nbar, double &sig, double &rem, bool mown, double mprev, double *mdst,
                           unsigned long long &ncoll, unsigned long long &ncand, int &walls, bool &limit)
 {
     const int lane = threadIdx.x;
@@ -657,7 +651,7 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
 
     // 2. collisions and 3. sample
     if (GATHER) {
-        tile_ntc<TC, CH>(s[2], s[3], s[4], L, a.N(), c0, ntc, nbar, sig, rem, ncoll, ncand);
+        tile_ntc<TC, CH>(s[2], s[3], s[4], L, a.N(), c0, ntc, own_ntc, nbar, sig, rem, ncoll, ncand);
         if (!STAGED) __threadfence();
         __syncthreads();
         if (a.sample) tile_sample<TC, CH>(s[2], s[3], s[4], L, ntc, mown, mprev, mdst);
@@ -743,11 +737,12 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a)
     }
     double nbar = 0.0, sig = 0.0, rem = 0.0;
     int nfin = 0;
-    if (GATHER && lane < ntc) {
+    if (GATHER && lane < ntc) nfin = a.farcnt_in()[c0 + lane];
+    const bool own_ntc = GATHER && lane < ntc;  // this lane runs the collisions of tile cell `lane`
+    if (own_ntc) {
         nbar = a.K().nbar[c0 + lane];
         sig = a.K().sigcmax[c0 + lane];
         rem = a.K().rem[c0 + lane];
-        nfin = a.farcnt_in()[c0 + lane];
     }
     const int team = lane / T, lt = lane - team * T, mslot = lt / SPAN;
     const bool mown = GATHER && a.sample && team < ntc && (lt % SPAN) == 0 && mslot < NMOM;
@@ -766,13 +761,13 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a)
     int walls = 0;
     bool limit = false;
     if (nt <= TileLds<TC, CH>::CAP)
-        tile_body<TC, CH, GATHER, MOVE, true>(a, L, c0, ntc, nt, n_old, nbar, sig, rem, mown, mprev, mdst, ncoll,
-                                              ncand, walls, limit);
+        tile_body<TC, CH, GATHER, MOVE, true>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev, mdst,
+                                              ncoll, ncand, walls, limit);
     else
-        tile_body<TC, CH, GATHER, MOVE, false>(a, L, c0, ntc, nt, n_old, nbar, sig, rem, mown, mprev, mdst, ncoll,
-                                               ncand, walls, limit);
+        tile_body<TC, CH, GATHER, MOVE, false>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev,
+                                               mdst, ncoll, ncand, walls, limit);
 
-    if (GATHER && lane < ntc) {
+    if (own_ntc) {
         a.K().nbar[c0 + lane] = nbar;
         a.K().sigcmax[c0 + lane] = sig;
         a.K().rem[c0 + lane] = rem;
@@ -818,7 +813,7 @@ __global__ __launch_bounds__(256) void k_cell_count(CellArgs a)
 #pragma unroll
         for (int d = 0; d < NDIR; ++d) {
             const int src = source_cell(a.nx, a.ny, cix, ciy, d);
-            if (src >= 0) total += a.grp[(size_t)src * NGRP + d];
+            if (src >= 0) total += a.grp[(size_t)src * GSTRIDE + d + 1] - a.grp[(size_t)src * GSTRIDE + d];
         }
         total += a.farcnt[c];
         a.countnew[c] = total;

@@ -16,8 +16,10 @@ struct NtcParams {
 
 // Per-cell partition of a moved state: inside every old cell's slot range
 // the particles are grouped by direction code 0..9 (the 9 near moves, then
-// long jumps), each group in slot order; grp[c][d] holds the group sizes.
+// long jumps), each group in slot order; grp[c][d] holds the first slot of
+// group d and grp[c][NGRP] the end of the cell's range.
 constexpr int NGRP = NDIR + 1;
+constexpr int GSTRIDE = NGRP + 1;  // per cell: first slot of each group, then the cell end
 
 // Everything the step kernels need that stays fixed for a context; kept in
 // device memory (inside the workspace) so that a launch passes a pointer
@@ -25,7 +27,7 @@ constexpr int NGRP = NDIR + 1;
 struct TileConst {
     double *st[2][5];        // the two state buffers (x, y, vx, vy, vz)
     int32_t *cs[2];          // their cell_start
-    int32_t *grp[2];         // [ncells][NGRP] group sizes, by step parity
+    int32_t *grp[2];         // [ncells][GSTRIDE] first slot of every group and the cell end, by step parity
     int32_t *far[2];         // long-jump lists, by step parity
     int32_t *farcnt[2];      // [ncells] long jumps arriving per cell, by step parity
     double *scr;             // [capacity] scratch of oversized tiles
@@ -104,7 +106,7 @@ struct StepArgs {
 };
 
 struct CellArgs {
-    const int32_t *grp;      // [ncells][NGRP] group sizes of the moved state
+    const int32_t *grp;      // [ncells][GSTRIDE] group starts and cell end of the moved state
     const int32_t *farcnt;   // [ncells] long jumps arriving per cell
     int32_t *countnew;
     int32_t *blocksum;
