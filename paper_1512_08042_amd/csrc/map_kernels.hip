@@ -135,30 +135,6 @@ __device__ __forceinline__ double grad_G(const double *p, double x, double y)
     return 1.0 + t2 / 2.0 + t3 / 6.0;
 }
 
-// Table 1 steps 4-5 for new particle k of cell c in reseed event e: Box-
-// Muller tries from counters (2t, c, e, RESEED|k), accepted when
-// C R <= G(xi) with R from counters (2t+1, c, e, RESEED|k).  After
-// max_tries rejections the last try is kept and `limit` is raised.
-__device__ __forceinline__ void ar_sample(uint32_t k0, uint32_t k1, const double *prm, uint32_t c, uint32_t e, uint32_t k,
-                                          int max_tries, double &z0, double &z1, bool &limit)
-{
-    const double C = prm[11];
-    long long t = 0;
-    for (;;) {
-        const U4 A = draw(k0, k1, (uint32_t)(2 * t), c, e, TAG_RESEED, k);
-        const U4 B = draw(k0, k1, (uint32_t)(2 * t + 1), c, e, TAG_RESEED, k);
-        box_muller(u53(A.x, A.y), u53(A.z, A.w), z0, z1);
-        const double R = u53(B.x, B.y);
-        const double G = grad_G(prm, z0, z1);
-        t += 1;
-        if (C * R <= G) break;
-        if (t >= max_tries) {
-            limit = true;
-            break;
-        }
-    }
-}
-
 // one thread per listed cell: mark the cell, Table 1 steps 1-3, and the
 // number of new particles floor(rho ppc + R) (mass conservation at the
 // coupling site), R from counters (0, c, e, RESEED_N)
@@ -285,20 +261,56 @@ __global__ __launch_bounds__(256) void k_reseed_gen(ReseedArgs a)
     double prm[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) prm[k] = a.prm[(size_t)i * 12 + k];
+    const double C = prm[11];
     const int ix = c % a.nx, iy = c / a.nx;
     bool limit = false;
-    for (int k = lane; k < nn; k += 64) {
-        double z0, z1, zz0, zz1;
-        ar_sample(a.k0, a.k1, prm, (uint32_t)c, a.event, (uint32_t)k, a.ar_max_tries, z0, z1, limit);
-        const U4 P = draw(a.k0, a.k1, 0u, (uint32_t)c, a.event, TAG_RESEED_POS, (uint32_t)k);
-        const U4 V = draw(a.k0, a.k1, 1u, (uint32_t)c, a.event, TAG_RESEED_POS, (uint32_t)k);
-        box_muller(u53(V.x, V.y), u53(V.z, V.w), zz0, zz1);
-        const int q = d0 + k;
-        a.out[0][q] = inside_cell(ix, u53(P.x, P.y));
-        a.out[1][q] = inside_cell(iy, u53(P.z, P.w));
-        a.out[2][q] = a.s_th * (z0 + prm[1]);
-        a.out[3][q] = a.s_th * (z1 + prm[2]);
-        a.out[4][q] = a.s_th * zz0;
+    // Table 1 steps 4-5 for new particle k of the cell: Box-Muller tries
+    // from counters (2t, c, e, RESEED|k), accepted when C R <= G(xi) with R
+    // from counters (2t+1, c, e, RESEED|k); after ar_max_tries rejections the
+    // last try is kept and the AR-limit status bit is raised.  Every lane
+    // samples one particle at a time, one try per pass; a lane whose
+    // particle is done takes the next unassigned ordinal, so the wave's
+    // passes follow the mean number of tries (about C) rather than the
+    // slowest lane's.  The draws are keyed by the ordinal, so the result does
+    // not depend on which lane samples which particle.
+    int k = lane;       // ordinal of this lane's particle
+    long long t = 0;    // its tries so far
+    int next = 64;      // first ordinal not yet assigned
+    while (ballot64(k < nn) != 0) {
+        bool fin = false;
+        if (k < nn) {
+            const U4 A = draw(a.k0, a.k1, (uint32_t)(2 * t), (uint32_t)c, a.event, TAG_RESEED, (uint32_t)k);
+            const U4 B = draw(a.k0, a.k1, (uint32_t)(2 * t + 1), (uint32_t)c, a.event, TAG_RESEED, (uint32_t)k);
+            double z0, z1;
+            box_muller(u53(A.x, A.y), u53(A.z, A.w), z0, z1);
+            const double R = u53(B.x, B.y);
+            const double G = grad_G(prm, z0, z1);
+            t += 1;
+            if (C * R <= G) {
+                fin = true;
+            } else if (t >= a.ar_max_tries) {
+                limit = true;
+                fin = true;
+            }
+            if (fin) {
+                double zz0, zz1;
+                const U4 Pp = draw(a.k0, a.k1, 0u, (uint32_t)c, a.event, TAG_RESEED_POS, (uint32_t)k);
+                const U4 V = draw(a.k0, a.k1, 1u, (uint32_t)c, a.event, TAG_RESEED_POS, (uint32_t)k);
+                box_muller(u53(V.x, V.y), u53(V.z, V.w), zz0, zz1);
+                const int q = d0 + k;
+                a.out[0][q] = inside_cell(ix, u53(Pp.x, Pp.y));
+                a.out[1][q] = inside_cell(iy, u53(Pp.z, Pp.w));
+                a.out[2][q] = a.s_th * (z0 + prm[1]);
+                a.out[3][q] = a.s_th * (z1 + prm[2]);
+                a.out[4][q] = a.s_th * zz0;
+            }
+        }
+        const uint64_t m = ballot64(fin);
+        if (fin) {
+            k = next + rank_below(m);
+            t = 0;
+        }
+        next += __popcll(m);
     }
     if (__ballot(limit) != 0 && lane == 0) atomicOr(&a.ctr->status, ST_AR_LIMIT);
 }

@@ -246,6 +246,27 @@ __device__ void tile_far_gather(const StepArgs &a, const TileLds<TC, CH> &L, dou
     }
 }
 
+// near group (source cell, size, first source slot) of lane t * NDIR + d:
+// move d into tile cell t; the partitioned state makes it the run
+// grp[s][d] .. grp[s][d+1] of source cell s
+template <int TC>
+__device__ __forceinline__ void tile_raw_group(const StepArgs &a, int c0, int ntc, int lane, int &s, int &n, int &src)
+{
+    s = -1;
+    n = 0;
+    src = 0;
+    if (lane >= TC * NDIR) return;
+    const int t = lane / NDIR, d = lane - t * NDIR;
+    if (t >= ntc) return;
+    const int nx = a.K().G.nx, c = c0 + t, ciy = c / nx, cix = c - ciy * nx;
+    const int sc = source_cell(nx, a.K().G.ny, cix, ciy, d);
+    if (sc < 0) return;
+    const int32_t *g = a.grp_in() + (size_t)sc * GSTRIDE + d;
+    src = g[0];
+    n = g[1] - g[0];
+    if (n > 0) s = sc;
+}
+
 // The groups arriving in every cell of the tile, in the order of the stable
 // sort: by source cell, each group in source-slot order.  The state read
 // here keeps every old cell's particles partitioned by move direction, so a
@@ -255,23 +276,7 @@ template <int TC, int CH>
 __device__ void tile_groups(const StepArgs &a, TileLds<TC, CH> &L, int ntc, int nfin)
 {
     const int lane = threadIdx.x, nx = a.geo().nx;
-    if (lane < TC * NDIR) {
-        const int t = lane / NDIR, d = lane - t * NDIR;
-        int s = -1, n = 0, src = 0;
-        if (t < ntc) {
-            const int sc = source_cell(nx, a.geo().ny, L.tix[t], L.tiy[t], d);
-            if (sc >= 0) {
-                const int32_t *g = a.grp_in() + (size_t)sc * GSTRIDE + d;
-                src = g[0];
-                n = g[1] - g[0];
-                if (n > 0) s = sc;
-            }
-        }
-        L.raw[0][lane] = s;
-        L.raw[1][lane] = n;
-        L.raw[2][lane] = src;
-    }
-    __syncthreads();
+    // L.raw holds the near groups (filled with the tile's other loads)
     if (lane < TC * NDIR) {
         const int t = lane / NDIR, d = lane - t * NDIR;
         const int s = L.raw[0][lane];
@@ -752,6 +757,13 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a)
     const int n_old = GATHER ? a.cs_old()[nc] : 0;
     unsigned long long *const tst = a.K().tstat + 3 * (size_t)blockIdx.x + (lane < 3 ? lane : 0);
     const unsigned long long tprev = lane < 3 ? *tst : 0ull;
+    if (GATHER && lane < TC * NDIR) {
+        int s, n, src;
+        tile_raw_group<TC>(a, c0, ntc, lane, s, n, src);
+        L.raw[0][lane] = s;
+        L.raw[1][lane] = n;
+        L.raw[2][lane] = src;
+    }
     __syncthreads();
     if (GATHER) tile_groups<TC, CH>(a, L, ntc, nfin);
     const int D0 = L.csn[0];
