@@ -86,20 +86,24 @@ typedef struct dsmc_config {
     uint64_t seed;         /* Philox key */
     int32_t ar_max_tries;  /* acceptance-rejection try limit per particle (<= 0: 65536) */
     int32_t far_capacity;  /* long-jump list entries per step (<= 0: min(capacity, 65536)) */
+    int32_t state_bits;    /* particle state precision: 64 (or 0) FP64; 32 FP32 storage with FP64
+                              arithmetic (every write of a particle value rounds to the nearest float) */
+    int32_t reserved;      /* 0 */
 } dsmc_config;
 
 typedef struct dsmc_sizes {
     int64_t ncells;          /* nx * ny */
     int64_t capacity;        /* particles per state array */
-    size_t state_array_bytes; /* bytes of each of the 10 state arrays (capacity * 8) */
+    size_t state_array_bytes; /* bytes of each of the 10 state arrays (capacity * 8, or * 4 for FP32 state) */
     size_t workspace_bytes;  /* bytes of the single workspace buffer */
 } dsmc_sizes;
 
 typedef struct dsmc_buffers {
     /* two structure-of-arrays particle buffers, [buffer][x, y, vx, vy, vz],
-     * each array `capacity` doubles of device memory; the library sorts from
-     * one into the other every step (see dsmc_get_views for which is current) */
-    double *state[2][5];
+     * each array `capacity` elements of device memory (double, or float when
+     * state_bits is 32); the library sorts from one into the other every step
+     * (see dsmc_get_views for which is current) */
+    void *state[2][5];
     void *workspace;        /* device memory, >= dsmc_sizes.workspace_bytes, 256-byte aligned */
     size_t workspace_bytes;
 } dsmc_buffers;

@@ -117,7 +117,13 @@ typedef struct {
     int64_t nsamples, step, reseed_events;
     int64_t ncoll, ncand, nwall;
     uint32_t status;
+    int32_t state32;                    /* 1: particle state stored in FP32 */
 } or_sim;
+
+/* Stored particle values: with FP32 state every value written to the
+ * particle arrays is rounded to the nearest float; the arithmetic itself is
+ * FP64 on the stored values. */
+static double stv(const or_sim *s, double v) { return s->state32 ? (double)(float)v : v; }
 
 static void *xalloc(size_t n) { void *p = calloc(n ? n : 1, 1); return p; }
 
@@ -219,6 +225,9 @@ static void sort_by_cell(or_sim *s)
  * fixed number of computational molecules in each cell), uniform in the cell,
  * velocities from the Maxwellian at the reference temperature drawn by
  * Box-Muller. Particle g = c*ppc + k of cell c uses counters (d, g, 0, INIT). */
+/* FP32 particle state (1) or FP64 (0); set before the state is first written */
+void or_set_state32(or_sim *s, int32_t on) { s->state32 = on ? 1 : 0; }
+
 void or_init_maxwell(or_sim *s)
 {
     int64_t n = (int64_t)s->ncells * s->ppc;
@@ -234,13 +243,13 @@ void or_init_maxwell(or_sim *s)
             draw(s->seed, 0u, (uint32_t)gi, 0u, OR_TAG_INIT, 0u, a);
             draw(s->seed, 1u, (uint32_t)gi, 0u, OR_TAG_INIT, 0u, b);
             draw(s->seed, 2u, (uint32_t)gi, 0u, OR_TAG_INIT, 0u, e);
-            s->x[gi] = inside(ix, or_u53(a[0], a[1]));
-            s->y[gi] = inside(iy, or_u53(a[2], a[3]));
             or_box_muller(or_u53(b[0], b[1]), or_u53(b[2], b[3]), z);
             or_box_muller(or_u53(e[0], e[1]), or_u53(e[2], e[3]), zz);
-            s->vx[gi] = s->s_th * z[0];
-            s->vy[gi] = s->s_th * z[1];
-            s->vz[gi] = s->s_th * zz[0];
+            s->x[gi] = stv(s, inside(ix, or_u53(a[0], a[1])));
+            s->y[gi] = stv(s, inside(iy, or_u53(a[2], a[3])));
+            s->vx[gi] = stv(s, s->s_th * z[0]);
+            s->vy[gi] = stv(s, s->s_th * z[1]);
+            s->vz[gi] = stv(s, s->s_th * zz[0]);
         }
     }
     for (int32_t c = 0; c <= s->ncells; ++c) {
@@ -258,6 +267,10 @@ int or_load(or_sim *s, int64_t n, const double *x, const double *y, const double
     memcpy(s->x, x, (size_t)n * 8); memcpy(s->y, y, (size_t)n * 8);
     memcpy(s->vx, vx, (size_t)n * 8); memcpy(s->vy, vy, (size_t)n * 8);
     memcpy(s->vz, vz, (size_t)n * 8);
+    for (int64_t p = 0; p < n; ++p) {
+        s->x[p] = stv(s, s->x[p]); s->y[p] = stv(s, s->y[p]);
+        s->vx[p] = stv(s, s->vx[p]); s->vy[p] = stv(s, s->vy[p]); s->vz[p] = stv(s, s->vz[p]);
+    }
     sort_by_cell(s);
     return 0;
 }
@@ -320,7 +333,7 @@ static void move_one(or_sim *s, int64_t p, double *px, double *py, double *pvx, 
     double xw = x - Lx * floor(x / Lx);
     if (xw < 0.0) xw = xw + Lx;
     if (xw >= Lx) xw = 0.0;
-    *px = xw; *py = y; *pvx = vx; *pvy = vy; *pvz = vz;
+    *px = stv(s, xw); *py = stv(s, y); *pvx = stv(s, vx); *pvy = stv(s, vy); *pvz = stv(s, vz);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -373,8 +386,8 @@ static void collide_cell(or_sim *s, int32_t c)
             double mx = 0.5 * (s->vx[pi] + s->vx[pj]);
             double my = 0.5 * (s->vy[pi] + s->vy[pj]);
             double mz = 0.5 * (s->vz[pi] + s->vz[pj]);
-            s->vx[pi] = mx + 0.5 * rx; s->vy[pi] = my + 0.5 * ry; s->vz[pi] = mz + 0.5 * rz;
-            s->vx[pj] = mx - 0.5 * rx; s->vy[pj] = my - 0.5 * ry; s->vz[pj] = mz - 0.5 * rz;
+            s->vx[pi] = stv(s, mx + 0.5 * rx); s->vy[pi] = stv(s, my + 0.5 * ry); s->vz[pi] = stv(s, mz + 0.5 * rz);
+            s->vx[pj] = stv(s, mx - 0.5 * rx); s->vy[pj] = stv(s, my - 0.5 * ry); s->vz[pj] = stv(s, mz - 0.5 * rz);
             s->ncoll += 1;
         }
     }
@@ -700,11 +713,11 @@ int or_lb2dsmc(or_sim *s, int32_t Q, int32_t order, const double *xi, const doub
             draw(s->seed, 0u, (uint32_t)c, e, OR_TAG_RESEED_POS, (uint32_t)k, a);
             draw(s->seed, 1u, (uint32_t)c, e, OR_TAG_RESEED_POS, (uint32_t)k, b);
             or_box_muller(or_u53(b[0], b[1]), or_u53(b[2], b[3]), zz);
-            s->tx[d] = inside(ix, or_u53(a[0], a[1]));
-            s->ty[d] = inside(iy, or_u53(a[2], a[3]));
-            s->tvx[d] = s->s_th * (z[0] + pr[1]);
-            s->tvy[d] = s->s_th * (z[1] + pr[2]);
-            s->tvz[d] = s->s_th * zz[0];
+            s->tx[d] = stv(s, inside(ix, or_u53(a[0], a[1])));
+            s->ty[d] = stv(s, inside(iy, or_u53(a[2], a[3])));
+            s->tvx[d] = stv(s, s->s_th * (z[0] + pr[1]));
+            s->tvy[d] = stv(s, s->s_th * (z[1] + pr[2]));
+            s->tvz[d] = stv(s, s->s_th * zz[0]);
         }
     }
     ncs[nc] = (int32_t)d;

@@ -62,6 +62,7 @@ def lib():
         d, i32, i64, u64, u32 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32
         L.or_create.restype = P
         L.or_create.argtypes = [i32, i32, i32, i32, i64, d, d, d, d, d, u64, i32]
+        L.or_set_state32.argtypes = [P, i32]
         L.or_destroy.argtypes = [P]
         L.or_init_maxwell.argtypes = [P]
         L.or_load.argtypes = [P, i64, P, P, P, P, P]
@@ -296,7 +297,9 @@ def lbm_tau(kn: float, ny: int, r: float) -> float:
 # --------------------------------------------------------------------------
 class Sim:
     def __init__(self, nx, ny, ppc, kn, dt=None, g=0.0, kT=1.0, sigcr0=6.0, seed=1, capacity=None,
-                 nbar_mode=0, ar_max_tries=65536):
+                 nbar_mode=0, ar_max_tries=65536, state32=False):
+        """state32: particle values are stored in FP32 (every write rounds to the
+        nearest float); the arithmetic stays FP64."""
         self.nx, self.ny, self.ppc = int(nx), int(ny), int(ppc)
         self.ncells = self.nx * self.ny
         self.kn, self.kT, self.g = float(kn), float(kT), float(g)
@@ -307,6 +310,8 @@ class Sim:
                                   self.g, self.kT, float(sigcr0), self.seed, int(ar_max_tries))
         if not self._h:
             raise ValueError("oracle rejected the configuration")
+        self.state32 = bool(state32)
+        lib().or_set_state32(self._h, 1 if self.state32 else 0)
 
     def __del__(self):
         h = getattr(self, "_h", None)

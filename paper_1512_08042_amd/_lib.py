@@ -26,7 +26,8 @@ EXPORTS = ("dsmc_query_sizes", "dsmc_init", "dsmc_step", "dsmc_sample_moments", 
 class Config(ctypes.Structure):
     _fields_ = [("nx", c_i32), ("ny", c_i32), ("ppc", c_i32), ("nbar_mode", c_i32), ("capacity", c_i64),
                 ("kn", c_d), ("dt", c_d), ("body_force_x", c_d), ("kT_over_m", c_d), ("sigcr_max0", c_d),
-                ("seed", c_u64), ("ar_max_tries", c_i32), ("far_capacity", c_i32)]
+                ("seed", c_u64), ("ar_max_tries", c_i32), ("far_capacity", c_i32), ("state_bits", c_i32),
+                ("reserved", c_i32)]
 
 
 class Sizes(ctypes.Structure):

@@ -48,6 +48,7 @@ class ChannelConfig:
     nbar_mode: int = 0
     ar_max_tries: int = 0
     far_capacity: int = 0
+    state_bits: int = 64  # 64: FP64 particle state; 32: FP32 storage, FP64 arithmetic
 
     def resolved(self) -> "ChannelConfig":
         c = ChannelConfig(**self.__dict__)

@@ -185,8 +185,11 @@ bool valid_config(const dsmc_config *c)
     if (!std::isfinite(c->kn) || !std::isfinite(c->dt) || !std::isfinite(c->body_force_x)) return false;
     if (!std::isfinite(c->kT_over_m) || !std::isfinite(c->sigcr_max0)) return false;
     if (c->nbar_mode != 0 && c->nbar_mode != 1) return false;
+    if (c->state_bits != 0 && c->state_bits != 32 && c->state_bits != 64) return false;
     return true;
 }
+
+bool state32(const dsmc_config &c) { return c.state_bits == 32; }
 
 int far_cap_of(const dsmc_config &c)
 {
@@ -244,7 +247,7 @@ struct ProfRec {
 
 struct dsmc_ctx {
     dsmc_config cfg;
-    double *st[2][5];
+    void *st[2][5];  // double, or float when state32
     int32_t *cs[2];
     int32_t *grp[2], *countnew, *farcnt, *blocksum, *far[2], *mark, *nnew, *perm;
     double *nbar, *sigcmax, *rem, *mom, *prm;
@@ -379,23 +382,31 @@ int upload_tile_const(dsmc_ctx *x, hipStream_t s)
 // one launch of the tile kernels: kind 0 = k_classify, 1 = k_step
 void launch_tiles(const dsmc_ctx *x, int kind, bool move, unsigned ntiles, hipStream_t s, const StepArgs &a)
 {
-#define DSMC_LAUNCH(TC, CH)                                          \
+#define DSMC_LAUNCH(TC, CH, S)                                       \
     do {                                                             \
         if (kind == 0)                                               \
-            k_classify<TC, CH><<<ntiles, 64, 0, s>>>(a);             \
+            k_classify<TC, CH, S><<<ntiles, 64, 0, s>>>(a);          \
         else if (move)                                               \
-            k_step<TC, CH, true><<<ntiles, 64, 0, s>>>(a);           \
+            k_step<TC, CH, true, S><<<ntiles, 64, 0, s>>>(a);        \
         else                                                         \
-            k_step<TC, CH, false><<<ntiles, 64, 0, s>>>(a);          \
+            k_step<TC, CH, false, S><<<ntiles, 64, 0, s>>>(a);       \
     } while (0)
-    if (x->tc == 4)
-        DSMC_LAUNCH(4, 4);
-    else if (x->tc == 2)
-        DSMC_LAUNCH(2, 4);
-    else if (x->ch == 4)
-        DSMC_LAUNCH(1, 4);
+#define DSMC_LAUNCH_SHAPE(S)          \
+    do {                              \
+        if (x->tc == 4)               \
+            DSMC_LAUNCH(4, 4, S);     \
+        else if (x->tc == 2)          \
+            DSMC_LAUNCH(2, 4, S);     \
+        else if (x->ch == 4)          \
+            DSMC_LAUNCH(1, 4, S);     \
+        else                          \
+            DSMC_LAUNCH(1, 8, S);     \
+    } while (0)
+    if (state32(x->cfg))
+        DSMC_LAUNCH_SHAPE(float);
     else
-        DSMC_LAUNCH(1, 8);
+        DSMC_LAUNCH_SHAPE(double);
+#undef DSMC_LAUNCH_SHAPE
 #undef DSMC_LAUNCH
 }
 
@@ -453,7 +464,7 @@ int dsmc_query_sizes(const dsmc_config *cfg, dsmc_sizes *out)
     const Layout L = make_layout(*cfg);
     out->ncells = (int64_t)cfg->nx * cfg->ny;
     out->capacity = cfg->capacity;
-    out->state_array_bytes = (size_t)cfg->capacity * 8;
+    out->state_array_bytes = (size_t)cfg->capacity * (state32(*cfg) ? 4 : 8);
     out->workspace_bytes = L.total;
     return DSMC_OK;
 }
@@ -566,7 +577,10 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
         a.k1 = (uint32_t)(cfg->seed >> 32);
         const size_t n = (size_t)ncells * cfg->ppc;
         const size_t nthreads = n > (size_t)ncells + 1 ? n : (size_t)ncells + 1;
-        k_init_maxwell<<<grid_threads(nthreads), 256, 0, s>>>(a);
+        if (state32(*cfg))
+            k_init_maxwell<float><<<grid_threads(nthreads), 256, 0, s>>>(a);
+        else
+            k_init_maxwell<double><<<grid_threads(nthreads), 256, 0, s>>>(a);
         if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
         x->cur = 0;
     } else if (rc == DSMC_OK) {
@@ -586,14 +600,20 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
         {
             rc = fill_i32(x->countnew, (size_t)ncells, 0, s);
             if (rc == DSMC_OK && n_load > 0) {
-                k_adopt_count<<<grid_threads((size_t)n_load), 256, 0, s>>>(a);
+                if (state32(*cfg))
+                    k_adopt_count<float><<<grid_threads((size_t)n_load), 256, 0, s>>>(a);
+                else
+                    k_adopt_count<double><<<grid_threads((size_t)n_load), 256, 0, s>>>(a);
                 if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
             }
             if (rc == DSMC_OK) rc = scan_counts(x, x->countnew, x->cs[1], s);
             if (rc == DSMC_OK && n_load > 0) {
                 k_adopt_place<<<grid_threads((size_t)n_load), 256, 0, s>>>(a);
                 k_adopt_sortcell<<<grid_threads((size_t)ncells), 256, 0, s>>>(a);
-                k_adopt_gather<<<grid_threads((size_t)n_load), 256, 0, s>>>(a);
+                if (state32(*cfg))
+                    k_adopt_gather<float><<<grid_threads((size_t)n_load), 256, 0, s>>>(a);
+                else
+                    k_adopt_gather<double><<<grid_threads((size_t)n_load), 256, 0, s>>>(a);
                 if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
             }
             if (rc == DSMC_OK) rc = fill_f64(x->nbar, (size_t)ncells, 0.0, s);
@@ -755,8 +775,14 @@ int map_lbm_to_dsmc(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f
         k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, x->cs[nxt], x->ncells, x->ctr, -1);
         k_block_scan<<<x->nblk, 256, 0, s>>>(x->countnew, x->ncells, x->blocksum, x->cs[nxt]);
         k_reseed_check<<<1, 64, 0, s>>>(a);
-        k_reseed_copy<<<(unsigned)((x->ncells + RC_TILE - 1) / RC_TILE), 256, 0, s>>>(a);
-        if (nsel > 0) k_reseed_gen<<<grid_cells_wave(nsel), 256, 0, s>>>(a);
+        const unsigned gcopy = (unsigned)((x->ncells + RC_TILE - 1) / RC_TILE);
+        if (state32(x->cfg)) {
+            k_reseed_copy<float><<<gcopy, 256, 0, s>>>(a);
+            if (nsel > 0) k_reseed_gen<float><<<grid_cells_wave(nsel), 256, 0, s>>>(a);
+        } else {
+            k_reseed_copy<double><<<gcopy, 256, 0, s>>>(a);
+            if (nsel > 0) k_reseed_gen<double><<<grid_cells_wave(nsel), 256, 0, s>>>(a);
+        }
         k_reseed_unmark<<<gsel, 256, 0, s>>>(a);
     }));
     x->cur = nxt;

@@ -214,6 +214,7 @@ __global__ void k_reseed_check(ReseedArgs a)
 // restored as well).
 constexpr int RC_TILE = 64;
 
+template <class S>
 __global__ __launch_bounds__(256) void k_reseed_copy(ReseedArgs a)
 {
     __shared__ int s_old[RC_TILE + 1], s_new[RC_TILE + 1], s_keep[RC_TILE];
@@ -243,12 +244,15 @@ __global__ __launch_bounds__(256) void k_reseed_copy(ReseedArgs a)
         if (!s_keep[lo]) continue;
         const int q = s_new[lo] + (p - s_old[lo]);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) a.out[k][q] = a.in[k][p];
+        for (int k = 0; k < 5; ++k) ((S *)a.out[k])[q] = ((const S *)a.in[k])[p];
     }
 }
+template __global__ void k_reseed_copy<double>(ReseedArgs);
+template __global__ void k_reseed_copy<float>(ReseedArgs);
 
 // Listed cells: one wave per listed cell generates its new particles
 // (Table 1 steps 4-6) into the cell's new slots.
+template <class S>
 __global__ __launch_bounds__(256) void k_reseed_gen(ReseedArgs a)
 {
     const int lane = threadIdx.x & 63;
@@ -298,11 +302,11 @@ __global__ __launch_bounds__(256) void k_reseed_gen(ReseedArgs a)
                 const U4 V = draw(a.k0, a.k1, 1u, (uint32_t)c, a.event, TAG_RESEED_POS, (uint32_t)k);
                 box_muller(u53(V.x, V.y), u53(V.z, V.w), zz0, zz1);
                 const int q = d0 + k;
-                a.out[0][q] = inside_cell(ix, u53(Pp.x, Pp.y));
-                a.out[1][q] = inside_cell(iy, u53(Pp.z, Pp.w));
-                a.out[2][q] = a.s_th * (z0 + prm[1]);
-                a.out[3][q] = a.s_th * (z1 + prm[2]);
-                a.out[4][q] = a.s_th * zz0;
+                ((S *)a.out[0])[q] = (S)inside_cell(ix, u53(Pp.x, Pp.y));
+                ((S *)a.out[1])[q] = (S)inside_cell(iy, u53(Pp.z, Pp.w));
+                ((S *)a.out[2])[q] = (S)(a.s_th * (z0 + prm[1]));
+                ((S *)a.out[3])[q] = (S)(a.s_th * (z1 + prm[2]));
+                ((S *)a.out[4])[q] = (S)(a.s_th * zz0);
             }
         }
         const uint64_t m = ballot64(fin);
@@ -314,6 +318,9 @@ __global__ __launch_bounds__(256) void k_reseed_gen(ReseedArgs a)
     }
     if (__ballot(limit) != 0 && lane == 0) atomicOr(&a.ctr->status, ST_AR_LIMIT);
 }
+
+template __global__ void k_reseed_gen<double>(ReseedArgs);
+template __global__ void k_reseed_gen<float>(ReseedArgs);
 
 __global__ __launch_bounds__(256) void k_reseed_unmark(ReseedArgs a)
 {

@@ -143,10 +143,10 @@ __device__ __forceinline__ void record_far(int32_t *far, int32_t *farcnt, Counte
 // ---- tiles of cells, one wave each ------------------------------------------------
 constexpr int NTC_ROUND = 32;  // NTC candidates drawn per round (all cells of a tile)
 
-template <int TC, int CH>
+template <int TC, int CH, class S>
 struct TileLds {
     static constexpr int CAP = 64 * CH;
-    double v[5][CAP];              // x, y, vx, vy, vz of the tile's particles, in new-slot order
+    S v[5][CAP];                   // x, y, vx, vy, vz of the tile's particles (stored precision), in new-slot order
     int32_t kr[CAP];               // next-step group (low 6 bits) and rank inside it, per slot
     double dr[5][NTC_ROUND];       // one round of NTC draws: R, cos(theta), sin(theta), cos(phi), sin(phi)
     int32_t di[2][NTC_ROUND];      // ... and the candidate pairs (i, j)
@@ -165,8 +165,8 @@ struct TileLds {
 };
 
 // cell (0 .. ntc-1) of tile slot i (0 <= i < nt)
-template <int TC, int CH>
-__device__ __forceinline__ int tile_cell(const TileLds<TC, CH> &L, int ntc, int D0, int i)
+template <int TC, int CH, class S>
+__device__ __forceinline__ int tile_cell(const TileLds<TC, CH, S> &L, int ntc, int D0, int i)
 {
     int t = 0;
 #pragma unroll
@@ -176,8 +176,8 @@ __device__ __forceinline__ int tile_cell(const TileLds<TC, CH> &L, int ntc, int 
 
 // source slot of the particle that the sort puts at offset r of tile cell t
 // when a near group holds that offset; -1 otherwise (a long jump's slot)
-template <int TC, int CH>
-__device__ __forceinline__ int tile_source(const TileLds<TC, CH> &L, int t, int r)
+template <int TC, int CH, class S>
+__device__ __forceinline__ int tile_source(const TileLds<TC, CH, S> &L, int t, int r)
 {
     // entries ng .. NDIR-1 of the table are padding (start INT_MAX, size 0)
     int k = 0;
@@ -190,8 +190,8 @@ __device__ __forceinline__ int tile_source(const TileLds<TC, CH> &L, int t, int 
 // Long jumps arriving in tile cell t (rare): every near group is preceded
 // in the sort by the long jumps from smaller source cells; counts them and
 // shifts the group starts.
-template <int TC, int CH>
-__device__ void tile_far_shift(const StepArgs &a, TileLds<TC, CH> &L, int t, int c, int nfin)
+template <int TC, int CH, class S>
+__device__ void tile_far_shift(const StepArgs &a, TileLds<TC, CH, S> &L, int t, int c, int nfin)
 {
     const uint32_t nf = min(a.K().ctr->nfar[a.far_in_slot()], (uint32_t)a.K().far_cap);
     const int ng = L.ng[t];
@@ -217,8 +217,8 @@ __device__ void tile_far_shift(const StepArgs &a, TileLds<TC, CH> &L, int t, int
 // Stages the long jumps arriving in the tile at their sorted slots: after
 // the near groups of smaller source cells and the long jumps of smaller
 // (source cell, source slot).  s[k] address the tile's stage.
-template <int TC, int CH>
-__device__ void tile_far_gather(const StepArgs &a, const TileLds<TC, CH> &L, double *const *s, int c0, int ntc,
+template <int TC, int CH, class S>
+__device__ void tile_far_gather(const StepArgs &a, const TileLds<TC, CH, S> &L, S *const *s, int c0, int ntc,
                                 int n_old)
 {
     const uint32_t nf = min(a.K().ctr->nfar[a.far_in_slot()], (uint32_t)a.K().far_cap);
@@ -242,7 +242,7 @@ __device__ void tile_far_gather(const StepArgs &a, const TileLds<TC, CH> &L, dou
             continue;
         }
 #pragma unroll
-        for (int k = 0; k < 5; ++k) s[k][slot] = a.in(k)[q];
+        for (int k = 0; k < 5; ++k) s[k][slot] = a.template in<S>(k)[q];
     }
 }
 
@@ -272,8 +272,8 @@ __device__ __forceinline__ void tile_raw_group(const StepArgs &a, int c0, int nt
 // here keeps every old cell's particles partitioned by move direction, so a
 // near group (source cell s, direction d) is the contiguous run that starts
 // after the groups 0 .. d-1 of s.
-template <int TC, int CH>
-__device__ void tile_groups(const StepArgs &a, TileLds<TC, CH> &L, int ntc, int nfin)
+template <int TC, int CH, class S>
+__device__ void tile_groups(const StepArgs &a, TileLds<TC, CH, S> &L, int ntc, int nfin)
 {
     const int lane = threadIdx.x, nx = a.geo().nx;
     // L.raw holds the near groups (filled with the tile's other loads)
@@ -317,7 +317,7 @@ __device__ void tile_groups(const StepArgs &a, TileLds<TC, CH> &L, int ntc, int 
     __syncthreads();
     if (lane < ntc && nfin > 0) {
         L.anyfar = 1;
-        tile_far_shift<TC, CH>(a, L, lane, L.tiy[lane] * nx + L.tix[lane], nfin);
+        tile_far_shift<TC, CH, S>(a, L, lane, L.tiy[lane] * nx + L.tix[lane], nfin);
     }
     __syncthreads();
 }
@@ -331,8 +331,8 @@ __device__ void tile_groups(const StepArgs &a, TileLds<TC, CH> &L, int ntc, int 
 // COLL).  The draws do not depend on the velocities, so a round of up to
 // NTC_ROUND/TC candidates per cell is drawn by the lanes of the wave at
 // once; one lane per cell then runs its candidates in order.
-template <int TC, int CH>
-__device__ __forceinline__ void ntc_draws(TileLds<TC, CH> &L, const NtcParams &P, int c0, int ntc, long long k0)
+template <int TC, int CH, class S>
+__device__ __forceinline__ void ntc_draws(TileLds<TC, CH, S> &L, const NtcParams &P, int c0, int ntc, long long k0)
 {
     constexpr int KC = NTC_ROUND / TC;
     const int lane = threadIdx.x;
@@ -359,8 +359,8 @@ __device__ __forceinline__ void ntc_draws(TileLds<TC, CH> &L, const NtcParams &P
     }
 }
 
-template <int TC, int CH>
-__device__ __forceinline__ void ntc_chain(double *vx, double *vy, double *vz, const TileLds<TC, CH> &L, int e0,
+template <int TC, int CH, class S>
+__device__ __forceinline__ void ntc_chain(S *vx, S *vy, S *vz, const TileLds<TC, CH, S> &L, int e0,
                                           int n, double &sig, unsigned long long &ncoll)
 {
     for (int e = e0; e < e0 + n; ++e) {
@@ -378,16 +378,16 @@ __device__ __forceinline__ void ntc_chain(double *vx, double *vy, double *vz, co
             const double mx = 0.5 * (vxi + vxj);
             const double my = 0.5 * (vyi + vyj);
             const double mz = 0.5 * (vzi + vzj);
-            vx[i] = mx + 0.5 * rx, vy[i] = my + 0.5 * ry, vz[i] = mz + 0.5 * rz;
-            vx[j] = mx - 0.5 * rx, vy[j] = my - 0.5 * ry, vz[j] = mz - 0.5 * rz;
+            vx[i] = (S)(mx + 0.5 * rx), vy[i] = (S)(my + 0.5 * ry), vz[i] = (S)(mz + 0.5 * rz);
+            vx[j] = (S)(mx - 0.5 * rx), vy[j] = (S)(my - 0.5 * ry), vz[j] = (S)(mz - 0.5 * rz);
             ncoll += 1;
         }
     }
 }
 
 // v* address the tile's velocities (LDS or global), slot 0 = first of the tile
-template <int TC, int CH>
-__device__ __forceinline__ void tile_ntc(double *vx, double *vy, double *vz, TileLds<TC, CH> &L,
+template <int TC, int CH, class S>
+__device__ __forceinline__ void tile_ntc(S *vx, S *vy, S *vz, TileLds<TC, CH, S> &L,
                                          const NtcParams &P, int c0, int ntc, bool own, double &nbar,
                                          double &sig, double &rem, unsigned long long &ncoll,
                                          unsigned long long &ncand)
@@ -413,11 +413,11 @@ __device__ __forceinline__ void tile_ntc(double *vx, double *vy, double *vz, Til
     }
     __syncthreads();
     for (long long k0 = 0; ballot64(lane < ntc && M > k0) != 0; k0 += KC) {
-        ntc_draws<TC, CH>(L, P, c0, ntc, k0);
+        ntc_draws<TC, CH, S>(L, P, c0, ntc, k0);
         __syncthreads();
         if (lane < ntc && M > k0) {
             const int n = (int)min(M - k0, (long long)KC);
-            ntc_chain<TC, CH>(vx + s0, vy + s0, vz + s0, L, lane * KC, n, sig, ncoll);
+            ntc_chain<TC, CH, S>(vx + s0, vy + s0, vz + s0, L, lane * KC, n, sig, ncoll);
             ncand += (unsigned long long)n;
         }
         __syncthreads();
@@ -426,9 +426,9 @@ __device__ __forceinline__ void tile_ntc(double *vx, double *vy, double *vz, Til
 
 // moment sample: a team of 64/TC lanes per cell; the lane that owns sum m of
 // cell t (see tile_kernel) adds the team total to the running sum
-template <int TC, int CH>
-__device__ __forceinline__ void tile_sample(const double *vx, const double *vy, const double *vz,
-                                            const TileLds<TC, CH> &L, int ntc, bool mown, double mprev,
+template <int TC, int CH, class S>
+__device__ __forceinline__ void tile_sample(const S *vx, const S *vy, const S *vz,
+                                            const TileLds<TC, CH, S> &L, int ntc, bool mown, double mprev,
                                             double *mdst)
 {
     constexpr int T = 64 / TC;
@@ -449,8 +449,8 @@ __device__ __forceinline__ void tile_sample(const double *vx, const double *vy, 
 constexpr int KEY_WALL = 63;  // marks a particle whose move crosses a wall (done in a second pass)
 
 // direction code of a particle of tile cell t now at (x, y)
-template <int TC, int CH>
-__device__ __forceinline__ int tile_dir(const StepArgs &a, const TileLds<TC, CH> &L, int t, double x, double y)
+template <int TC, int CH, class S>
+__device__ __forceinline__ int tile_dir(const StepArgs &a, const TileLds<TC, CH, S> &L, int t, double x, double y)
 {
     int nix, niy;
     cell_xy(a.geo(), x, y, nix, niy);
@@ -461,14 +461,14 @@ __device__ __forceinline__ int tile_dir(const StepArgs &a, const TileLds<TC, CH>
 // (slots b0 .. b0+63 of the tile) that do not reach a wall, in place; their
 // direction codes go to kr.  A particle that would cross a wall is left as
 // it is and marked KEY_WALL.  Returns whether the chunk has such particles.
-template <int TC, int CH>
-__device__ __forceinline__ bool move_chunk_free(const StepArgs &a, const TileLds<TC, CH> &L, double *const *s,
+template <int TC, int CH, class S>
+__device__ __forceinline__ bool move_chunk_free(const StepArgs &a, const TileLds<TC, CH, S> &L, S *const *s,
                                                 int32_t *kr, int ntc, int nt, int b0)
 {
     const int i = b0 + (int)threadIdx.x;
     bool wall = false;
     if (i < nt) {
-        const int t = tile_cell<TC, CH>(L, ntc, L.csn[0], i);
+        const int t = tile_cell<TC, CH, S>(L, ntc, L.csn[0], i);
         const double dt = a.K().dt, g = a.K().g, H = a.K().G.H, Lx = a.K().G.Lx;
         double x = s[0][i], vx = s[2][i];
         const double y = s[1][i], vy = s[3][i];
@@ -487,31 +487,34 @@ __device__ __forceinline__ bool move_chunk_free(const StepArgs &a, const TileLds
                 if (xw >= Lx) xw = 0.0;
                 x = xw;
             }
-            s[0][i] = x;
-            s[1][i] = yn;
-            s[2][i] = vx;
-            kr[i] = t * NGRP + tile_dir<TC, CH>(a, L, t, x, yn);
+            // the stored (for FP32 state: rounded) position decides the cell
+            const S xs = (S)x, ys = (S)yn;
+            s[0][i] = xs;
+            s[1][i] = ys;
+            s[2][i] = (S)vx;
+            kr[i] = t * NGRP + tile_dir<TC, CH, S>(a, L, t, (double)xs, (double)ys);
         }
     }
     return ballot64(wall) != 0;
 }
 
 // the particles of one chunk marked KEY_WALL: the full move with walls
-template <int TC, int CH>
-__device__ void move_chunk_walls(const StepArgs &a, const TileLds<TC, CH> &L, double *const *s, int32_t *kr,
+template <int TC, int CH, class S>
+__device__ void move_chunk_walls(const StepArgs &a, const TileLds<TC, CH, S> &L, S *const *s, int32_t *kr,
                                  int ntc, int nt, int b0, int &walls, bool &limit)
 {
     const int i = b0 + (int)threadIdx.x;
     if (i < nt && kr[i] == KEY_WALL) {
-        const int t = tile_cell<TC, CH>(L, ntc, L.csn[0], i);
+        const int t = tile_cell<TC, CH, S>(L, ntc, L.csn[0], i);
         double x = s[0][i], y = s[1][i], vx = s[2][i], vy = s[3][i], vz = s[4][i];
         walls += move_particle(a.geo(), a.M1(), (uint32_t)(L.csn[0] + i), x, y, vx, vy, vz, limit);
-        s[0][i] = x;
-        s[1][i] = y;
-        s[2][i] = vx;
-        s[3][i] = vy;
-        s[4][i] = vz;
-        kr[i] = t * NGRP + tile_dir<TC, CH>(a, L, t, x, y);
+        const S xs = (S)x, ys = (S)y;
+        s[0][i] = xs;
+        s[1][i] = ys;
+        s[2][i] = (S)vx;
+        s[3][i] = (S)vy;
+        s[4][i] = (S)vz;
+        kr[i] = t * NGRP + tile_dir<TC, CH, S>(a, L, t, (double)xs, (double)ys);
     }
 }
 
@@ -519,8 +522,8 @@ __device__ void move_chunk_walls(const StepArgs &a, const TileLds<TC, CH> &L, do
 // (key t * NGRP + d, in kr), continuing from earlier chunks: lane k of `run`
 // holds the size of group k so far.  One ballot per bit of the direction
 // code, masked to the lanes of the particle's own cell, ranks all lanes.
-template <int TC, int CH>
-__device__ __forceinline__ void rank_chunk(const TileLds<TC, CH> &L, int32_t *kr, int ntc, int nt, int b0, int &run)
+template <int TC, int CH, class S>
+__device__ __forceinline__ void rank_chunk(const TileLds<TC, CH, S> &L, int32_t *kr, int ntc, int nt, int b0, int &run)
 {
     const int lane = threadIdx.x;
     const int D0 = L.csn[0];
@@ -554,8 +557,8 @@ __device__ __forceinline__ void rank_chunk(const TileLds<TC, CH> &L, int32_t *kr
 
 // offsets of the tile cells' next-step groups inside each cell (sizes held
 // by lane t * NGRP + d), published as absolute first slots with the cell end
-template <int TC, int CH>
-__device__ __forceinline__ void tile_group_offsets(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc, int run)
+template <int TC, int CH, class S>
+__device__ __forceinline__ void tile_group_offsets(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int ntc, int run)
 {
     const int lane = threadIdx.x;
     if (lane < TC * NGRP) L.run[lane] = run;
@@ -583,14 +586,14 @@ __device__ __forceinline__ void tile_group_offsets(const StepArgs &a, TileLds<TC
 //     and partitioned in place.
 // STAGED tiles (at most 64*CH particles) are staged in LDS; larger ones run
 // the same steps on the tile's destination range in global memory.
-template <int TC, int CH, bool GATHER, bool MOVE, bool STAGED>
-__device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc, int nt, int n_old, bool own_ntc,
+template <int TC, int CH, class S, bool GATHER, bool MOVE, bool STAGED>
+__device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int ntc, int nt, int n_old, bool own_ntc,
                           double &nbar, double &sig, double &rem, bool mown, double mprev, double *mdst,
                           unsigned long long &ncoll, unsigned long long &ncand, int &walls, bool &limit)
 {
     const int lane = threadIdx.x;
     const int D0 = L.csn[0];
-    double *s[5];
+    S *s[5];
     int32_t *kr;
     if (STAGED) {
 #pragma unroll
@@ -598,14 +601,14 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
         kr = L.kr;
     } else {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) s[k] = a.out(k) + D0;  // k_classify: out == in (in place)
+        for (int k = 0; k < 5; ++k) s[k] = a.template out<S>(k) + D0;  // k_classify: out == in (in place)
         kr = a.K().scr_i + D0;
     }
 
     // 1. gather
     if (STAGED) {
         // every load of the tile in flight at once
-        double g[CH][5];
+        S g[CH][5];
         bool g_ok[CH];
 #pragma unroll
         for (int b = 0; b < CH; ++b) {
@@ -613,8 +616,8 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
             int src = -1;
             if (i < nt) {
                 if (GATHER) {
-                    const int t = tile_cell<TC, CH>(L, ntc, D0, i);
-                    src = tile_source<TC, CH>(L, t, i - (L.csn[t] - D0));
+                    const int t = tile_cell<TC, CH, S>(L, ntc, D0, i);
+                    src = tile_source<TC, CH, S>(L, t, i - (L.csn[t] - D0));
                     if (src >= n_old) {
                         src = -1;
                         atomicOr(&a.K().ctr->status, ST_INTERNAL);
@@ -625,7 +628,7 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
             }
             g_ok[b] = src >= 0;
 #pragma unroll
-            for (int k = 0; k < 5; ++k) g[b][k] = src >= 0 ? a.in(k)[src] : 0.0;
+            for (int k = 0; k < 5; ++k) g[b][k] = src >= 0 ? a.template in<S>(k)[src] : (S)0;
         }
 #pragma unroll
         for (int b = 0; b < CH; ++b) {
@@ -637,36 +640,36 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
         }
         if (GATHER && L.anyfar) {
             __syncthreads();
-            tile_far_gather<TC, CH>(a, L, s, c0, ntc, n_old);
+            tile_far_gather<TC, CH, S>(a, L, s, c0, ntc, n_old);
         }
         __syncthreads();
     } else if (GATHER) {
         for (int i = lane; i < nt; i += 64) {
-            const int t = tile_cell<TC, CH>(L, ntc, D0, i);
-            const int src = tile_source<TC, CH>(L, t, i - (L.csn[t] - D0));
+            const int t = tile_cell<TC, CH, S>(L, ntc, D0, i);
+            const int src = tile_source<TC, CH, S>(L, t, i - (L.csn[t] - D0));
             if (src >= n_old) atomicOr(&a.K().ctr->status, ST_INTERNAL);
             if (src < 0 || src >= n_old) continue;
 #pragma unroll
-            for (int k = 0; k < 5; ++k) s[k][i] = a.in(k)[src];
+            for (int k = 0; k < 5; ++k) s[k][i] = a.template in<S>(k)[src];
         }
-        if (L.anyfar) tile_far_gather<TC, CH>(a, L, s, c0, ntc, n_old);
+        if (L.anyfar) tile_far_gather<TC, CH, S>(a, L, s, c0, ntc, n_old);
         __threadfence();
         __syncthreads();
     }
 
     // 2. collisions and 3. sample
     if (GATHER) {
-        tile_ntc<TC, CH>(s[2], s[3], s[4], L, a.N(), c0, ntc, own_ntc, nbar, sig, rem, ncoll, ncand);
+        tile_ntc<TC, CH, S>(s[2], s[3], s[4], L, a.N(), c0, ntc, own_ntc, nbar, sig, rem, ncoll, ncand);
         if (!STAGED) __threadfence();
         __syncthreads();
-        if (a.sample) tile_sample<TC, CH>(s[2], s[3], s[4], L, ntc, mown, mprev, mdst);
+        if (a.sample) tile_sample<TC, CH, S>(s[2], s[3], s[4], L, ntc, mown, mprev, mdst);
     }
 
     if (!MOVE) {
         if (STAGED) {
             for (int i = lane; i < nt; i += 64) {
 #pragma unroll
-                for (int k = 0; k < 5; ++k) a.out(k)[D0 + i] = L.v[k][i];
+                for (int k = 0; k < 5; ++k) a.template out<S>(k)[D0 + i] = L.v[k][i];
             }
         }
         return;  // unstaged: already in place, in sorted order
@@ -675,17 +678,17 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
     // 4. move for the next step (walls in a second pass), grouped by (cell,
     // direction) in slot order
     bool anywall = false;
-    for (int b0 = 0; b0 < nt; b0 += 64) anywall |= move_chunk_free<TC, CH>(a, L, s, kr, ntc, nt, b0);
+    for (int b0 = 0; b0 < nt; b0 += 64) anywall |= move_chunk_free<TC, CH, S>(a, L, s, kr, ntc, nt, b0);
     if (!STAGED) __threadfence();
     __syncthreads();
     if (anywall) {
-        for (int b0 = 0; b0 < nt; b0 += 64) move_chunk_walls<TC, CH>(a, L, s, kr, ntc, nt, b0, walls, limit);
+        for (int b0 = 0; b0 < nt; b0 += 64) move_chunk_walls<TC, CH, S>(a, L, s, kr, ntc, nt, b0, walls, limit);
         if (!STAGED) __threadfence();
         __syncthreads();
     }
     int run = 0;
-    for (int b0 = 0; b0 < nt; b0 += 64) rank_chunk<TC, CH>(L, kr, ntc, nt, b0, run);
-    tile_group_offsets<TC, CH>(a, L, c0, ntc, run);
+    for (int b0 = 0; b0 < nt; b0 += 64) rank_chunk<TC, CH, S>(L, kr, ntc, nt, b0, run);
+    tile_group_offsets<TC, CH, S>(a, L, c0, ntc, run);
 
     // 5. write out, partitioned by group inside each cell
     if (STAGED) {
@@ -693,7 +696,7 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
             const int k6 = kr[i], key = k6 & 63, t = key / NGRP;
             const int q = L.csn[t] + L.excl[key] + (k6 >> 6);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) a.out(k)[q] = L.v[k][i];
+            for (int k = 0; k < 5; ++k) a.template out<S>(k)[q] = L.v[k][i];
         }
     } else {
         __threadfence();
@@ -704,7 +707,7 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
             __syncthreads();
             for (int i = lane; i < nt; i += 64) {
                 const int k6 = kr[i], key = k6 & 63, t = key / NGRP;
-                a.out(k)[L.csn[t] + L.excl[key] + (k6 >> 6)] = a.K().scr[D0 + i];
+                a.template out<S>(k)[L.csn[t] + L.excl[key] + (k6 >> 6)] = a.K().scr[D0 + i];
             }
             __threadfence();
             __syncthreads();
@@ -715,18 +718,18 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH> &L, int c0, int ntc
         if (key - t * NGRP != DIR_FAR) continue;
         const int q = L.csn[t] + L.excl[key] + (k6 >> 6);
         int nix, niy;
-        cell_xy(a.geo(), STAGED ? L.v[0][i] : a.out(0)[q], STAGED ? L.v[1][i] : a.out(1)[q], nix, niy);
+        cell_xy(a.geo(), STAGED ? L.v[0][i] : a.template out<S>(0)[q], STAGED ? L.v[1][i] : a.template out<S>(1)[q], nix, niy);
         record_far(a.far_out(), a.farcnt_out(), a.K().ctr, a.far_out_slot(), a.K().far_cap, q, c0 + t, niy * a.geo().nx + nix);
     }
 }
 
-template <int TC, int CH, bool GATHER, bool MOVE>
+template <int TC, int CH, class S, bool GATHER, bool MOVE>
 __device__ __forceinline__ void tile_kernel(const StepArgs &a)
 {
     static_assert(TC == 1 || TC == 2 || TC == 4, "tile sizes with teams of >= 16 lanes");
     static_assert(TC * NGRP <= 64 && NTC_ROUND <= 64, "");
     static_assert(GATHER || MOVE, "");
-    __shared__ TileLds<TC, CH> L;
+    __shared__ TileLds<TC, CH, S> L;
     constexpr int T = 64 / TC, SPAN = T / 16;
     const int lane = threadIdx.x;
     const int nc = a.K().ncells, nx = a.geo().nx;
@@ -765,18 +768,18 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a)
         L.raw[2][lane] = src;
     }
     __syncthreads();
-    if (GATHER) tile_groups<TC, CH>(a, L, ntc, nfin);
+    if (GATHER) tile_groups<TC, CH, S>(a, L, ntc, nfin);
     const int D0 = L.csn[0];
     const int nt = L.csn[ntc] - D0;
 
     unsigned long long ncoll = 0, ncand = 0;
     int walls = 0;
     bool limit = false;
-    if (nt <= TileLds<TC, CH>::CAP)
-        tile_body<TC, CH, GATHER, MOVE, true>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev, mdst,
+    if (nt <= TileLds<TC, CH, S>::CAP)
+        tile_body<TC, CH, S, GATHER, MOVE, true>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev, mdst,
                                               ncoll, ncand, walls, limit);
     else
-        tile_body<TC, CH, GATHER, MOVE, false>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev,
+        tile_body<TC, CH, S, GATHER, MOVE, false>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev,
                                                mdst, ncoll, ncand, walls, limit);
 
     if (own_ntc) {
@@ -792,26 +795,30 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a)
     if (MOVE && ballot64(limit) != 0 && lane == 0) atomicOr(&a.K().ctr->status, ST_WALL_LIMIT);
 }
 
-template <int TC, int CH>
+template <int TC, int CH, class S>
 __global__ __launch_bounds__(64) void k_classify(StepArgs a)
 {
-    tile_kernel<TC, CH, false, true>(a);
+    tile_kernel<TC, CH, S, false, true>(a);
 }
 
-template <int TC, int CH, bool MOVE>
+template <int TC, int CH, bool MOVE, class S>
 __global__ __launch_bounds__(64) void k_step(StepArgs a)
 {
-    tile_kernel<TC, CH, true, MOVE>(a);
+    tile_kernel<TC, CH, S, true, MOVE>(a);
 }
 
-#define DSMC_TILE_INSTANCES(TC, CH)                              \
-    template __global__ void k_classify<TC, CH>(StepArgs);       \
-    template __global__ void k_step<TC, CH, true>(StepArgs);     \
-    template __global__ void k_step<TC, CH, false>(StepArgs);
-DSMC_TILE_INSTANCES(4, 4)
-DSMC_TILE_INSTANCES(2, 4)
-DSMC_TILE_INSTANCES(1, 4)
-DSMC_TILE_INSTANCES(1, 8)
+#define DSMC_TILE_INSTANCES(TC, CH, S)                              \
+    template __global__ void k_classify<TC, CH, S>(StepArgs);       \
+    template __global__ void k_step<TC, CH, true, S>(StepArgs);     \
+    template __global__ void k_step<TC, CH, false, S>(StepArgs);
+DSMC_TILE_INSTANCES(4, 4, double)
+DSMC_TILE_INSTANCES(2, 4, double)
+DSMC_TILE_INSTANCES(1, 4, double)
+DSMC_TILE_INSTANCES(1, 8, double)
+DSMC_TILE_INSTANCES(4, 4, float)
+DSMC_TILE_INSTANCES(2, 4, float)
+DSMC_TILE_INSTANCES(1, 4, float)
+DSMC_TILE_INSTANCES(1, 8, float)
 #undef DSMC_TILE_INSTANCES
 
 // particles arriving in every cell with the step's sort, and their block sums
@@ -880,6 +887,7 @@ __global__ __launch_bounds__(256) void k_average(const double *mom, double *out,
 }
 
 // ---- initial state: ppc Maxwellian particles per cell ----------------------
+template <class S>
 __global__ __launch_bounds__(256) void k_init_maxwell(InitArgs a)
 {
     const size_t g = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -898,24 +906,29 @@ __global__ __launch_bounds__(256) void k_init_maxwell(InitArgs a)
     double z0, z1, zz0, zz1;
     box_muller(u53(b.x, b.y), u53(b.z, b.w), z0, z1);
     box_muller(u53(e.x, e.y), u53(e.z, e.w), zz0, zz1);
-    a.st[0][g] = inside_cell(ix, u53(p.x, p.y));
-    a.st[1][g] = inside_cell(iy, u53(p.z, p.w));
-    a.st[2][g] = a.s_th * z0;
-    a.st[3][g] = a.s_th * z1;
-    a.st[4][g] = a.s_th * zz0;
+    ((S *)a.st[0])[g] = (S)inside_cell(ix, u53(p.x, p.y));
+    ((S *)a.st[1])[g] = (S)inside_cell(iy, u53(p.z, p.w));
+    ((S *)a.st[2])[g] = (S)(a.s_th * z0);
+    ((S *)a.st[3])[g] = (S)(a.s_th * z1);
+    ((S *)a.st[4])[g] = (S)(a.s_th * zz0);
 }
+template __global__ void k_init_maxwell<double>(InitArgs);
+template __global__ void k_init_maxwell<float>(InitArgs);
 
 // ---- adoption of a caller-written, unsorted particle set -------------------
+template <class S>
 __global__ __launch_bounds__(256) void k_adopt_count(AdoptArgs a)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= a.n) return;
     int ix, iy;
-    cell_xy(a.G, a.in[0][p], a.in[1][p], ix, iy);
+    cell_xy(a.G, (double)((const S *)a.in[0])[p], (double)((const S *)a.in[1])[p], ix, iy);
     const int c = iy * a.G.nx + ix;
     a.cellid[p] = c;
     atomicAdd(&a.counts[c], 1);
 }
+template __global__ void k_adopt_count<double>(AdoptArgs);
+template __global__ void k_adopt_count<float>(AdoptArgs);
 
 // generic block sums of per-cell counts
 __global__ __launch_bounds__(256) void k_block_sums(const int32_t *counts, int ncells, int32_t *blocksum)
@@ -965,14 +978,17 @@ __global__ __launch_bounds__(256) void k_adopt_sortcell(AdoptArgs a)
     a.cursor[c] = 0;
 }
 
+template <class S>
 __global__ __launch_bounds__(256) void k_adopt_gather(AdoptArgs a)
 {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= a.n) return;
     const int p = a.perm[q];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) a.out[k][q] = a.in[k][p];
+    for (int k = 0; k < 5; ++k) ((S *)a.out[k])[q] = ((const S *)a.in[k])[p];
 }
+template __global__ void k_adopt_gather<double>(AdoptArgs);
+template __global__ void k_adopt_gather<float>(AdoptArgs);
 
 __global__ __launch_bounds__(256) void k_fill_f64(double *p, size_t n, double v)
 {

@@ -25,7 +25,7 @@ constexpr int GSTRIDE = NGRP + 1;  // per cell: first slot of each group, then t
 // device memory (inside the workspace) so that a launch passes a pointer
 // and a few words instead of a large argument block.
 struct TileConst {
-    double *st[2][5];        // the two state buffers (x, y, vx, vy, vz)
+    void *st[2][5];          // the two state buffers (x, y, vx, vy, vz; double or float)
     int32_t *cs[2];          // their cell_start
     int32_t *grp[2];         // [ncells][GSTRIDE] first slot of every group and the cell end, by step parity
     int32_t *far[2];         // long-jump lists, by step parity
@@ -69,8 +69,10 @@ struct StepArgs {
         return g;
     }
     __device__ int po() const { return classify ? (int)(step & 1u) : (int)((step + 1u) & 1u); }
-    __device__ const double *in(int k) const { return K().st[cur][k]; }
-    __device__ double *out(int k) const { return K().st[classify ? cur : 1 - cur][k]; }
+    template <class S>
+    __device__ const S *in(int k) const { return (const S *)K().st[cur][k]; }
+    template <class S>
+    __device__ S *out(int k) const { return (S *)K().st[classify ? cur : 1 - cur][k]; }
     __device__ const int32_t *cs_old() const { return K().cs[cur]; }
     __device__ const int32_t *cs_new() const { return K().cs[classify ? cur : 1 - cur]; }
     __device__ const int32_t *grp_in() const { return K().grp[step & 1u]; }
@@ -114,7 +116,7 @@ struct CellArgs {
 };
 
 struct InitArgs {
-    double *st[5];
+    void *st[5];  // double or float
     int32_t *cs;
     double *nbar, *sigcmax, *rem;
     int nx, ncells, ppc;
@@ -123,8 +125,8 @@ struct InitArgs {
 };
 
 struct AdoptArgs {
-    const double *in[5];
-    double *out[5];
+    const void *in[5];  // double or float
+    void *out[5];
     int32_t *cellid, *counts, *cursor, *perm;
     const int32_t *cs;
     Geometry G;
@@ -151,8 +153,8 @@ struct ReseedArgs {
     int32_t *cs_new;
     int32_t *countnew;
     int32_t *blocksum;
-    const double *in[5];
-    double *out[5];
+    const void *in[5];  // double or float
+    void *out[5];
     Counters *ctr;
     Lattice L;
     int nx, ncells, ppc, order, ar_max_tries;
@@ -170,21 +172,25 @@ struct LbmArgs {
     double tau, gx;
 };
 
-// TC cells per tile (one wave); tiles of up to 64*CH particles are staged in LDS
-template <int TC, int CH>
+// TC cells per tile (one wave); tiles of up to 64*CH particles are staged in
+// LDS; S is the stored particle type (double, or float with FP64 arithmetic)
+template <int TC, int CH, class S>
 __global__ void k_classify(StepArgs a);
-template <int TC, int CH, bool MOVE>
+template <int TC, int CH, bool MOVE, class S>
 __global__ void k_step(StepArgs a);
 __global__ void k_cell_count(CellArgs a);
 __global__ void k_scan_blocks(int32_t *blocksum, int nblk, int32_t *cs_out, int ncells, Counters *ctr,
                               int reset_slot);
 __global__ void k_average(const double *mom, double *out, size_t n, double S);
+template <class S>
 __global__ void k_init_maxwell(InitArgs a);
+template <class S>
 __global__ void k_adopt_count(AdoptArgs a);
 __global__ void k_block_sums(const int32_t *counts, int ncells, int32_t *blocksum);
 __global__ void k_block_scan(const int32_t *counts, int ncells, const int32_t *blockoff, int32_t *cs);
 __global__ void k_adopt_place(AdoptArgs a);
 __global__ void k_adopt_sortcell(AdoptArgs a);
+template <class S>
 __global__ void k_adopt_gather(AdoptArgs a);
 __global__ void k_fill_f64(double *p, size_t n, double v);
 __global__ void k_fill_i32(int32_t *p, size_t n, int32_t v);
@@ -197,7 +203,9 @@ __global__ void k_project(ProjectArgs a);
 __global__ void k_reseed_prep(ReseedArgs a);
 __global__ void k_reseed_count(ReseedArgs a);
 __global__ void k_reseed_check(ReseedArgs a);
+template <class S>
 __global__ void k_reseed_copy(ReseedArgs a);
+template <class S>
 __global__ void k_reseed_gen(ReseedArgs a);
 __global__ void k_reseed_unmark(ReseedArgs a);
 __global__ void k_lbm(LbmArgs a);

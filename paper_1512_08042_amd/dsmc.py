@@ -46,12 +46,14 @@ class Channel:
         self.cfg = c = cfg.resolved()
         self.device = torch.device(device)
         self._c = _lib.Config(c.nx, c.ny, c.ppc, c.nbar_mode, c.capacity, c.kn, c.dt, c.body_force_x, c.kT_over_m,
-                              c.sigcr_max0, c.seed, c.ar_max_tries, c.far_capacity)
+                              c.sigcr_max0, c.seed, c.ar_max_tries, c.far_capacity, int(c.state_bits), 0)
         sz = _lib.Sizes()
         check(lib().dsmc_query_sizes(ctypes.byref(self._c), ctypes.byref(sz)), "dsmc_query_sizes")
         self.ncells = int(sz.ncells)
         self.capacity = int(sz.capacity)
-        self.state = torch.zeros((2, 5, self.capacity), dtype=torch.float64, device=self.device)
+        # particle state: FP64, or FP32 storage (the arithmetic is FP64 either way)
+        self.state_dtype = torch.float32 if int(c.state_bits) == 32 else torch.float64
+        self.state = torch.zeros((2, 5, self.capacity), dtype=self.state_dtype, device=self.device)
         self.workspace = torch.zeros(int(sz.workspace_bytes) + 256, dtype=torch.uint8, device=self.device)
         ws = _ptr(self.workspace)
         self._ws = (ws + 255) & ~255
@@ -66,7 +68,7 @@ class Channel:
             mode = 1
             n = int(particles[0].numel())
             for k in range(5):
-                self.state[0, k, :n].copy_(torch.as_tensor(particles[k], dtype=torch.float64))
+                self.state[0, k, :n].copy_(torch.as_tensor(particles[k], dtype=torch.float64).to(self.state_dtype))
         self._h = ctypes.c_void_p()
         check(lib().dsmc_init(ctypes.byref(self._c), ctypes.byref(b), mode, n, _stream(stream), ctypes.byref(self._h)),
               "dsmc_init")

@@ -69,3 +69,17 @@ def test_run_parameters_agree_with_oracle_reading():
         assert config.time_step(kn, ny) == O.default_dt(kn, ny)
         assert config.body_force(kn, ny, 0.1) == O.body_force_for_mach(kn, ny, 0.1)
     assert config.bgk_tau(0.1, 64, 3 ** 0.5) == O.lbm_tau(0.1, 64, 3 ** 0.5)
+
+
+def test_state_precision_sizes():
+    # FP32 particle state halves the state arrays; other widths are rejected
+    L = _lib.lib()
+    s64, s32 = _lib.Sizes(), _lib.Sizes()
+    c = _lib.Config(4, 8, 10, 0, 1000, 0.1, 0.1, 0.0, 1.0, 6.0, 1, 0, 0, 64, 0)
+    assert L.dsmc_query_sizes(ctypes.byref(c), ctypes.byref(s64)) == 0
+    c.state_bits = 32
+    assert L.dsmc_query_sizes(ctypes.byref(c), ctypes.byref(s32)) == 0
+    assert s64.state_array_bytes == 1000 * 8 and s32.state_array_bytes == 1000 * 4
+    assert s32.workspace_bytes == s64.workspace_bytes
+    c.state_bits = 16
+    assert L.dsmc_query_sizes(ctypes.byref(c), ctypes.byref(s32)) == _lib.EINVAL

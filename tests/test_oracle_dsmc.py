@@ -167,10 +167,10 @@ def _hermite_sums(avg):
             "yyy": (m[8] - 3 * m[1], 6.0), "zz": (m[9] - 1, 2.0)}
 
 
-@pytest.mark.parametrize("nsteps", [0, 60])
-def test_equilibrium_moments_within_standard_errors(nsteps):
+@pytest.mark.parametrize("nsteps,state32", [(0, False), (60, False), (60, True)])
+def test_equilibrium_moments_within_standard_errors(nsteps, state32):
     nx, ny, ppc = 16, 16, 100
-    s = O.Sim(nx, ny, ppc, 0.1, seed=21)
+    s = O.Sim(nx, ny, ppc, 0.1, seed=21, state32=state32)
     s.init_maxwell()
     s.step(nsteps)
     s.reset_moments()
@@ -235,3 +235,26 @@ def test_low_kn_poiseuille_profile():
     expect = -g / nu
     se = curv.std(ddof=1) / math.sqrt(nb)
     assert abs(curv.mean() - expect) < max(0.03 * abs(expect), 4 * se), (curv.mean(), expect, se)
+
+
+def test_fp32_state_rounds_every_stored_value():
+    # FP32 state: every stored value is a float, and one step of the FP32
+    # form differs from the FP64 form only by the rounding of the stored
+    # values (a few FP32 ulps; no collision outcome or wall decision changes
+    # on this small box)
+    kw = dict(g=0.01, seed=7, capacity=4096)
+    a = O.Sim(4, 6, 40, 0.2, state32=True, **kw)
+    b = O.Sim(4, 6, 40, 0.2, **kw)
+    for s in (a, b):
+        s.init_maxwell()
+    pa, pb = a.particles(), b.particles()
+    for u, v in zip(pa, pb):
+        assert np.array_equal(np.asarray(u, dtype=np.float32).astype(np.float64), u)
+        assert np.all(np.abs(u - v) <= 2.0 ** -24 * np.abs(v) + 1e-300)  # init: one rounding each
+    a.step(1)
+    b.step(1)
+    assert a.counters()["ncoll"] == b.counters()["ncoll"] and a.counters()["nwall"] == b.counters()["nwall"]
+    assert np.array_equal(a.cells()[0], b.cells()[0])
+    for u, v in zip(a.particles(), b.particles()):
+        assert np.array_equal(np.asarray(u, dtype=np.float32).astype(np.float64), u)
+        assert np.all(np.abs(u - v) <= 1e-6 * (np.abs(v) + 1.0))
