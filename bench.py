@@ -21,7 +21,15 @@ Printed JSON line: metric, value, ..., plus
             from the committed summary under profiles/ while the kernel
             sources are unchanged since it was made, else null;
   cpu_baseline: the FP64 oracle timed on this host on one cycle of the same
-            workload (single-threaded).
+            workload (single-threaded);
+  precision: the FP32-state form against plain FP64 on a 2048 x 1024 x 50
+            channel (Kn 0.02, Ma 0.1): particle-steps/s of each, and per
+            moment order the RMS and mean over cells of z = (m32 - m64) / SE,
+            m the time-averaged Hermite moments of each run and SE their
+            sampling error under the Maxwellian (consecutive steps counted as
+            independent, which overstates z), beside the same z between two
+            FP64 runs of different seeds: the FP32 form's moment error is
+            stated against that sampling noise.
 """
 from __future__ import annotations
 
@@ -56,13 +64,86 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_512x256x100_fp64_traffi
 TRACE_SUMMARY = os.path.join(ROOT, "profiles", "dsmc_cycle_512x256x100_fp64_kernel_trace.md")
 # the commands whose output the summaries condense (run from the repository root)
 TRACE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace -o trace -- "
-             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline")
+             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-precision")
 PMC_CMDS = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --copy-calibration",
             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration")
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --copy-calibration")
 # kernel-name prefixes of the library's kernels, by profiling id
 KERNEL_PREFIX = {"step": "void dsmc::k_step<", "classify": "void dsmc::k_classify<"}
+
+
+# the precision workload (FP32 state vs FP64)
+PREC = dict(nx=2048, ny=1024, ppc=50, kn=0.02, mach=0.1, seed=4)
+PREC_WARM, PREC_STEPS = 20, 100
+# Hermite components per order: (sum indices, unit-Maxwellian variance), from
+# the 11 per-cell sums N, x, y, xx, xy, yy, xxx, xxy, xyy, yyy, zz
+HERMITE = {1: [((1,), 1.0), ((2,), 1.0)],
+           2: [((3, -1), 2.0), ((4,), 1.0), ((5, -1), 2.0)],
+           3: [((6, 1, -3), 6.0), ((7, 2, -1), 2.0), ((8, 1, -1), 2.0), ((9, 2, -3), 6.0)]}
+
+
+def _moment_z(a, b, steps):
+    """Per moment order: z = (m_a - m_b) / SE over cells (and components)."""
+    import numpy as np
+
+    N = 0.5 * (a[0] + b[0])
+    ok = N > 0
+    S = float(steps)
+    z = {0: (a[0] - b[0])[ok] / np.sqrt(N[ok] / S)}
+    for order, comps in HERMITE.items():
+        zs = []
+        for idx, var in comps:
+            def hermite(m):
+                inv = 1.0 / np.where(m[0] > 0, m[0], 1.0)
+                h = m[idx[0]] * inv
+                if len(idx) == 2:  # x_i x_j - delta_ij
+                    h = h + idx[1]
+                elif len(idx) == 3:  # cubic - c * linear
+                    h = h + idx[2] * m[idx[1]] * inv
+                return h
+            se = np.sqrt(var / (N * S))
+            zs.append(((hermite(a) - hermite(b)) / se)[ok])
+        z[order] = np.concatenate(zs)
+    return {str(k): {"rms": round(float(np.sqrt(np.mean(v ** 2))), 3), "mean": round(float(np.mean(v)), 3)}
+            for k, v in z.items()}
+
+
+def precision_comparison():
+    """FP32-state vs FP64 on the precision workload: rates and moment error,
+    beside the seed-to-seed difference of two FP64 runs (the sampling noise)."""
+    import torch
+
+    from paper_1512_08042_amd import ChannelConfig
+    from paper_1512_08042_amd import dsmc as D
+
+    res, avgs = {}, {}
+    n = PREC["nx"] * PREC["ny"] * PREC["ppc"]
+    for bits, seed in ((64, PREC["seed"]), (32, PREC["seed"]), (64, PREC["seed"] + 1)):
+        cfg = dict(PREC)
+        cfg["seed"] = seed
+        ch = D.Channel(ChannelConfig(state_bits=bits, **cfg))
+        ch.step(PREC_WARM)
+        ch.reset_moments()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.step(PREC_STEPS, sample_every=1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if seed == PREC["seed"]:
+            res["fp%d_particle_steps_per_s" % bits] = n * PREC_STEPS / (t1 - t0)
+        avgs[(bits, seed)] = ch.sample_moments().cpu().numpy()
+        del ch
+        torch.cuda.empty_cache()
+    out = {"workload": "2048x1024 cells x 50 particles/cell, Kn 0.02, Ma 0.1; %d warm-up steps, %d sampled steps; "
+                       "FP32 and FP64 from seed %d, a second FP64 run from seed %d" %
+                       (PREC_WARM, PREC_STEPS, PREC["seed"], PREC["seed"] + 1)}
+    out.update({k: float("%.4g" % v) for k, v in res.items()})
+    out["fp32_speedup"] = round(res["fp32_particle_steps_per_s"] / res["fp64_particle_steps_per_s"], 3)
+    s0, s1 = PREC["seed"], PREC["seed"] + 1
+    out["moment_z_by_order"] = {"fp32_vs_fp64": _moment_z(avgs[(32, s0)], avgs[(64, s0)], PREC_STEPS),
+                                "fp64_seed_to_seed": _moment_z(avgs[(64, s1)], avgs[(64, s0)], PREC_STEPS)}
+    return out
 
 
 def source_hash() -> str:
@@ -179,6 +260,7 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=8, help="coupling cycles the CPU oracle is timed on")
+    ap.add_argument("--no-precision", action="store_true", help="skip the FP32-vs-FP64 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three plain 1 GiB device copies (reference for HBM byte counters)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
@@ -323,6 +405,10 @@ def main():
         "profiled_ms_per_step": 1e3 * (tp1 - tp0) / args.steps,
         "status_bits": st["bits"],
     }
+    if not args.no_precision:
+        del ch, f, ftmp
+        torch.cuda.empty_cache()
+        out["precision"] = precision_comparison()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(strip, args.cpu_cycles)
     print(json.dumps(out), flush=True)

@@ -391,22 +391,26 @@ void launch_tiles(const dsmc_ctx *x, int kind, bool move, unsigned ntiles, hipSt
         else                                                         \
             k_step<TC, CH, false, S><<<ntiles, 64, 0, s>>>(a);       \
     } while (0)
-#define DSMC_LAUNCH_SHAPE(S)          \
-    do {                              \
-        if (x->tc == 4)               \
-            DSMC_LAUNCH(4, 4, S);     \
-        else if (x->tc == 2)          \
-            DSMC_LAUNCH(2, 4, S);     \
-        else if (x->ch == 4)          \
-            DSMC_LAUNCH(1, 4, S);     \
-        else                          \
-            DSMC_LAUNCH(1, 8, S);     \
-    } while (0)
-    if (state32(x->cfg))
-        DSMC_LAUNCH_SHAPE(float);
-    else
-        DSMC_LAUNCH_SHAPE(double);
-#undef DSMC_LAUNCH_SHAPE
+    // the tile shapes each state type uses (see dsmc_init)
+    if (state32(x->cfg)) {
+        if (x->tc == 4 && x->ch == 8)
+            DSMC_LAUNCH(4, 8, float);
+        else if (x->tc == 4)
+            DSMC_LAUNCH(4, 4, float);
+        else if (x->tc == 2)
+            DSMC_LAUNCH(2, 8, float);
+        else
+            DSMC_LAUNCH(1, 8, float);
+    } else {
+        if (x->tc == 4)
+            DSMC_LAUNCH(4, 4, double);
+        else if (x->tc == 2)
+            DSMC_LAUNCH(2, 4, double);
+        else if (x->ch == 4)
+            DSMC_LAUNCH(1, 4, double);
+        else
+            DSMC_LAUNCH(1, 8, double);
+    }
 #undef DSMC_LAUNCH
 }
 
@@ -544,10 +548,18 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
     x->nsamples = 0;
     x->reseed_events = 0;
     x->classified = false;
-    // step tiles of about 200 particles (one wave each) inside an LDS stage
-    // of 256 slots; denser gases get single-cell tiles with 512 slots
-    x->tc = cfg->ppc <= 50 ? 4 : (cfg->ppc <= 100 ? 2 : 1);
-    x->ch = cfg->ppc <= 200 ? 4 : 8;
+    // step tiles, one wave each: FP64 state, about 200 particles in an LDS
+    // stage of 256 slots; FP32 state (half the stage bytes), about 400
+    // particles in 512 slots (measured best for each at 100 particles per
+    // cell); denser gases get single-cell tiles with 512 slots
+    if (state32(*cfg)) {
+        x->tc = cfg->ppc <= 100 ? 4 : (cfg->ppc <= 200 ? 2 : 1);
+        x->ch = 4 * cfg->ppc * 5 / 4 <= 256 ? 4 : 8;
+        if (x->tc < 4) x->ch = 8;
+    } else {
+        x->tc = cfg->ppc <= 50 ? 4 : (cfg->ppc <= 100 ? 2 : 1);
+        x->ch = cfg->ppc <= 200 ? 4 : 8;
+    }
     x->ntiles = (int)((ncells + x->tc - 1) / x->tc);
     x->prof = false;
     hipStream_t s = S(stream);

@@ -815,9 +815,9 @@ DSMC_TILE_INSTANCES(4, 4, double)
 DSMC_TILE_INSTANCES(2, 4, double)
 DSMC_TILE_INSTANCES(1, 4, double)
 DSMC_TILE_INSTANCES(1, 8, double)
+DSMC_TILE_INSTANCES(4, 8, float)
 DSMC_TILE_INSTANCES(4, 4, float)
-DSMC_TILE_INSTANCES(2, 4, float)
-DSMC_TILE_INSTANCES(1, 4, float)
+DSMC_TILE_INSTANCES(2, 8, float)
 DSMC_TILE_INSTANCES(1, 8, float)
 #undef DSMC_TILE_INSTANCES
 
