@@ -207,6 +207,65 @@ typedef struct lbm_config {
  * e_a.  Errors: DSMC_EINVAL. */
 int lbm_step(const lbm_config *cfg, double *f, double *f_tmp, int32_t nsteps, void *stream);
 
+/* lbm_step that also keeps checkpoints for the adjoint: before steps 0,
+ * every, 2 every, ... the populations entering the step are written to
+ * ckpt[k] (device, [ceil(nsteps/every)][Q][nx*ny]; ckpt may be NULL).  The
+ * result is in f, as for lbm_step.  Errors: DSMC_EINVAL (also every < 1). */
+int lbm_step_checkpointed(const lbm_config *cfg, double *f, double *f_tmp, double *ckpt, int32_t nsteps,
+                          int32_t every, void *stream);
+
+/* Bytes of device workspace that lbm_adjoint needs for segments of `every`
+ * steps (per-block partial sums, one cotangent buffer, every - 1 recomputed
+ * states); every = 0 gives the (small) size that lbm_adjoint_step needs.
+ * Errors: DSMC_EINVAL. */
+int lbm_adjoint_workspace(const lbm_config *cfg, int32_t every, size_t *bytes);
+
+/* Reverse-mode derivative of one lbm_step step (Section 3.1; tau of
+ * Eq. (tau)): with f_n the populations entering the step (device,
+ * [Q][nx*ny]) and lam_next = dJ/df_{n+1} (same layout), writes
+ * lam_out = (df_{n+1}/df_n)^T lam_next and adds this step's dJ/dg and dJ/dtau
+ * to grad[0] and grad[1] (device, 2 doubles; g = body_force_x).  Buffer rows
+ * (y_mode 1) pass cotangents through; populations streamed into them were
+ * dropped and carry none.  The sums are in a fixed order (bitwise
+ * reproducible).  lam_out must not alias lam_next or f_n.  work: device,
+ * lbm_adjoint_workspace(cfg, 0) bytes, caller-owned.  Errors: DSMC_EINVAL. */
+int lbm_adjoint_step(const lbm_config *cfg, const double *f_n, const double *lam_next, double *lam_out,
+                     double *grad, void *work, void *stream);
+
+/* Reverse pass of nsteps lbm_step steps from the checkpoints that
+ * lbm_step_checkpointed wrote with the same cfg and every: each segment's
+ * states are recomputed into the workspace, then the adjoint steps run from
+ * the last step back to the first.  lam: device [Q][nx*ny], on entry
+ * dJ/df_N, on return dJ/df_0.  grad[0], grad[1] += dJ/dg, dJ/dtau over all
+ * steps.  work: lbm_adjoint_workspace(cfg, every) bytes.  nsteps = 0 leaves
+ * lam and grad unchanged.  Errors: DSMC_EINVAL. */
+int lbm_adjoint(const lbm_config *cfg, const double *ckpt, int32_t nsteps, int32_t every, double *lam,
+                double *grad, void *work, void *stream);
+
+/* Hermite coefficients of populations (the expansion that
+ * Eq. (discretefunctions) truncates): a_out[n][i] = sum_q f[q][nodes[i]]
+ * H(n)(xi_q) for the (order+1)(order+2)/2 tensors up to `order` (0..3) in the
+ * row order 1, x, y, xx, xy, yy, xxx, xxy, xyy, yyy.  f: device
+ * [Q][nnodes]; nodes: device, nsel ids; a_out: device [nh][nsel].  An id
+ * outside [0, nnodes) gets NaN coefficients.  Errors: DSMC_EINVAL. */
+int lbm_hermite_moments(int32_t lattice, int32_t order, const double *f, int64_t nnodes, const int32_t *nodes,
+                        int32_t nsel, double *a_out, void *stream);
+
+/* Transpose of lbm_hermite_moments: f_bar[q][nodes[i]] += sum_n H(n)(xi_q)
+ * a_bar[n][i].  The ids must be distinct (repeated ids race); ids outside
+ * [0, nnodes) are skipped.  Errors: DSMC_EINVAL. */
+int lbm_hermite_moments_adjoint(int32_t lattice, int32_t order, const double *a_bar, const int32_t *nodes,
+                                int32_t nsel, double *f_bar, int64_t nnodes, void *stream);
+
+/* Transpose of dsmc_project_moments (Eq. (discretefunctions) with the
+ * coefficients of Eq. (nordercoefficients)), which is linear in the averages
+ * of a cell with <N> > 0: avg_bar[k][c] = sum_q f_bar[q][c] df_q/davg_k.
+ * avg (device [11][ncells]) is only read for <N> > 0; empty cells and row 10
+ * (vz^2, unused by the projection) get zero.  f_bar: device [Q][ncells];
+ * avg_bar: device [11][ncells], overwritten.  Errors: DSMC_EINVAL. */
+int dsmc_project_moments_adjoint(const double *f_bar, const double *avg, int64_t ncells, int32_t ppc,
+                                 double kT_over_m, int32_t lattice, int32_t order, double *avg_bar, void *stream);
+
 /* Host copy of a lattice table: e_out int[Q][2], w_out double[Q], r_out. */
 int dsmc_lattice(int32_t lattice, int32_t *e_out, double *w_out, double *r_out);
 

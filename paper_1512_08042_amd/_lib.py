@@ -20,7 +20,9 @@ KERNEL_NAMES = ("classify", "cell_count", "scan", "cell_final", "step", "project
 # every symbol include/dsmc.h declares
 EXPORTS = ("dsmc_query_sizes", "dsmc_init", "dsmc_step", "dsmc_sample_moments", "map_dsmc_to_lbm",
            "dsmc_project_moments", "map_lbm_to_dsmc", "lbm_step", "dsmc_lattice", "dsmc_read_status",
-           "dsmc_get_views", "dsmc_profile_enable", "dsmc_profile_read", "dsmc_destroy", "dsmc_strerror")
+           "dsmc_get_views", "dsmc_profile_enable", "dsmc_profile_read", "dsmc_destroy", "dsmc_strerror",
+           "lbm_step_checkpointed", "lbm_adjoint_workspace", "lbm_adjoint_step", "lbm_adjoint",
+           "lbm_hermite_moments", "lbm_hermite_moments_adjoint", "dsmc_project_moments_adjoint")
 
 
 class Config(ctypes.Structure):
@@ -77,6 +79,13 @@ def lib():
         L.dsmc_project_moments.argtypes = [c_p, c_i64, c_i32, c_d, c_i32, c_i32, c_p, c_p]
         L.map_lbm_to_dsmc.argtypes = [c_p, c_i32, c_i32, c_p, c_p, c_i32, c_p]
         L.lbm_step.argtypes = [P(LbmConfig), c_p, c_p, c_i32, c_p]
+        L.lbm_step_checkpointed.argtypes = [P(LbmConfig), c_p, c_p, c_p, c_i32, c_i32, c_p]
+        L.lbm_adjoint_workspace.argtypes = [P(LbmConfig), c_i32, P(c_sz)]
+        L.lbm_adjoint_step.argtypes = [P(LbmConfig), c_p, c_p, c_p, c_p, c_p, c_p]
+        L.lbm_adjoint.argtypes = [P(LbmConfig), c_p, c_i32, c_i32, c_p, c_p, c_p, c_p]
+        L.lbm_hermite_moments.argtypes = [c_i32, c_i32, c_p, c_i64, c_p, c_i32, c_p, c_p]
+        L.lbm_hermite_moments_adjoint.argtypes = [c_i32, c_i32, c_p, c_p, c_i32, c_p, c_i64, c_p]
+        L.dsmc_project_moments_adjoint.argtypes = [c_p, c_p, c_i64, c_i32, c_d, c_i32, c_i32, c_p, c_p]
         L.dsmc_lattice.argtypes = [c_i32, c_p, c_p, c_p]
         L.dsmc_read_status.argtypes = [c_p, P(Status), c_i32, c_p]
         L.dsmc_get_views.argtypes = [c_p, P(Views)]

@@ -3,6 +3,7 @@
 // every kernel is launched from the unit that defines it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -13,6 +14,7 @@
 #include "step_kernels.hpp"
 #include "step_kernels.hip"
 #include "map_kernels.hip"
+#include "adjoint_kernels.hip"
 
 using namespace dsmc;
 
@@ -148,6 +150,14 @@ bool make_lattice(int Q, Lattice &L)
     return true;
 }
 
+template <int Q>
+int first_of_shell(int s)
+{
+    for (int a = 0; a < Q; ++a)
+        if (VelSet<Q>::sh[a] == s) return a;
+    return 0;
+}
+
 struct LatticeTables {
     Lattice q9, q37;
     int e9[9][2], e37[37][2];
@@ -163,6 +173,14 @@ struct LatticeTables {
             e37[a][0] = (int)std::lround(q37.xi[a][0] / q37.r);
             e37[a][1] = (int)std::lround(q37.xi[a][1] / q37.r);
         }
+        // the lattice kernels' compile-time velocity sets and shell indices
+        // must describe these tables exactly
+        for (int a = 0; a < 9; ++a)
+            ok = ok && e9[a][0] == VelSet<9>::ex[a] && e9[a][1] == VelSet<9>::ey[a] &&
+                 q9.w[a] == q9.w[first_of_shell<9>(VelSet<9>::sh[a])];
+        for (int a = 0; a < 37; ++a)
+            ok = ok && e37[a][0] == VelSet<37>::ex[a] && e37[a][1] == VelSet<37>::ey[a] &&
+                 q37.w[a] == q37.w[first_of_shell<37>(VelSet<37>::sh[a])];
     }
 };
 
@@ -444,6 +462,123 @@ const Lattice *lattice_of(int q)
     if (q == 9) return &t.q9;
     if (q == 37) return &t.q37;
     return nullptr;
+}
+
+// Checks an lbm_config and fills the step arguments shared by the forward and
+// adjoint kernels (lattice, velocities, buffer depth K = max|e_y|).
+bool lbm_args(const lbm_config *cfg, LbmArgs &a)
+{
+    if (!cfg || cfg->nx < 1 || cfg->ny < 1) return false;
+    if ((int64_t)cfg->nx * cfg->ny >= ((int64_t)1 << 29)) return false;  // 32-bit byte offsets within a plane
+    const Lattice *L = lattice_of(cfg->lattice);
+    if (!L || !(cfg->tau > 0.5) || !std::isfinite(cfg->tau) || !std::isfinite(cfg->body_force_x)) return false;
+    if (cfg->y_mode != 0 && cfg->y_mode != 1) return false;
+    const LatticeTables &t = tables();
+    std::memset(&a, 0, sizeof(a));
+    a.L.Q = L->Q;
+    a.L.r = L->r;
+    int K = 0;
+    for (int q = 0; q < L->Q; ++q) {
+        const int ey = cfg->lattice == 9 ? t.e9[q][1] : t.e37[q][1];
+        a.L.ws[cfg->lattice == 9 ? VelSet<9>::sh[q] : VelSet<37>::sh[q]] = L->w[q];
+        if (std::abs(ey) > K) K = std::abs(ey);
+    }
+    a.nx = cfg->nx;
+    a.ny = cfg->ny;
+    a.y_mode = cfg->y_mode;
+    a.K = K;
+    a.tau = cfg->tau;
+    a.gx = cfg->body_force_x;
+    return true;
+}
+
+// launches the lattice step / its adjoint instance that fits the grid
+void launch_lbm(const LbmArgs &a, hipStream_t s)
+{
+    const size_t nn = (size_t)a.nx * a.ny;
+    const int R = a.L.Q == 9 ? 1 : 3;
+    const bool yb = a.y_mode == 1, narrow = a.nx < R || a.ny < R;
+#define DSMC_LBM(Q, YB, NW) k_lbm<Q, YB, NW><<<grid_threads(nn), 256, 0, s>>>(a)
+    if (a.L.Q == 9) {
+        if (yb) { if (narrow) DSMC_LBM(9, true, true); else DSMC_LBM(9, true, false); }
+        else { if (narrow) DSMC_LBM(9, false, true); else DSMC_LBM(9, false, false); }
+    } else {
+        if (yb) { if (narrow) DSMC_LBM(37, true, true); else DSMC_LBM(37, true, false); }
+        else { if (narrow) DSMC_LBM(37, false, true); else DSMC_LBM(37, false, false); }
+    }
+#undef DSMC_LBM
+}
+
+void launch_lbm_adjoint(const LbmAdjArgs &b, unsigned nblk, hipStream_t s)
+{
+    const int R = b.L.Q == 9 ? 1 : 3;
+    const bool yb = b.y_mode == 1, narrow = b.nx < R || b.ny < R;
+#define DSMC_ADJ(Q, YB, NW) k_lbm_adjoint<Q, YB, NW><<<nblk, 256, 0, s>>>(b)
+    if (b.L.Q == 9) {
+        if (yb) { if (narrow) DSMC_ADJ(9, true, true); else DSMC_ADJ(9, true, false); }
+        else { if (narrow) DSMC_ADJ(9, false, true); else DSMC_ADJ(9, false, false); }
+    } else {
+        if (yb) { if (narrow) DSMC_ADJ(37, true, true); else DSMC_ADJ(37, true, false); }
+        else { if (narrow) DSMC_ADJ(37, false, true); else DSMC_ADJ(37, false, false); }
+    }
+#undef DSMC_ADJ
+}
+
+LbmAdjArgs adj_args(const LbmArgs &a, const double *f, const double *lam_in, double *lam_out, double *partial,
+                    int accumulate)
+{
+    LbmAdjArgs b;
+    b.f = f;
+    b.lam_in = lam_in;
+    b.lam_out = lam_out;
+    b.partial = partial;
+    b.accumulate = accumulate;
+    b.L = a.L;
+    b.nx = a.nx;
+    b.ny = a.ny;
+    b.y_mode = a.y_mode;
+    b.K = a.K;
+    b.tau = a.tau;
+    b.gx = a.gx;
+    return b;
+}
+
+// Adjoint workspace: per-block partial sums, one cotangent buffer and the
+// every - 1 states recomputed inside a checkpoint segment.  every = 0: the
+// partial sums only (one adjoint step).
+struct AdjLayout {
+    size_t nblk, partial, lam, states, total;
+};
+
+AdjLayout adj_layout(const lbm_config *cfg, int Q, int32_t every)
+{
+    const size_t nn = (size_t)cfg->nx * cfg->ny, st = nn * (size_t)Q * sizeof(double);
+    AdjLayout W;
+    W.nblk = (nn + 255) / 256;
+    W.partial = 0;
+    W.lam = al(2 * W.nblk * sizeof(double));
+    if (every == 0) {
+        W.states = W.lam;
+        W.total = W.lam;
+        return W;
+    }
+    W.states = W.lam + al(st);
+    W.total = W.states + (size_t)(every - 1) * al(st);
+    return W;
+}
+
+HermiteArgs hermite_args(const Lattice &L, int order, const double *f, int64_t nnodes, const int32_t *nodes,
+                         int32_t nsel)
+{
+    HermiteArgs h;
+    std::memset(&h, 0, sizeof(h));
+    h.f = f;
+    h.nodes = nodes;
+    h.nnodes = nnodes;
+    h.nsel = nsel;
+    h.nh = (order + 1) * (order + 2) / 2;  // 1, 3, 6, 10 coefficients up to order 0..3
+    h.L = L;
+    return h;
 }
 
 }  // namespace
@@ -804,43 +939,147 @@ int map_lbm_to_dsmc(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f
 
 int lbm_step(const lbm_config *cfg, double *f, double *f_tmp, int32_t nsteps, void *stream)
 {
-    if (!cfg || !f || !f_tmp || nsteps < 0 || cfg->nx < 1 || cfg->ny < 1) return DSMC_EINVAL;
-    if ((int64_t)cfg->nx * cfg->ny > (int64_t)0x3FFFFFFF) return DSMC_EINVAL;
-    const Lattice *L = lattice_of(cfg->lattice);
-    if (!L || !(cfg->tau > 0.5) || !std::isfinite(cfg->tau) || !std::isfinite(cfg->body_force_x)) return DSMC_EINVAL;
-    if (cfg->y_mode != 0 && cfg->y_mode != 1) return DSMC_EINVAL;
-    const LatticeTables &t = tables();
+    return lbm_step_checkpointed(cfg, f, f_tmp, nullptr, nsteps, 1, stream);
+}
+
+int lbm_step_checkpointed(const lbm_config *cfg, double *f, double *f_tmp, double *ckpt, int32_t nsteps,
+                          int32_t every, void *stream)
+{
     LbmArgs a;
-    a.L = *L;
-    int K = 0;
-    for (int q = 0; q < L->Q; ++q) {
-        a.ex[q] = cfg->lattice == 9 ? t.e9[q][0] : t.e37[q][0];
-        a.ey[q] = cfg->lattice == 9 ? t.e9[q][1] : t.e37[q][1];
-        if (std::abs(a.ey[q]) > K) K = std::abs(a.ey[q]);
-    }
-    a.nx = cfg->nx;
-    a.ny = cfg->ny;
-    a.y_mode = cfg->y_mode;
-    a.K = K;
-    a.tau = cfg->tau;
-    a.gx = cfg->body_force_x;
+    if (!lbm_args(cfg, a) || !f || !f_tmp || nsteps < 0 || every < 1) return DSMC_EINVAL;
     hipStream_t s = S(stream);
-    const size_t nn = (size_t)cfg->nx * cfg->ny;
+    const size_t nn = (size_t)cfg->nx * cfg->ny, st = nn * (size_t)a.L.Q;
     double *src = f, *dst = f_tmp;
     for (int32_t it = 0; it < nsteps; ++it) {
         a.f = src;
         a.ft = dst;
-        k_lbm<<<grid_threads(nn), 256, 0, s>>>(a);
+        a.keep = (ckpt && it % every == 0) ? ckpt + (size_t)(it / every) * st : nullptr;
+        launch_lbm(a, s);
         if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
         double *t2 = src;
         src = dst;
         dst = t2;
     }
     if (src != f) {
-        if (hipMemcpyAsync(f, src, nn * (size_t)L->Q * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return DSMC_EHIP;
+        if (hipMemcpyAsync(f, src, st * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) return DSMC_EHIP;
     }
     return DSMC_OK;
+}
+
+int lbm_adjoint_workspace(const lbm_config *cfg, int32_t every, size_t *bytes)
+{
+    LbmArgs a;
+    if (!lbm_args(cfg, a) || every < 0 || !bytes) return DSMC_EINVAL;
+    *bytes = adj_layout(cfg, a.L.Q, every).total;
+    return DSMC_OK;
+}
+
+int lbm_adjoint_step(const lbm_config *cfg, const double *f_n, const double *lam_next, double *lam_out,
+                     double *grad, void *work, void *stream)
+{
+    LbmArgs a;
+    if (!lbm_args(cfg, a) || !f_n || !lam_next || !lam_out || !grad || !work) return DSMC_EINVAL;
+    if (lam_next == lam_out) return DSMC_EINVAL;
+    const AdjLayout W = adj_layout(cfg, a.L.Q, 0);
+    hipStream_t s = S(stream);
+    double *partial = (double *)((char *)work + W.partial);
+    LbmAdjArgs b = adj_args(a, f_n, lam_next, lam_out, partial, 0);
+    launch_lbm_adjoint(b, (unsigned)W.nblk, s);
+    k_adjoint_finish<<<1, 256, 0, s>>>(partial, (int)W.nblk, grad);
+    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
+int lbm_adjoint(const lbm_config *cfg, const double *ckpt, int32_t nsteps, int32_t every, double *lam,
+                double *grad, void *work, void *stream)
+{
+    LbmArgs a;
+    if (!lbm_args(cfg, a) || !ckpt || !lam || !grad || !work || nsteps < 0 || every < 1) return DSMC_EINVAL;
+    if (nsteps == 0) return DSMC_OK;
+    const AdjLayout W = adj_layout(cfg, a.L.Q, every);
+    hipStream_t s = S(stream);
+    const size_t nn = (size_t)cfg->nx * cfg->ny, st = nn * (size_t)a.L.Q;
+    double *partial = (double *)((char *)work + W.partial);
+    double *lam_tmp = (double *)((char *)work + W.lam);
+    double *states = (double *)((char *)work + W.states);
+    double *cur = lam, *other = lam_tmp;
+    bool first = true;
+    const int32_t nseg = (nsteps + every - 1) / every;
+    for (int32_t k = nseg - 1; k >= 0; --k) {
+        const int32_t s0 = k * every;
+        const int32_t len = std::min(every, nsteps - s0);
+        const double *base = ckpt + (size_t)k * st;
+        // recompute the segment's states f_{s0+1} .. f_{s0+len-1}
+        a.keep = nullptr;
+        for (int32_t i = 1; i < len; ++i) {
+            a.f = i == 1 ? base : states + (size_t)(i - 2) * st;
+            a.ft = states + (size_t)(i - 1) * st;
+            launch_lbm(a, s);
+        }
+        for (int32_t i = len - 1; i >= 0; --i) {
+            const double *fn = i == 0 ? base : states + (size_t)(i - 1) * st;
+            LbmAdjArgs b = adj_args(a, fn, cur, other, partial, first ? 0 : 1);
+            launch_lbm_adjoint(b, (unsigned)W.nblk, s);
+            first = false;
+            double *t2 = cur;
+            cur = other;
+            other = t2;
+        }
+        if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
+    }
+    k_adjoint_finish<<<1, 256, 0, s>>>(partial, (int)W.nblk, grad);
+    if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
+    if (cur != lam) {
+        if (hipMemcpyAsync(lam, cur, st * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) return DSMC_EHIP;
+    }
+    return DSMC_OK;
+}
+
+int lbm_hermite_moments(int32_t lattice, int32_t order, const double *f, int64_t nnodes, const int32_t *nodes,
+                        int32_t nsel, double *a_out, void *stream)
+{
+    const Lattice *L = lattice_of(lattice);
+    if (!L || order < 0 || order > 3 || nnodes < 1 || nsel < 0) return DSMC_EINVAL;
+    if (nsel == 0) return DSMC_OK;
+    if (!f || !nodes || !a_out) return DSMC_EINVAL;
+    HermiteArgs h = hermite_args(*L, order, f, nnodes, nodes, nsel);
+    h.a = a_out;
+    k_hermite_moments<<<grid_threads((size_t)nsel), 256, 0, S(stream)>>>(h);
+    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
+int lbm_hermite_moments_adjoint(int32_t lattice, int32_t order, const double *a_bar, const int32_t *nodes,
+                                int32_t nsel, double *f_bar, int64_t nnodes, void *stream)
+{
+    const Lattice *L = lattice_of(lattice);
+    if (!L || order < 0 || order > 3 || nnodes < 1 || nsel < 0) return DSMC_EINVAL;
+    if (nsel == 0) return DSMC_OK;
+    if (!a_bar || !nodes || !f_bar) return DSMC_EINVAL;
+    HermiteArgs h = hermite_args(*L, order, nullptr, nnodes, nodes, nsel);
+    h.a_bar = a_bar;
+    h.f_bar = f_bar;
+    k_hermite_moments_adjoint<<<grid_threads((size_t)nsel), 256, 0, S(stream)>>>(h);
+    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
+int dsmc_project_moments_adjoint(const double *f_bar, const double *avg, int64_t ncells, int32_t ppc,
+                                 double kT_over_m, int32_t lattice, int32_t order, double *avg_bar, void *stream)
+{
+    const Lattice *L = lattice_of(lattice);
+    if (!L || order < 0 || order > 3 || ncells < 0 || ncells > (int64_t)0x3FFFFFFF || ppc < 1) return DSMC_EINVAL;
+    if (!(kT_over_m > 0.0) || !std::isfinite(kT_over_m)) return DSMC_EINVAL;
+    if (ncells == 0) return DSMC_OK;
+    if (!f_bar || !avg || !avg_bar) return DSMC_EINVAL;
+    ProjectAdjArgs p;
+    p.f_bar = f_bar;
+    p.avg = avg;
+    p.avg_bar = avg_bar;
+    p.L = *L;
+    p.ncells = (int)ncells;
+    p.ppc = ppc;
+    p.order = order;
+    p.s1 = std::sqrt(kT_over_m);
+    k_project_adjoint<<<grid_threads((size_t)ncells), 256, 0, S(stream)>>>(p);
+    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
 }
 
 int dsmc_read_status(dsmc_ctx *x, dsmc_status *out, int32_t clear, void *stream)

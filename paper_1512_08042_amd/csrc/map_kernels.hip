@@ -336,65 +336,126 @@ __global__ __launch_bounds__(256) void k_reseed_unmark(ReseedArgs a)
 }
 
 // ---- BGK lattice step (Section 3.1), one thread per node, push streaming ----
-template <int Q>
+// periodic index in [0, n) for any shift (grids narrower than the velocities too)
+__device__ __forceinline__ int wrap_index(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// The node's neighbour columns and rows for offsets -R..R: wrapped column
+// index, start of the row (row * nx) and whether the row keeps what streams
+// into it.  YB (y_mode 1): only interior rows keep anything; rows beyond the
+// grid are clamped to it so that an address formed from them stays in bounds.
+// NARROW: the grid is narrower than R in x or y and needs a full modulo.
+template <int R>
+struct Nbr {
+    int col[2 * R + 1];
+    int row[2 * R + 1];
+    bool in[2 * R + 1];
+};
+
+template <int R, bool YB, bool NARROW>
+__device__ __forceinline__ void neighbours(int ix, int iy, int nx, int ny, int K, Nbr<R> &n)
+{
+#pragma unroll
+    for (int d = -R; d <= R; ++d) {
+        int c = ix + d;
+        if (NARROW) {
+            c = wrap_index(c, nx);
+        } else {
+            c += c < 0 ? nx : 0;
+            c -= c >= nx ? nx : 0;
+        }
+        n.col[d + R] = c;
+        int y = iy + d;
+        if (YB) {
+            n.in[d + R] = y >= K && y < ny - K;
+            y = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+        } else {
+            n.in[d + R] = true;
+            if (NARROW) {
+                y = wrap_index(y, ny);
+            } else {
+                y += y < 0 ? ny : 0;
+                y -= y >= ny ? ny : 0;
+            }
+        }
+        n.row[d + R] = y * nx;
+    }
+}
+
+template <int Q, bool YB, bool NARROW>
 __device__ __forceinline__ void lbm_node(const LbmArgs &a, int node)
 {
+    using V = VelSet<Q>;
+    constexpr int R = V::R;
     const int nx = a.nx, ny = a.ny;
     const size_t nn = (size_t)nx * ny;
     const int ix = node % nx, iy = node / nx;
-    const bool buffer = (a.y_mode == 1) && (iy < a.K || iy >= ny - a.K);
+    const bool buffer = YB && (iy < a.K || iy >= ny - a.K);
+    const double r = a.L.r;
     double fe[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) fe[q] = a.f[(size_t)q * nn + node];
-    if (buffer) {
+    for (int q = 0; q < Q; ++q) fe[q] = *plane_ptr(a.f, nn, q, (uint32_t)node);
+    if (a.keep) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) a.ft[(size_t)q * nn + node] = fe[q];
-    } else {
+        for (int q = 0; q < Q; ++q) *plane_ptr(a.keep, nn, q, (uint32_t)node) = fe[q];
+    }
+    if (!buffer) {
         double rho = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             rho += fe[q];
-            jx += fe[q] * a.L.xi[q][0];
-            jy += fe[q] * a.L.xi[q][1];
+            jx += fe[q] * (r * (double)V::ex[q]);
+            jy += fe[q] * (r * (double)V::ey[q]);
         }
-        const double gx = a.gx, tau = a.tau;
-        const double ux = (jx + 0.5 * rho * gx) / rho;
-        const double uy = jy / rho;
+        const double gx = a.gx, itau = 1.0 / a.tau;
+        const double cf = 1.0 - 0.5 * itau;
+        const double irho = 1.0 / rho;
+        const double ux = (jx + 0.5 * rho * gx) * irho;
+        const double uy = jy * irho;
         const double uu = ux * ux + uy * uy;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const double cu = a.L.xi[q][0] * ux + a.L.xi[q][1] * uy;
+            const double x = r * (double)V::ex[q], y = r * (double)V::ey[q], w = a.L.ws[V::sh[q]];
+            const double cu = x * ux + y * uy;
             double eq = 1.0 + cu + 0.5 * (cu * cu - uu);
-            if (Q != 9) eq += (cu * (cu * cu - 3.0 * uu)) / 6.0;
-            const double feq = a.L.w[q] * rho * eq;
-            const double cg = a.L.xi[q][0] * gx;
-            const double F = (1.0 - 0.5 / tau) * a.L.w[q] * rho * (cg + cg * cu - gx * ux);
+            if (Q != 9) eq += (cu * (cu * cu - 3.0 * uu)) * (1.0 / 6.0);
+            const double feq = w * rho * eq;
+            const double cg = x * gx;
+            const double F = cf * w * rho * (cg + cg * cu - gx * ux);
             const double fa = fe[q];
-            fe[q] = fa - (fa - feq) / tau + F;
+            fe[q] = fa - (fa - feq) * itau + F;
         }
     }
+    // buffer rows keep their populations (written back unchanged) and send
+    // them on; nothing streamed into a buffer row is kept
+    Nbr<R> nb;
+    neighbours<R, YB, NARROW>(ix, iy, nx, ny, a.K, nb);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        int jx2 = ix + a.ex[q];
-        int jy2 = iy + a.ey[q];
-        jx2 = ((jx2 % nx) + nx) % nx;
-        if (a.y_mode == 1) {
-            if (jy2 < a.K || jy2 >= ny - a.K) continue;
-        } else {
-            jy2 = ((jy2 % ny) + ny) % ny;
-        }
-        a.ft[(size_t)q * nn + (size_t)jy2 * nx + jx2] = fe[q];
+        if (YB && buffer) *plane_ptr(a.ft, nn, q, (uint32_t)node) = fe[q];
+        if (!YB || nb.in[V::ey[q] + R])
+            *plane_ptr(a.ft, nn, q, (uint32_t)(nb.row[V::ey[q] + R] + nb.col[V::ex[q] + R])) = fe[q];
     }
 }
 
+template <int Q, bool YB, bool NARROW>
 __global__ __launch_bounds__(256) void k_lbm(LbmArgs a)
 {
     const int node = blockIdx.x * 256 + threadIdx.x;
     if (node >= a.nx * a.ny) return;
-    if (a.L.Q == 9)
-        lbm_node<9>(a, node);
-    else
-        lbm_node<37>(a, node);
+    lbm_node<Q, YB, NARROW>(a, node);
 }
+
+#define DSMC_LBM_INSTANCES(Q)                                          \
+    template __global__ void k_lbm<Q, false, false>(LbmArgs);          \
+    template __global__ void k_lbm<Q, false, true>(LbmArgs);           \
+    template __global__ void k_lbm<Q, true, false>(LbmArgs);           \
+    template __global__ void k_lbm<Q, true, true>(LbmArgs);
+DSMC_LBM_INSTANCES(9)
+DSMC_LBM_INSTANCES(37)
+#undef DSMC_LBM_INSTANCES
 
 }  // namespace dsmc

@@ -163,13 +163,86 @@ struct ReseedArgs {
     uint32_t k0, k1, event;
 };
 
+// Velocity sets in the ABI order (shells of increasing |e|, counter-clockwise
+// within a shell from the first-octant representative) as compile-time
+// tables, so the lattice kernels keep only the scale r and one weight per
+// shell in registers; the host checks them against its lattice tables.
+template <int Q>
+struct VelSet;
+template <>
+struct VelSet<9> {
+    static constexpr int R = 1;  // largest |e| component
+    static constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static constexpr int sh[9] = {0, 1, 1, 1, 1, 2, 2, 2, 2};
+};
+template <>
+struct VelSet<37> {
+    static constexpr int R = 3;
+    static constexpr int ex[37] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0, 2, 1, -1, -2, -2, -1, 1, 2,
+                                   2, -2, -2, 2, 3, 0, -3, 0, 3, 1, -1, -3, -3, -1, 1, 3};
+    static constexpr int ey[37] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2, 1, 2, 2, 1, -1, -2, -2, -1,
+                                   2, 2, -2, -2, 0, 3, 0, -3, 1, 3, 3, 1, -1, -3, -3, -1};
+    static constexpr int sh[37] = {0, 1, 1, 1, 1, 2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4, 4, 4,
+                                   5, 5, 5, 5, 6, 6, 6, 6, 7, 7, 7, 7, 7, 7, 7, 7};
+};
+
+// Element i of plane q of a [Q][nn] array, addressed as a uniform plane base
+// plus a 32-bit byte offset (the host keeps nn * 8 below 2^32), so the loads
+// and stores take one 32-bit register per lane instead of a 64-bit address.
+__device__ __forceinline__ const double *plane_ptr(const double *base, size_t nn, int q, uint32_t i)
+{
+    return (const double *)((const char *)(base + (size_t)q * nn) + (size_t)(uint32_t)(i * 8u));
+}
+__device__ __forceinline__ double *plane_ptr(double *base, size_t nn, int q, uint32_t i)
+{
+    return (double *)((char *)(base + (size_t)q * nn) + (size_t)(uint32_t)(i * 8u));
+}
+
+struct LatShells {
+    int Q;         // 9 or 37
+    double r;      // xi_q = r e_q
+    double ws[8];  // weight of each shell
+};
+
 struct LbmArgs {
     const double *f;
     double *ft;
-    Lattice L;
-    int ex[37], ey[37];
+    double *keep;  // when not null, also receives f (a checkpoint of the step's input)
+    LatShells L;
     int nx, ny, y_mode, K;
     double tau, gx;
+};
+
+struct LbmAdjArgs {
+    const double *f;       // populations entering the step [Q][nx*ny]
+    const double *lam_in;  // cotangent of the step's output
+    double *lam_out;       // cotangent of its input
+    double *partial;       // [gridDim.x][2]: per-block (dJ/dg, dJ/dtau)
+    int accumulate;        // add to partial (else overwrite)
+    LatShells L;
+    int nx, ny, y_mode, K;
+    double tau, gx;
+};
+
+struct HermiteArgs {
+    const double *f;      // [Q][nnodes]
+    const int32_t *nodes; // [nsel]
+    double *a;            // [nh][nsel]
+    const double *a_bar;  // [nh][nsel]
+    double *f_bar;        // [Q][nnodes]
+    int64_t nnodes;
+    int nsel, nh;
+    Lattice L;
+};
+
+struct ProjectAdjArgs {
+    const double *f_bar;  // [Q][ncells]
+    const double *avg;    // [11][ncells]
+    double *avg_bar;      // [11][ncells]
+    Lattice L;
+    int ncells, ppc, order;
+    double s1;            // sqrt(kT/m)
 };
 
 // TC cells per tile (one wave); tiles of up to 64*CH particles are staged in
@@ -208,6 +281,15 @@ __global__ void k_reseed_copy(ReseedArgs a);
 template <class S>
 __global__ void k_reseed_gen(ReseedArgs a);
 __global__ void k_reseed_unmark(ReseedArgs a);
+// lattice step and its adjoint for Q velocities; YB: y_mode 1 (buffer rows);
+// NARROW: the grid is narrower than the largest velocity component
+template <int Q, bool YB, bool NARROW>
 __global__ void k_lbm(LbmArgs a);
+template <int Q, bool YB, bool NARROW>
+__global__ void k_lbm_adjoint(LbmAdjArgs a);
+__global__ void k_adjoint_finish(const double *partial, int nblk, double *grad);
+__global__ void k_hermite_moments(HermiteArgs a);
+__global__ void k_hermite_moments_adjoint(HermiteArgs a);
+__global__ void k_project_adjoint(ProjectAdjArgs a);
 
 }  // namespace dsmc

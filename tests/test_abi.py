@@ -83,3 +83,34 @@ def test_state_precision_sizes():
     assert s32.workspace_bytes == s64.workspace_bytes
     c.state_bits = 16
     assert L.dsmc_query_sizes(ctypes.byref(c), ctypes.byref(s32)) == _lib.EINVAL
+
+
+def test_adjoint_entries_validate_without_gpu():
+    L = _lib.lib()
+    cfg = _lib.LbmConfig(100, 30, 37, 1, 0.8, 1e-3)
+    size = ctypes.c_size_t()
+    assert L.lbm_adjoint_workspace(ctypes.byref(cfg), 20, ctypes.byref(size)) == 0
+    al = lambda x: (x + 255) // 256 * 256
+    nblk = (3000 + 255) // 256
+    state = al(37 * 3000 * 8)
+    assert size.value == al(2 * nblk * 8) + state + 19 * state
+    assert L.lbm_adjoint_workspace(ctypes.byref(cfg), 0, ctypes.byref(size)) == 0
+    assert size.value == al(2 * nblk * 8)
+    assert L.lbm_adjoint_workspace(ctypes.byref(cfg), -1, ctypes.byref(size)) == _lib.EINVAL
+    bad = _lib.LbmConfig(100, 30, 37, 1, 0.5, 1e-3)  # tau must exceed 1/2
+    assert L.lbm_adjoint_workspace(ctypes.byref(bad), 20, ctypes.byref(size)) == _lib.EINVAL
+    big = _lib.LbmConfig(1 << 15, 1 << 14, 9, 0, 0.8, 0.0)  # 2^29 nodes: beyond 32-bit plane offsets
+    assert L.lbm_adjoint_workspace(ctypes.byref(big), 1, ctypes.byref(size)) == _lib.EINVAL
+    p = ctypes.c_void_p(256)  # never dereferenced: these calls return before any GPU work
+    assert L.lbm_adjoint(ctypes.byref(cfg), p, 0, 20, p, p, p, None) == 0  # zero steps: nothing to do
+    assert L.lbm_adjoint(ctypes.byref(cfg), None, 5, 20, p, p, p, None) == _lib.EINVAL
+    assert L.lbm_adjoint(ctypes.byref(cfg), p, 5, 0, p, p, p, None) == _lib.EINVAL
+    assert L.lbm_adjoint_step(ctypes.byref(cfg), p, p, p, p, p, None) == _lib.EINVAL  # lam_out aliases lam_next
+    assert L.lbm_step_checkpointed(ctypes.byref(cfg), p, p, None, 3, 0, None) == _lib.EINVAL
+    assert L.lbm_hermite_moments(37, 3, p, 3000, p, 0, p, None) == 0
+    assert L.lbm_hermite_moments(37, 4, p, 3000, p, 5, p, None) == _lib.EINVAL
+    assert L.lbm_hermite_moments(10, 2, p, 3000, p, 5, p, None) == _lib.EINVAL
+    assert L.lbm_hermite_moments_adjoint(9, 2, None, p, 5, p, 3000, None) == _lib.EINVAL
+    assert L.dsmc_project_moments_adjoint(p, p, 0, 100, 1.0, 37, 3, p, None) == 0
+    assert L.dsmc_project_moments_adjoint(p, p, 10, 0, 1.0, 37, 3, p, None) == _lib.EINVAL
+    assert L.dsmc_project_moments_adjoint(p, p, 10, 100, -1.0, 37, 3, p, None) == _lib.EINVAL
