@@ -22,6 +22,14 @@ Printed JSON line: metric, value, ..., plus
             sources are unchanged since it was made, else null;
   cpu_baseline: the FP64 oracle timed on this host on one cycle of the same
             workload (single-threaded);
+  adjoint:  the gradient of the coupling-node moment mismatch with respect to
+            the body force and the relaxation time (and to the initial
+            populations and the DSMC moment averages) on a D2Q37 1024 x 512
+            lattice with the 32 rows at each wall coupled to DSMC strips of
+            100 particles per cell (Kn 0.1, 200 steps, checkpoints every 20):
+            time per gradient, the adjoint and forward lattice kernels against
+            the HBM roofline, and the gradient against central differences of
+            the library's own forward;
   precision: the FP32-state form against plain FP64 on a 2048 x 1024 x 50
             channel (Kn 0.02, Ma 0.1): particle-steps/s of each, and per
             moment order the RMS and mean over cells of z = (m32 - m64) / SE,
@@ -35,6 +43,7 @@ from __future__ import annotations
 
 import argparse
 import csv
+import ctypes
 import glob
 import hashlib
 import json
@@ -64,13 +73,22 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_512x256x100_fp64_traffi
 TRACE_SUMMARY = os.path.join(ROOT, "profiles", "dsmc_cycle_512x256x100_fp64_kernel_trace.md")
 # the commands whose output the summaries condense (run from the repository root)
 TRACE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace -o trace -- "
-             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-precision")
+             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-precision --no-adjoint")
 PMC_CMDS = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --copy-calibration",
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --copy-calibration",
             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --copy-calibration")
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --copy-calibration")
 # kernel-name prefixes of the library's kernels, by profiling id
 KERNEL_PREFIX = {"step": "void dsmc::k_step<", "classify": "void dsmc::k_classify<"}
+ADJ_TRACE_SUMMARY = os.path.join(ROOT, "profiles", "lbm_adjoint_1024x512_d2q37_kernel_trace.md")
+ADJ_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "lbm_adjoint_1024x512_d2q37_traffic.md")
+ADJ_TRACE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/adj_trace -o trace -- "
+                 "python3 bench.py --adjoint-only")
+ADJ_PMC_CMDS = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/adj_fetch -o fetch -- "
+                "python3 bench.py --adjoint-only --copy-calibration",
+                "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/adj_write -o write -- "
+                "python3 bench.py --adjoint-only --copy-calibration")
+ADJ_KERNEL_PREFIX = {"lbm_adjoint": "void dsmc::k_lbm_adjoint<", "lbm_step": "void dsmc::k_lbm<"}
 
 
 # the precision workload (FP32 state vs FP64)
@@ -146,6 +164,142 @@ def precision_comparison():
     return out
 
 
+# the differentiation workload: D2Q37 lattice 1024 x 512 (edge rows held), Kn
+# 0.1 on its 512 rows, Ma 0.1; DSMC strips 32 cells thick at both walls, 100
+# particles per cell, stood in for by one 1024 x 64 DSMC channel with the same
+# mean free path (rows 0..31 face the lower wall, rows 32..63 the upper one)
+ADJ = dict(nx=1024, ny=512, strip=32, ppc=100, kn=0.1, mach=0.1, seed=5, steps=200, every=20,
+           dsmc_warm=20, dsmc_sampled=50)
+
+
+def adjoint_benchmark(reps=3):
+    """Times the mismatch gradient of the differentiation workload and
+    checks it against central differences of the forward."""
+    import numpy as np
+    import torch
+
+    from paper_1512_08042_amd import ChannelConfig, bgk_tau, body_force
+    from paper_1512_08042_amd import _lib, lbm
+    from paper_1512_08042_amd import dsmc as D
+
+    A = ADJ
+    nx, ny, q, S = A["nx"], A["ny"], 37, A["strip"]
+    nn = nx * ny
+    g_acc = body_force(A["kn"], ny, A["mach"])
+    lam_cells = A["kn"] * ny
+    ch = D.Channel(ChannelConfig(nx=nx, ny=2 * S, ppc=A["ppc"], kn=lam_cells / (2 * S), body_force_x=g_acc,
+                                 seed=A["seed"]))
+    ch.step(A["dsmc_warm"])
+    ch.reset_moments()
+    ch.step(A["dsmc_sampled"], sample_every=1)
+    avg = ch.sample_moments().contiguous()
+    nparticles = ch.status()["n"]
+    del ch
+    rows = np.r_[0:S, ny - S:ny]
+    nodes = torch.tensor((rows[:, None] * nx + np.arange(nx)[None, :]).ravel(), dtype=torch.int32, device="cuda")
+    cells = torch.arange(2 * S * nx, dtype=torch.int32, device="cuda")
+    e, w, r = D.lattice(q)
+    tau = bgk_tau(A["kn"], ny, r)
+    g = g_acc / r
+    # Poiseuille start: third-order equilibrium of u_x = 4 U y (H - y) / H^2, U = Ma
+    yv = (torch.arange(ny, dtype=torch.float64, device="cuda") + 0.5) / ny
+    ux = (4.0 * A["mach"] * yv * (1 - yv)).repeat_interleave(nx)
+    xi_x = torch.tensor(r * e[:, 0], dtype=torch.float64, device="cuda")[:, None]
+    cu = xi_x * ux[None, :]
+    wt = torch.tensor(w, dtype=torch.float64, device="cuda")[:, None]
+    f0 = (wt * (1 + cu + 0.5 * (cu * cu - ux * ux) + cu * (cu * cu - 3 * ux * ux) / 6)).contiguous()
+
+    def gradient():
+        m = avg.clone().requires_grad_(True)
+        f = f0.clone().requires_grad_(True)
+        g_t = torch.tensor(g, dtype=torch.float64, device="cuda", requires_grad=True)
+        t_t = torch.tensor(tau, dtype=torch.float64, device="cuda", requires_grad=True)
+        fD = lbm.project_moments(m, A["ppc"], q, 3)
+        fN = lbm.rollout(f, g_t, t_t, nx, ny, q, 1, A["steps"], A["every"])
+        J = lbm.coupling_mismatch(fN, nodes, fD, cells, q, 3)
+        J.backward()
+        return float(J.detach()), float(g_t.grad), float(t_t.grad)
+
+    def J_only(gv, tv):
+        with torch.no_grad():
+            fD = lbm.project_moments(avg, A["ppc"], q, 3)
+            fN = lbm.rollout(f0, gv, tv, nx, ny, q, 1, A["steps"], A["every"])
+            return float(lbm.coupling_mismatch(fN, nodes, fD, cells, q, 3))
+
+    res = gradient()  # warm-up
+    times, ftimes = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = gradient()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        J_only(g, tau)
+        torch.cuda.synchronize()
+        ftimes.append(time.perf_counter() - t0)
+    J, dg, dtau = res
+    hg, ht = 1e-4 * g, 1e-4 * tau
+    fd_g = (J_only(g + hg, tau) - J_only(g - hg, tau)) / (2 * hg)
+    fd_t = (J_only(g, tau + ht) - J_only(g, tau - ht)) / (2 * ht)
+
+    # the two lattice kernels alone, HIP events on the launch stream
+    L = _lib.lib()
+    cfg = _lib.LbmConfig(nx, ny, q, 1, tau, g)
+    s = torch.cuda.current_stream()
+    fa, fb = f0.clone(), torch.empty_like(f0)
+    lam_a = torch.randn_like(f0)
+    # the adjoint kernel alone: a 20-step reverse pass with a checkpoint at
+    # every step (nothing recomputed), one finishing reduction per 20 steps
+    NADJ = 20
+    ckpt = f0.unsqueeze(0).repeat(NADJ, 1, 1).contiguous()
+    size = ctypes.c_size_t()
+    _lib.check(L.lbm_adjoint_workspace(ctypes.byref(cfg), 1, ctypes.byref(size)), "lbm_adjoint_workspace")
+    work = torch.empty(size.value, dtype=torch.uint8, device="cuda")
+    grad = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+    def timed(fn, n=50):
+        for _ in range(3):
+            fn()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(s)
+        for _ in range(n):
+            fn()
+        ev1.record(s)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) * 1e3 / n
+
+    # two steps per call: the result lands back in f without a copy
+    us_fwd = timed(lambda: L.lbm_step(ctypes.byref(cfg), fa.data_ptr(), fb.data_ptr(), 2, s.cuda_stream)) / 2
+    us_adj = timed(lambda: L.lbm_adjoint(ctypes.byref(cfg), ckpt.data_ptr(), NADJ, 1, lam_a.data_ptr(),
+                                         grad.data_ptr(), work.data_ptr(), s.cuda_stream), n=10) / NADJ
+    us_copy = timed(lambda: fb.copy_(fa))
+    us_fwd_kernel = us_fwd
+    adj_bytes, fwd_bytes = 24.0 * q * nn, 16.0 * q * nn
+    med = sorted(times)[len(times) // 2]
+    fmed = sorted(ftimes)[len(ftimes) // 2]
+    achieved = adj_bytes / (us_adj * 1e-6) / 1e9
+    return {
+        "workload": "D2Q37 BGK 1024x512 (3 edge rows held), tau of Eq. (tau) at Kn 0.1 on 512 rows = %.3f, "
+                    "g for Ma 0.1; J = 1/2 sum over the 32 rows at each wall (65,536 nodes) of the squared "
+                    "mismatch of the ten Hermite coefficients to third order between the lattice after %d steps "
+                    "and the D2Q37 projection of DSMC averages (1024x64 DSMC cells, 100 particles/cell, "
+                    "%d particles, %d sampled steps); checkpoints every %d steps"
+                    % (tau, A["steps"], nparticles, A["dsmc_sampled"], A["every"]),
+        "ms_per_gradient": round(1e3 * med, 3),
+        "ms_forward_only": round(1e3 * fmed, 3),
+        "gradient_node_steps_per_s": nn * A["steps"] / med,
+        "J": J, "dJ_dg": dg, "dJ_dtau": dtau,
+        "fd_rel_err": {"g": abs(dg - fd_g) / abs(fd_g), "tau": abs(dtau - fd_t) / abs(fd_t)},
+        "kernels_us_per_launch": {"lbm_adjoint": round(us_adj, 2), "lbm_step": round(us_fwd_kernel, 2)},
+        "roofline": {"bound": "hbm", "kernel": "k_lbm_adjoint", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": stored_traffic("lbm_adjoint", ADJ_TRAFFIC_SUMMARY), "bytes_per_launch": adj_bytes,
+                     "forward_kernel_GBps": round(fwd_bytes / (us_fwd_kernel * 1e-6) / 1e9, 1),
+                     "copy_GBps": round(2 * 8.0 * q * nn / (us_copy * 1e-6) / 1e9, 1)},
+    }
+
+
 def source_hash() -> str:
     """sha256 over the library's kernel sources and its C header."""
     h = hashlib.sha256()
@@ -159,11 +313,11 @@ def source_hash() -> str:
     return h.hexdigest()
 
 
-def stored_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when the summary is missing or the sources changed since."""
+def stored_traffic(kernel: str, summary: str = TRAFFIC_SUMMARY):
+    """HBM bytes per launch of `kernel` from a committed counter summary, or
+    None when the summary is missing or the sources changed since."""
     try:
-        with open(TRAFFIC_SUMMARY) as fh:
+        with open(summary) as fh:
             lines = fh.read().splitlines()
     except OSError:
         return None
@@ -181,15 +335,32 @@ def _counter_rows(path):
         return list(csv.DictReader(fh))
 
 
-def summarize(trace_dir, fetch_dir, write_dir):
-    """Writes the two summaries under profiles/ from rocprofv3 output."""
-    # kernel trace statistics
+# what each summary covers: title, the commands, the kernels reported per
+# profiling id (name prefixes), and the files under profiles/
+SUMMARIES = {
+    "cycle": dict(
+        title="coupling cycle, 512x256 cells x 100 particles/cell, FP64",
+        trace_cmd=TRACE_CMD, pmc_cmds=PMC_CMDS, prefixes=KERNEL_PREFIX,
+        trace_file=TRACE_SUMMARY, traffic_file=TRAFFIC_SUMMARY,
+        note=["Each bench cycle: 10 DSMC steps (k_classify once, then cell kernels + k_step per step), the D2Q37",
+              "projection, one BGK step and the strip reseed.  Timed and profiled cycles both appear."]),
+    "adjoint": dict(
+        title="mismatch gradient, D2Q37 1024x512, 200 steps, checkpoints every 20",
+        trace_cmd=ADJ_TRACE_CMD, pmc_cmds=ADJ_PMC_CMDS, prefixes=ADJ_KERNEL_PREFIX,
+        trace_file=ADJ_TRACE_SUMMARY, traffic_file=ADJ_TRAFFIC_SUMMARY,
+        note=["Each gradient: the DSMC2LB projection, 200 forward steps (every 20th keeps a checkpoint), the",
+              "Hermite coefficients and their adjoint, then per 20-step segment 19 recomputed forward steps and",
+              "20 adjoint steps; the bench also times the two lattice kernels alone and runs central differences."]),
+}
+
+
+def summarize(which, trace_dir, fetch_dir, write_dir):
+    """Writes the two summaries of one workload under profiles/ from rocprofv3 output."""
+    W = SUMMARIES[which]
     stats = _counter_rows(glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))[0])
-    out = ["# Kernel trace: coupling cycle, 512x256 cells x 100 particles/cell, FP64", "",
-           "Command (from the repository root, on one MI355X):", "", "    " + TRACE_CMD, "",
-           "Each bench cycle: 10 DSMC steps (k_classify once, then cell kernels + k_step per step), the D2Q37",
-           "projection, one BGK step and the strip reseed.  Timed and profiled cycles both appear.", "",
-           "| kernel | calls | mean us | total % |", "|---|---|---|---|"]
+    out = ["# Kernel trace: " + W["title"], "",
+           "Command (from the repository root, on one MI355X):", "", "    " + W["trace_cmd"], ""] + W["note"] + [
+           "", "| kernel | calls | mean us | total % |", "|---|---|---|---|"]
     for r in stats:
         name = r["Name"]
         if "dsmc::" not in name and "copyBuffer" not in name:
@@ -197,15 +368,14 @@ def summarize(trace_dir, fetch_dir, write_dir):
         out.append("| `%s` | %s | %.1f | %s |" % (name.replace("|", "/"), r["Calls"], float(r["AverageNs"]) / 1e3,
                                                  r["Percentage"]))
     out.append("")
-    out.append("Mean duration per profiling id (all template variants, weighted by calls), the figure bench.py's")
-    out.append("HIP-event timing reports as kernels_us_per_launch:")
+    out.append("Mean duration per profiling id (all template variants, weighted by calls):")
     out.append("")
-    for kid, pre in sorted(KERNEL_PREFIX.items()):
+    for kid, pre in sorted(W["prefixes"].items()):
         calls = [(float(r["Calls"]), float(r["AverageNs"])) for r in stats if r["Name"].startswith(pre)]
         if calls:
             n = sum(c for c, _ in calls)
             out.append("mean_us %s: %.1f" % (kid, sum(c * a for c, a in calls) / n / 1e3))
-    with open(TRACE_SUMMARY, "w") as fh:
+    with open(W["trace_file"], "w") as fh:
         fh.write("\n".join(out) + "\n")
 
     # HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), calibrated on
@@ -222,9 +392,9 @@ def summarize(trace_dir, fetch_dir, write_dir):
     cw = [v for v in write.get("__amd_rocclr_copyBuffer", []) if v > 0.5 * gib_kib]
     f_fetch = gib_kib / (sum(cf) / len(cf))
     f_write = gib_kib / (sum(cw) / len(cw))
-    out = ["# HBM traffic per launch: coupling cycle, 512x256 cells x 100 particles/cell, FP64", "",
+    out = ["# HBM traffic per launch: " + W["title"], "",
            "Commands (from the repository root, on one MI355X), one counter per run:", "",
-           "    " + PMC_CMDS[0], "    " + PMC_CMDS[1], "",
+           "    " + W["pmc_cmds"][0], "    " + W["pmc_cmds"][1], "",
            "Calibration: a 1 GiB device-to-device copy reads FETCH_SIZE = %.0f KiB and WRITE_SIZE = %.0f KiB, so"
            % (gib_kib / f_fetch, gib_kib / f_write),
            "bytes = %.3f x FETCH_SIZE + %.3f x WRITE_SIZE (KiB -> bytes x 1024)." % (f_fetch, f_write), "",
@@ -237,7 +407,7 @@ def summarize(trace_dir, fetch_dir, write_dir):
         mw = sum(write[name]) / len(write[name])
         mb = (mf * f_fetch + mw * f_write) * 1024 / 1e6
         out.append("| `%s` | %d | %.0f | %.0f | %.1f |" % (name, len(fetch[name]), mf, mw, mb))
-        for kid, pre in KERNEL_PREFIX.items():
+        for kid, pre in W["prefixes"].items():
             if name.startswith(pre):
                 per_id.setdefault(kid, []).extend(
                     [(a * f_fetch + b * f_write) * 1024 for a, b in zip(fetch[name], write[name])])
@@ -248,9 +418,9 @@ def summarize(trace_dir, fetch_dir, write_dir):
         out.append("traffic_bytes_per_launch %s: %.0f" % (kid, sum(v) / len(v)))
     out.append("")
     out.append("source_sha256: " + source_hash())
-    with open(TRAFFIC_SUMMARY, "w") as fh:
+    with open(W["traffic_file"], "w") as fh:
         fh.write("\n".join(out) + "\n")
-    print("wrote", TRACE_SUMMARY, TRAFFIC_SUMMARY)
+    print("wrote", W["trace_file"], W["traffic_file"])
 
 
 def _parse():
@@ -261,10 +431,15 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=8, help="coupling cycles the CPU oracle is timed on")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32-vs-FP64 comparison")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the differentiation workload and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three plain 1 GiB device copies (reference for HBM byte counters)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the profiles/ summaries from rocprofv3 output directories and exit")
+    ap.add_argument("--summarize-adjoint", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="the same for the differentiation workload")
     return ap.parse_args()
 
 
@@ -300,7 +475,10 @@ def cpu_baseline(strip, cycles):
 def main():
     args = _parse()
     if args.summarize:
-        summarize(*args.summarize)
+        summarize("cycle", *args.summarize)
+        return
+    if args.summarize_adjoint:
+        summarize("adjoint", *args.summarize_adjoint)
         return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the hot path here is a single-GPU build "
@@ -322,6 +500,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_benchmark()}), flush=True)
+        return
     cfg = ChannelConfig(nx=NX, ny=NY, ppc=PPC, kn=KN, mach=MACH, seed=SEED).resolved()
     ch = D.Channel(cfg)
     e, w, r = D.lattice(37)
@@ -405,9 +586,12 @@ def main():
         "profiled_ms_per_step": 1e3 * (tp1 - tp0) / args.steps,
         "status_bits": st["bits"],
     }
-    if not args.no_precision:
-        del ch, f, ftmp
+    del ch, f, ftmp
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_benchmark()
         torch.cuda.empty_cache()
+    if not args.no_precision:
         out["precision"] = precision_comparison()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(strip, args.cpu_cycles)

@@ -51,9 +51,31 @@ __device__ __forceinline__ double block_sum256(double v, double *sh)
 // By = sum_q l*_q w_q (dE_q/du_y / tau + c xi_qx xi_qy g);
 // dJ/dtau += sum_q l*_q [(f_q - f_eq,q)/tau^2 + w_q rho P_q / (2 tau^2)],
 // dJ/dg += rho [c sum_q l*_q w_q (xi_qx (1 + xi_q.u) - u_x) + Bx / 2].
+// Every q-sum above is a polynomial of degree <= 3 in xi_q, so the node first
+// forms the moments M_a = sum_q w_q l*_q xi_q^a (|a| <= 3, ten of them, with
+// the integer velocity components as compile-time coefficients) and then
+// evaluates the sums from them.
+
+template <int Q, int q>
+__device__ __forceinline__ void adj_moments(double wl, double M[10])
+{
+    constexpr int x = VelSet<Q>::ex[q], y = VelSet<Q>::ey[q];
+    M[0] += wl;
+    cmad<x>(M[1], wl);
+    cmad<y>(M[2], wl);
+    cmad<x * x>(M[3], wl);
+    cmad<x * y>(M[4], wl);
+    cmad<y * y>(M[5], wl);
+    cmad<x * x * x>(M[6], wl);
+    cmad<x * x * y>(M[7], wl);
+    cmad<x * y * y>(M[8], wl);
+    cmad<y * y * y>(M[9], wl);
+}
+
 template <int Q, bool YB, bool NARROW>
 __device__ __forceinline__ void lbm_adj_node(const LbmAdjArgs &a, int node, double &dg, double &dtau)
 {
+#pragma clang fp contract(fast)
     using V = VelSet<Q>;
     constexpr int R = V::R;
     const int nx = a.nx, ny = a.ny;
@@ -79,51 +101,65 @@ __device__ __forceinline__ void lbm_adj_node(const LbmAdjArgs &a, int node, doub
             *plane_ptr(a.lam_out, nn, q, (uint32_t)node) = *plane_ptr(a.lam_in, nn, q, (uint32_t)node) + lp[q];
         return;
     }
-    double rho = 0.0, jx = 0.0, jy = 0.0, lf = 0.0;
+    const double *fp[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const double fq = *plane_ptr(a.f, nn, q, (uint32_t)node);
+    for (int q = 0; q < Q; ++q) fp[q] = plane_ptr(a.f, nn, q, (uint32_t)node);
+    double rho = 0.0, ex = 0.0, ey = 0.0, lf = 0.0, M[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) M[k] = 0.0;
+    static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const double fq = *fp[q];
         rho += fq;
-        jx += fq * (r * (double)V::ex[q]);
-        jy += fq * (r * (double)V::ey[q]);
+        cmad<V::ex[q]>(ex, fq);
+        cmad<V::ey[q]>(ey, fq);
         lf += lp[q] * fq;
-    }
+        adj_moments<Q, q>(a.L.ws[V::sh[q]] * lp[q], M);
+    });
+    const double r2 = r * r, r3 = r2 * r;
+    M[1] *= r, M[2] *= r;
+    M[3] *= r2, M[4] *= r2, M[5] *= r2;
+    M[6] *= r3, M[7] *= r3, M[8] *= r3, M[9] *= r3;
     const double g = a.gx;
     const double itau = 1.0 / a.tau, c = 1.0 - 0.5 * itau;
     const double irho = 1.0 / rho;
+    const double jx = r * ex, jy = r * ey;
     const double ux = (jx + 0.5 * rho * g) * irho;
     const double uy = jy * irho;
     const double wx = jx * irho;
     const double uu = ux * ux + uy * uy;
-    double Leq = 0.0, Lp = 0.0, Lg = 0.0, Bx = 0.0, By = 0.0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const double x = r * (double)V::ex[q], y = r * (double)V::ey[q];
-        const double wl = a.L.ws[V::sh[q]] * lp[q];
-        const double cu = x * ux + y * uy;
-        double E = 1.0 + cu + 0.5 * (cu * cu - uu);
-        double Ex = x + cu * x - ux;
-        double Ey = y + cu * y - uy;
-        if (Q != 9) {
-            E += cu * (cu * cu - 3.0 * uu) * (1.0 / 6.0);
-            Ex += 0.5 * x * (cu * cu - uu) - cu * ux;
-            Ey += 0.5 * y * (cu * cu - uu) - cu * uy;
-        }
-        const double cg = x * g;
-        const double P = cg + cg * cu - g * ux;
-        Leq += wl * E;
-        Lp += wl * P;
-        Lg += wl * (x + x * cu - ux);
-        Bx += wl * (Ex * itau + c * (cg * x - g));
-        By += wl * (Ey * itau + c * cg * y);
+    // sums over q of w l* times: xi.u, xi_x xi.u, xi_y xi.u, (xi.u)^2
+    const double C1 = ux * M[1] + uy * M[2];
+    const double Dx = ux * M[3] + uy * M[4];
+    const double Dy = ux * M[4] + uy * M[5];
+    const double C2 = ux * Dx + uy * Dy;
+    const double Lg = M[1] + Dx - ux * M[0];
+    double Leq = M[0] + C1 + 0.5 * (C2 - uu * M[0]);
+    double SEx = Lg;
+    double SEy = M[2] + Dy - uy * M[0];
+    if (Q != 9) {
+        // ... and xi_x (xi.u)^2, xi_y (xi.u)^2, (xi.u)^3
+        const double Ex2 = ux * ux * M[6] + 2.0 * ux * uy * M[7] + uy * uy * M[8];
+        const double Ey2 = ux * ux * M[7] + 2.0 * ux * uy * M[8] + uy * uy * M[9];
+        const double C3 = ux * Ex2 + uy * Ey2;
+        Leq += (C3 - 3.0 * uu * C1) * (1.0 / 6.0);
+        SEx += 0.5 * (Ex2 - uu * M[1]) - ux * C1;
+        SEy += 0.5 * (Ey2 - uu * M[2]) - uy * C1;
     }
+    const double Lp = g * Lg;
     const double A = Leq * itau + c * Lp;
+    const double Bx = SEx * itau + c * g * (M[3] - M[0]);
+    const double By = SEy * itau + c * g * M[4];
     const double k1 = 1.0 - itau;
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-        *plane_ptr(a.lam_out, nn, q, (uint32_t)node) =
-            k1 * lp[q] + A + Bx * (r * (double)V::ex[q] - wx) + By * (r * (double)V::ey[q] - uy);
-    dtau = (lf - rho * Leq) * itau * itau + 0.5 * rho * Lp * itau * itau;
+    const double A0 = A - Bx * wx - By * uy, Bxr = Bx * r, Byr = By * r;
+    static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        double v = k1 * lp[q] + A0;
+        cmad<V::ex[q]>(v, Bxr);
+        cmad<V::ey[q]>(v, Byr);
+        *plane_ptr(a.lam_out, nn, q, (uint32_t)node) = v;
+    });
+    dtau = ((lf - rho * Leq) + 0.5 * rho * Lp) * itau * itau;
     dg = rho * (c * Lg + 0.5 * Bx);
 }
 

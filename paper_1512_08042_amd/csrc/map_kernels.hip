@@ -388,6 +388,7 @@ __device__ __forceinline__ void neighbours(int ix, int iy, int nx, int ny, int K
 template <int Q, bool YB, bool NARROW>
 __device__ __forceinline__ void lbm_node(const LbmArgs &a, int node)
 {
+#pragma clang fp contract(fast)
     using V = VelSet<Q>;
     constexpr int R = V::R;
     const int nx = a.nx, ny = a.ny;
@@ -403,31 +404,40 @@ __device__ __forceinline__ void lbm_node(const LbmArgs &a, int node)
         for (int q = 0; q < Q; ++q) *plane_ptr(a.keep, nn, q, (uint32_t)node) = fe[q];
     }
     if (!buffer) {
-        double rho = 0.0, jx = 0.0, jy = 0.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        // rho and the momentum from the integer velocity components
+        double rho = 0.0, ex = 0.0, ey = 0.0;
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
             rho += fe[q];
-            jx += fe[q] * (r * (double)V::ex[q]);
-            jy += fe[q] * (r * (double)V::ey[q]);
-        }
-        const double gx = a.gx, itau = 1.0 / a.tau;
-        const double cf = 1.0 - 0.5 * itau;
+            cmad<V::ex[q]>(ex, fe[q]);
+            cmad<V::ey[q]>(ey, fe[q]);
+        });
+        const double g = a.gx, itau = 1.0 / a.tau;
+        const double cf = 1.0 - 0.5 * itau, k1 = 1.0 - itau;
         const double irho = 1.0 / rho;
-        const double ux = (jx + 0.5 * rho * gx) * irho;
-        const double uy = jy * irho;
+        const double ux = (r * ex + 0.5 * rho * g) * irho;
+        const double uy = r * ey * irho;
         const double uu = ux * ux + uy * uy;
+        const double rux = r * ux, ruy = r * uy, rg = r * g, gux = g * ux;
+        double wr[8], fr[8];  // per shell: w rho / tau and (1 - 1/(2 tau)) w rho
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const double x = r * (double)V::ex[q], y = r * (double)V::ey[q], w = a.L.ws[V::sh[q]];
-            const double cu = x * ux + y * uy;
-            double eq = 1.0 + cu + 0.5 * (cu * cu - uu);
-            if (Q != 9) eq += (cu * (cu * cu - 3.0 * uu)) * (1.0 / 6.0);
-            const double feq = w * rho * eq;
-            const double cg = x * gx;
-            const double F = cf * w * rho * (cg + cg * cu - gx * ux);
-            const double fa = fe[q];
-            fe[q] = fa - (fa - feq) * itau + F;
+        for (int s = 0; s < 8; ++s) {
+            wr[s] = a.L.ws[s] * rho * itau;
+            fr[s] = cf * a.L.ws[s] * rho;
         }
+        // post-collision f - (f - f_eq)/tau + force, with f_eq = w rho E(xi.u)
+        // and force (1 - 1/(2 tau)) w rho [xi_x g (1 + xi.u) - g u_x]
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int s = V::sh[q];
+            double cu = 0.0, cg = 0.0;
+            cmad<V::ex[q]>(cu, rux);
+            cmad<V::ey[q]>(cu, ruy);
+            cmad<V::ex[q]>(cg, rg);
+            double eq = 1.0 + cu + 0.5 * (cu * cu - uu);
+            if (Q != 9) eq += cu * (cu * cu - 3.0 * uu) * (1.0 / 6.0);
+            fe[q] = k1 * fe[q] + wr[s] * eq + fr[s] * (cg + cg * cu - gux);
+        });
     }
     // buffer rows keep their populations (written back unchanged) and send
     // them on; nothing streamed into a buffer row is kept

@@ -2,6 +2,8 @@
 // the host side of libdsmc (passed by value; all pointers are device memory).
 #pragma once
 
+#include <utility>
+
 #include "dsmc_device.hpp"
 
 namespace dsmc {
@@ -197,6 +199,30 @@ __device__ __forceinline__ const double *plane_ptr(const double *base, size_t nn
 __device__ __forceinline__ double *plane_ptr(double *base, size_t nn, int q, uint32_t i)
 {
     return (double *)((char *)(base + (size_t)q * nn) + (size_t)(uint32_t)(i * 8u));
+}
+
+// acc += C v for a compile-time integer C (nothing for 0, an add for +-1)
+template <int C>
+__device__ __forceinline__ void cmad(double &acc, double v)
+{
+    if constexpr (C == 1)
+        acc += v;
+    else if constexpr (C == -1)
+        acc -= v;
+    else if constexpr (C != 0)
+        acc += (double)C * v;
+}
+
+// f(std::integral_constant<int, q>) for q = 0 .. N-1, unrolled at compile time
+template <class F, int... qs>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, qs...>)
+{
+    (f(std::integral_constant<int, qs>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 struct LatShells {
