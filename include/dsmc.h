@@ -269,6 +269,70 @@ int dsmc_project_moments_adjoint(const double *f_bar, const double *avg, int64_t
 /* Host copy of a lattice table: e_out int[Q][2], w_out double[Q], r_out. */
 int dsmc_lattice(int32_t lattice, int32_t *e_out, double *w_out, double *r_out);
 
+/* ---- batches of independent channels ------------------------------------
+ * A batch context holds nrep independent channels (replicas) of a force-
+ * driven Poiseuille flow (Section 3.1), each with its own size, particles per
+ * cell, Knudsen number, time step, body force and Philox seed, stored one
+ * after the other: replica r owns cells [cbase_r, cbase_r + nx_r ny_r) of
+ * every per-cell array (cbase_r = sum of the cells of replicas < r, each
+ * replica's cells in its own row-major order) and, after every call, the
+ * particle slots [cell_start[cbase_r], cell_start[cbase_r + nx_r ny_r]).
+ * One launch steps the cell tiles of all replicas together.  Every random
+ * draw is keyed by cell and slot indices inside the replica, so replica r
+ * evolves bit for bit as a one-channel context with its parameters would.
+ * dsmc_step, dsmc_sample_moments (cells in the order above; rho = N/ppc_r is
+ * the caller's), dsmc_read_status (totals over all replicas),
+ * dsmc_get_views and the profiling calls take batch contexts;
+ * map_dsmc_to_lbm and map_lbm_to_dsmc return DSMC_ESTATE for them. */
+typedef struct dsmc_replica {
+    int32_t nx, ny;        /* cells (>= 1 each) */
+    int32_t ppc;           /* particles per cell at density 1 (>= 1) */
+    int32_t reserved;      /* 0 */
+    double kn;             /* Knudsen number on the replica's height ny (> 0) */
+    double dt;             /* time step (> 0) */
+    double body_force_x;   /* acceleration along x */
+    uint64_t seed;         /* Philox key */
+} dsmc_replica;
+
+/* Sizes for a batch: common->capacity must hold every replica's
+ * nx ny ppc particles; common's nx, ny, ppc, kn, dt, body_force_x and seed
+ * are not used (each replica has its own).  Errors: DSMC_EINVAL. */
+int dsmc_batch_query_sizes(const dsmc_config *common, const dsmc_replica *reps, int32_t nrep, dsmc_sizes *out);
+
+/* A batch context, every replica started as dsmc_init mode 0 would start it
+ * alone (a Maxwellian at kT/m with exactly ppc particles per cell).  reps is
+ * host memory, copied.  Errors: DSMC_EINVAL, DSMC_ECAPACITY, DSMC_EHIP. */
+int dsmc_batch_init(const dsmc_config *common, const dsmc_replica *reps, int32_t nrep, const dsmc_buffers *buf,
+                    void *stream, dsmc_ctx **out);
+
+/* Step tiling: every replica's cells are cut into tiles of TC consecutive
+ * cells (one wavefront each) holding about particles_per_tile particles
+ * (0: the default, 200 for FP64 and 400 for FP32 state); tiles of equal shape
+ * share a launch.  Particles, cell starts and counters do not depend on the
+ * tiling; the moment sums add the same terms in an order that follows the
+ * tile shape (agreeing to rounding).  Synchronises the stream.
+ * Errors: DSMC_EINVAL, DSMC_EHIP. */
+int dsmc_set_tiling(dsmc_ctx *ctx, int32_t particles_per_tile, void *stream);
+
+/* Tiling autotuner: runs steps_per_trial real steps (sampling every
+ * sample_every, as dsmc_step) under each candidate particles_per_tile, timed
+ * with HIP events, and keeps the fastest.  The trial steps advance the run
+ * like any other steps; the trajectory does not depend on the tiling.  out
+ * (host, may be NULL) receives the candidates, their times and the choice.
+ * Errors: DSMC_EINVAL, DSMC_EHIP. */
+typedef struct dsmc_tuning {
+    int32_t ncand;                  /* candidates tried */
+    int32_t chosen;                 /* index of the one kept */
+    int32_t particles_per_tile[8];
+    double ms_per_step[8];
+} dsmc_tuning;
+int dsmc_autotune(dsmc_ctx *ctx, int32_t steps_per_trial, int32_t sample_every, dsmc_tuning *out, void *stream);
+
+/* Per-replica counters since init: out (host, [nrep][3]) = accepted
+ * collisions, collision candidates, wall hits.  Synchronises the stream.
+ * Errors: DSMC_EINVAL, DSMC_EHIP. */
+int dsmc_replica_counters(dsmc_ctx *ctx, uint64_t *out, void *stream);
+
 /* Synchronise the context's last stream and read the status word and
  * counters; clear != 0 resets the status bits.  Errors: DSMC_EHIP. */
 int dsmc_read_status(dsmc_ctx *ctx, dsmc_status *out, int32_t clear, void *stream);

@@ -22,7 +22,8 @@ EXPORTS = ("dsmc_query_sizes", "dsmc_init", "dsmc_step", "dsmc_sample_moments", 
            "dsmc_project_moments", "map_lbm_to_dsmc", "lbm_step", "dsmc_lattice", "dsmc_read_status",
            "dsmc_get_views", "dsmc_profile_enable", "dsmc_profile_read", "dsmc_destroy", "dsmc_strerror",
            "lbm_step_checkpointed", "lbm_adjoint_workspace", "lbm_adjoint_step", "lbm_adjoint",
-           "lbm_hermite_moments", "lbm_hermite_moments_adjoint", "dsmc_project_moments_adjoint")
+           "lbm_hermite_moments", "lbm_hermite_moments_adjoint", "dsmc_project_moments_adjoint",
+           "dsmc_batch_query_sizes", "dsmc_batch_init", "dsmc_set_tiling", "dsmc_autotune", "dsmc_replica_counters")
 
 
 class Config(ctypes.Structure):
@@ -30,6 +31,15 @@ class Config(ctypes.Structure):
                 ("kn", c_d), ("dt", c_d), ("body_force_x", c_d), ("kT_over_m", c_d), ("sigcr_max0", c_d),
                 ("seed", c_u64), ("ar_max_tries", c_i32), ("far_capacity", c_i32), ("state_bits", c_i32),
                 ("reserved", c_i32)]
+
+
+class Replica(ctypes.Structure):
+    _fields_ = [("nx", c_i32), ("ny", c_i32), ("ppc", c_i32), ("reserved", c_i32), ("kn", c_d), ("dt", c_d),
+                ("body_force_x", c_d), ("seed", c_u64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("ncand", c_i32), ("chosen", c_i32), ("particles_per_tile", c_i32 * 8), ("ms_per_step", c_d * 8)]
 
 
 class Sizes(ctypes.Structure):
@@ -88,6 +98,11 @@ def lib():
         L.dsmc_project_moments_adjoint.argtypes = [c_p, c_p, c_i64, c_i32, c_d, c_i32, c_i32, c_p, c_p]
         L.dsmc_lattice.argtypes = [c_i32, c_p, c_p, c_p]
         L.dsmc_read_status.argtypes = [c_p, P(Status), c_i32, c_p]
+        L.dsmc_batch_query_sizes.argtypes = [P(Config), P(Replica), c_i32, P(Sizes)]
+        L.dsmc_batch_init.argtypes = [P(Config), P(Replica), c_i32, P(Buffers), c_p, P(c_p)]
+        L.dsmc_set_tiling.argtypes = [c_p, c_i32, c_p]
+        L.dsmc_autotune.argtypes = [c_p, c_i32, c_i32, P(Tuning), c_p]
+        L.dsmc_replica_counters.argtypes = [c_p, P(c_u64), c_p]
         L.dsmc_get_views.argtypes = [c_p, P(Views)]
         L.dsmc_profile_enable.argtypes = [c_p, c_i32]
         L.dsmc_profile_read.argtypes = [c_p, c_i32, P(c_d), P(c_i64)]

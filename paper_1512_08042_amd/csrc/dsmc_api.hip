@@ -217,12 +217,12 @@ int far_cap_of(const dsmc_config &c)
 
 struct Layout {
     size_t cs0, cs1, grp0, grp1, countnew, farcnt, blocksum, far0, far1, nbar, sigcmax, rem, mom, mark, prm, nnew, perm,
-        tstat, kc, ctr, total;
+        tstat, kc, ctr, rep, tiles, cell_rep, rstat, total;
 };
 
-Layout make_layout(const dsmc_config &c)
+// nc: cells of all channels together; nrep: channels
+Layout make_layout(const dsmc_config &c, size_t nc, size_t nrep)
 {
-    const size_t nc = (size_t)c.nx * (size_t)c.ny;
     const size_t nblk = (nc + 255) / 256;
     const size_t cap = (size_t)c.capacity;
     Layout L;
@@ -249,11 +249,59 @@ Layout make_layout(const dsmc_config &c)
     L.prm = take(nc * 12 * 8);
     L.nnew = take(nc * 4);
     L.perm = take(cap * 12);  // adoption: permutation + cell ids; steps: scratch of oversized tiles
-    L.tstat = take(3 * nc * 8);  // per step tile (at most one tile per cell)
+    L.tstat = take(3 * nc * 8);  // per step tile, at its first cell
     L.kc = take(sizeof(TileConst));
     L.ctr = take(sizeof(Counters));
+    L.rep = take(nrep * sizeof(RepConst));
+    L.tiles = take(2 * nc * 4);  // at most one tile per cell
+    L.cell_rep = take(nc * 4);
+    L.rstat = take(3 * nrep * 8);
     L.total = o;
     return L;
+}
+
+bool valid_replica(const dsmc_replica &r)
+{
+    if (r.nx < 1 || r.ny < 1 || r.ppc < 1) return false;
+    if ((int64_t)r.nx * (int64_t)r.ny > (int64_t)0x3FFFFFFF) return false;
+    if (!(r.kn > 0.0) || !(r.dt > 0.0) || !std::isfinite(r.kn) || !std::isfinite(r.dt)) return false;
+    return std::isfinite(r.body_force_x);
+}
+
+// the channels of a batch: common settings valid, every replica valid, the
+// cells and the initial particles within the limits
+bool valid_batch(const dsmc_config *c, const dsmc_replica *reps, int32_t nrep, int64_t *ncells, int64_t *npart)
+{
+    if (!c || !reps || nrep < 1) return false;
+    if (c->capacity < 1 || c->capacity > (int64_t)0x7FFFFFFF) return false;
+    if (!(c->kT_over_m > 0.0) || !(c->sigcr_max0 > 0.0)) return false;
+    if (!std::isfinite(c->kT_over_m) || !std::isfinite(c->sigcr_max0)) return false;
+    if (c->nbar_mode != 0 && c->nbar_mode != 1) return false;
+    if (c->state_bits != 0 && c->state_bits != 32 && c->state_bits != 64) return false;
+    int64_t nc = 0, np = 0;
+    for (int32_t r = 0; r < nrep; ++r) {
+        if (!valid_replica(reps[r])) return false;
+        nc += (int64_t)reps[r].nx * reps[r].ny;
+        np += (int64_t)reps[r].nx * reps[r].ny * reps[r].ppc;
+        if (nc > (int64_t)0x3FFFFFFF) return false;
+    }
+    *ncells = nc;
+    *npart = np;
+    return true;
+}
+
+dsmc_replica replica_of(const dsmc_config &c)
+{
+    dsmc_replica r;
+    std::memset(&r, 0, sizeof(r));
+    r.nx = c.nx;
+    r.ny = c.ny;
+    r.ppc = c.ppc;
+    r.kn = c.kn;
+    r.dt = c.dt;
+    r.body_force_x = c.body_force_x;
+    r.seed = c.seed;
+    return r;
 }
 
 struct ProfRec {
@@ -274,10 +322,23 @@ struct dsmc_ctx {
     TileConst *kc;       // device copy of kc_host
     TileConst kc_host;
     int ncells, nblk, far_cap, ntiles;
-    double K, s_th;
-    Geometry G;
+    double K, s_th;  // K of a single channel (reseed)
+    Geometry G;      // geometry of a single channel (reseed, adoption)
     int cur;
-    int tc, ch;  // cells per step tile, 64-slot chunks of its LDS stage
+    // the channels (one, or the replicas of a batch) and the step tiles:
+    // tiles are grouped by shape (TC cells, CH 64-slot chunks of LDS stage),
+    // one launch per group
+    int nrep;
+    std::vector<RepConst> reps;
+    RepConst *rep;
+    int32_t *tiles, *cell_rep;
+    unsigned long long *rstat;
+    struct TileGroup {
+        int tc, ch, tile0, ntiles;
+    };
+    std::vector<TileGroup> groups;
+    std::vector<int32_t> tiles_host;
+    int particles_per_tile;
     int64_t step, nsamples, reseed_events;
     // Inside a dsmc_step call the state between steps is kept already moved
     // for the coming step and partitioned by direction inside every cell
@@ -330,34 +391,12 @@ int launch(dsmc_ctx *x, int kid, hipStream_t s, F &&f)
 inline unsigned grid_cells_wave(int ncells) { return (unsigned)((ncells + 3) / 4); }
 inline unsigned grid_threads(size_t n) { return (unsigned)((n + 255) / 256); }
 
-MoveParams move_params(const dsmc_ctx *x, int64_t step)
-{
-    MoveParams M;
-    M.dt = x->cfg.dt;
-    M.g = x->cfg.body_force_x;
-    M.s_th = x->s_th;
-    M.k0 = (uint32_t)x->cfg.seed;
-    M.k1 = (uint32_t)(x->cfg.seed >> 32);
-    M.step = (uint32_t)step;
-    return M;
-}
-
-NtcParams ntc_params(const dsmc_ctx *x, int64_t step)
-{
-    NtcParams N;
-    N.K = x->K;
-    N.dt = x->cfg.dt;
-    N.k0 = (uint32_t)x->cfg.seed;
-    N.k1 = (uint32_t)(x->cfg.seed >> 32);
-    N.step = (uint32_t)step;
-    N.nbar_mode = x->cfg.nbar_mode;
-    return N;
-}
-
 StepArgs step_args(const dsmc_ctx *x, int32_t cur, int64_t step, bool sample, bool classify)
 {
     StepArgs a;
     a.kc = x->kc;
+    a.tiles = x->tiles;
+    a.r = 0;
     a.step = (uint32_t)step;
     a.cur = cur;
     a.sample = sample ? 1 : 0;
@@ -384,52 +423,114 @@ int upload_tile_const(dsmc_ctx *x, hipStream_t s)
     k.nbar = x->nbar;
     k.sigcmax = x->sigcmax;
     k.rem = x->rem;
-    k.G = x->G;
-    k.dt = x->cfg.dt;
-    k.g = x->cfg.body_force_x;
+    k.rep = x->rep;
     k.s_th = x->s_th;
-    k.K = x->K;
-    k.k0 = (uint32_t)x->cfg.seed;
-    k.k1 = (uint32_t)(x->cfg.seed >> 32);
     k.nbar_mode = x->cfg.nbar_mode;
     k.ncells = x->ncells;
     k.far_cap = x->far_cap;
+    k.nrep = x->nrep;
     return hipMemcpyAsync(x->kc, &k, sizeof(TileConst), hipMemcpyHostToDevice, s) == hipSuccess ? DSMC_OK : DSMC_EHIP;
 }
 
-// one launch of the tile kernels: kind 0 = k_classify, 1 = k_step
-void launch_tiles(const dsmc_ctx *x, int kind, bool move, unsigned ntiles, hipStream_t s, const StepArgs &a)
+// the tile shape (TC, CH) a channel of ppc particles per cell gets for a
+// target of about `ppt` particles per tile (from the shapes instantiated for
+// each state type): as many cells as fit the target, then the LDS stage
+// that holds them with a quarter to spare
+void tile_shape(bool f32, int ppc, int ppt, int &tc, int &ch)
 {
-#define DSMC_LAUNCH(TC, CH, S)                                       \
-    do {                                                             \
-        if (kind == 0)                                               \
-            k_classify<TC, CH, S><<<ntiles, 64, 0, s>>>(a);          \
-        else if (move)                                               \
-            k_step<TC, CH, true, S><<<ntiles, 64, 0, s>>>(a);        \
-        else                                                         \
-            k_step<TC, CH, false, S><<<ntiles, 64, 0, s>>>(a);       \
-    } while (0)
-    // the tile shapes each state type uses (see dsmc_init)
-    if (state32(x->cfg)) {
-        if (x->tc == 4 && x->ch == 8)
-            DSMC_LAUNCH(4, 8, float);
-        else if (x->tc == 4)
-            DSMC_LAUNCH(4, 4, float);
-        else if (x->tc == 2)
-            DSMC_LAUNCH(2, 8, float);
-        else
-            DSMC_LAUNCH(1, 8, float);
+    tc = 4;
+    while (tc > 1 && tc * ppc > ppt) tc /= 2;
+    const bool small = (double)tc * ppc * 1.25 <= 256.0;
+    if (f32) {
+        ch = (tc == 4 && small) ? 4 : 8;
     } else {
-        if (x->tc == 4)
-            DSMC_LAUNCH(4, 4, double);
-        else if (x->tc == 2)
-            DSMC_LAUNCH(2, 4, double);
-        else if (x->ch == 4)
-            DSMC_LAUNCH(1, 4, double);
-        else
-            DSMC_LAUNCH(1, 8, double);
+        while (tc > 1 && (double)tc * ppc * 1.25 > 256.0) tc /= 2;  // FP64 stages of 512 slots are single-cell
+        ch = (double)tc * ppc * 1.25 <= 256.0 ? 4 : 8;
     }
+}
+
+// Builds the tile groups for a target of ppt particles per tile (0: the
+// default, about 200 for FP64 and 400 for FP32 state) and uploads the tile
+// table.  The trajectory does not depend on the tiling (the moment sums only
+// to rounding: their summation order follows the tile shape).
+int set_tiling(dsmc_ctx *x, int ppt, hipStream_t s)
+{
+    const bool f32 = state32(x->cfg);
+    if (ppt <= 0) ppt = f32 ? 400 : 200;
+    static const int SHAPES[2][4][2] = {{{4, 4}, {2, 4}, {1, 4}, {1, 8}}, {{4, 8}, {4, 4}, {2, 8}, {1, 8}}};
+    std::vector<int> shape_of(x->nrep);
+    for (int r = 0; r < x->nrep; ++r) {
+        int tc, ch;
+        tile_shape(f32, x->reps[r].ppc, ppt, tc, ch);
+        shape_of[r] = -1;
+        for (int k = 0; k < 4; ++k)
+            if (SHAPES[f32][k][0] == tc && SHAPES[f32][k][1] == ch) shape_of[r] = k;
+        if (shape_of[r] < 0) return DSMC_EINVAL;
+    }
+    x->groups.clear();
+    x->tiles_host.clear();
+    for (int k = 0; k < 4; ++k) {
+        dsmc_ctx::TileGroup g;
+        g.tc = SHAPES[f32][k][0];
+        g.ch = SHAPES[f32][k][1];
+        g.tile0 = (int)(x->tiles_host.size() / 2);
+        for (int r = 0; r < x->nrep; ++r) {
+            if (shape_of[r] != k) continue;
+            for (int c = x->reps[r].cbase; c < x->reps[r].cend; c += g.tc) {
+                x->tiles_host.push_back(c);
+                x->tiles_host.push_back(r);
+            }
+        }
+        g.ntiles = (int)(x->tiles_host.size() / 2) - g.tile0;
+        if (g.ntiles > 0) x->groups.push_back(g);
+    }
+    x->ntiles = (int)(x->tiles_host.size() / 2);
+    x->particles_per_tile = ppt;
+    if (hipMemcpyAsync(x->tiles, x->tiles_host.data(), x->tiles_host.size() * 4, hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return DSMC_EHIP;
+    // the host table must outlive the copy
+    return hipStreamSynchronize(s) == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
+// the launches of one pass of the tile kernels, one per tile group: kind 0
+// = k_classify, 1 = k_step
+void launch_tiles(const dsmc_ctx *x, int kind, bool move, hipStream_t s, const StepArgs &a0)
+{
+    for (const dsmc_ctx::TileGroup &g : x->groups) {
+        StepArgs a = a0;
+        a.tiles = x->tiles + 2 * (size_t)g.tile0;
+        const unsigned n = (unsigned)g.ntiles;
+#define DSMC_LAUNCH(TC, CH, S)                                  \
+    do {                                                        \
+        if (kind == 0)                                          \
+            k_classify<TC, CH, S><<<n, 64, 0, s>>>(a);          \
+        else if (move)                                          \
+            k_step<TC, CH, true, S><<<n, 64, 0, s>>>(a);        \
+        else                                                    \
+            k_step<TC, CH, false, S><<<n, 64, 0, s>>>(a);       \
+    } while (0)
+        if (state32(x->cfg)) {
+            if (g.tc == 4 && g.ch == 8)
+                DSMC_LAUNCH(4, 8, float);
+            else if (g.tc == 4)
+                DSMC_LAUNCH(4, 4, float);
+            else if (g.tc == 2)
+                DSMC_LAUNCH(2, 8, float);
+            else
+                DSMC_LAUNCH(1, 8, float);
+        } else {
+            if (g.tc == 4)
+                DSMC_LAUNCH(4, 4, double);
+            else if (g.tc == 2)
+                DSMC_LAUNCH(2, 4, double);
+            else if (g.ch == 4)
+                DSMC_LAUNCH(1, 4, double);
+            else
+                DSMC_LAUNCH(1, 8, double);
+        }
 #undef DSMC_LAUNCH
+    }
 }
 
 int fill_f64(double *p, size_t n, double v, hipStream_t s)
@@ -600,7 +701,7 @@ const char *dsmc_strerror(int code)
 int dsmc_query_sizes(const dsmc_config *cfg, dsmc_sizes *out)
 {
     if (!valid_config(cfg) || !out) return DSMC_EINVAL;
-    const Layout L = make_layout(*cfg);
+    const Layout L = make_layout(*cfg, (size_t)cfg->nx * cfg->ny, 1);
     out->ncells = (int64_t)cfg->nx * cfg->ny;
     out->capacity = cfg->capacity;
     out->state_array_bytes = (size_t)cfg->capacity * (state32(*cfg) ? 4 : 8);
@@ -624,26 +725,37 @@ int dsmc_lattice(int32_t lattice, int32_t *e_out, double *w_out, double *r_out)
     return DSMC_OK;
 }
 
-int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int64_t n_load, void *stream,
-              dsmc_ctx **out)
+}  // extern "C"
+
+namespace {
+
+// A context over nrep channels (cfg supplies the settings they share; the
+// single-channel entry passes its own channel as the only replica).
+int init_ctx(const dsmc_config *cfg, const dsmc_replica *reps, int32_t nrep, const dsmc_buffers *buf, int32_t mode,
+             int64_t n_load, hipStream_t s, dsmc_ctx **out)
 {
-    if (!out || !valid_config(cfg) || !buf || !buf->workspace) return DSMC_EINVAL;
-    *out = nullptr;
-    for (int b = 0; b < 2; ++b)
-        for (int k = 0; k < 5; ++k)
-            if (!buf->state[b][k]) return DSMC_EINVAL;
-    if (((uintptr_t)buf->workspace & 255u) != 0) return DSMC_EINVAL;
-    const Layout L = make_layout(*cfg);
+    int64_t ncells = 0, npart = 0;
+    if (!valid_batch(cfg, reps, nrep, &ncells, &npart)) return DSMC_EINVAL;
+    const Layout L = make_layout(*cfg, (size_t)ncells, (size_t)nrep);
     if (buf->workspace_bytes < L.total) return DSMC_EINVAL;
     if (mode != 0 && mode != 1) return DSMC_EINVAL;
-    const int64_t ncells = (int64_t)cfg->nx * cfg->ny;
-    if (mode == 0 && ncells * cfg->ppc > cfg->capacity) return DSMC_ECAPACITY;
+    if (mode == 1 && nrep != 1) return DSMC_EINVAL;
+    if (mode == 0 && npart > cfg->capacity) return DSMC_ECAPACITY;
     if (mode == 1 && (n_load < 0 || n_load > cfg->capacity)) return n_load < 0 ? DSMC_EINVAL : DSMC_ECAPACITY;
     if (!tables().ok) return DSMC_EINVAL;
 
     dsmc_ctx *x = new (std::nothrow) dsmc_ctx();
     if (!x) return DSMC_EINVAL;
     x->cfg = *cfg;
+    if (nrep == 1) {  // the channel's own parameters, for the single-channel calls
+        x->cfg.nx = reps[0].nx;
+        x->cfg.ny = reps[0].ny;
+        x->cfg.ppc = reps[0].ppc;
+        x->cfg.kn = reps[0].kn;
+        x->cfg.dt = reps[0].dt;
+        x->cfg.body_force_x = reps[0].body_force_x;
+        x->cfg.seed = reps[0].seed;
+    }
     char *w = (char *)buf->workspace;
     for (int b = 0; b < 2; ++b)
         for (int k = 0; k < 5; ++k) x->st[b][k] = buf->state[b][k];
@@ -667,68 +779,93 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
     x->ctr = (Counters *)(w + L.ctr);
     x->tstat = (unsigned long long *)(w + L.tstat);
     x->kc = (TileConst *)(w + L.kc);
+    x->rep = (RepConst *)(w + L.rep);
+    x->tiles = (int32_t *)(w + L.tiles);
+    x->cell_rep = (int32_t *)(w + L.cell_rep);
+    x->rstat = (unsigned long long *)(w + L.rstat);
     x->ncells = (int)ncells;
     x->nblk = (int)((ncells + 255) / 256);
     x->far_cap = far_cap_of(*cfg);
-    const double lambda = cfg->kn * (double)cfg->ny;
-    // Eq. (MFP): lambda = 1/(sqrt(2) pi d^2 n), n = ppc F_N / V_c
-    x->K = 1.0 / (std::sqrt(2.0) * lambda * (double)cfg->ppc);
     x->s_th = std::sqrt(cfg->kT_over_m);
-    x->G.nx = cfg->nx;
-    x->G.ny = cfg->ny;
-    x->G.Lx = (double)cfg->nx;
-    x->G.H = (double)cfg->ny;
+    x->nrep = nrep;
+    x->reps.resize(nrep);
+    std::vector<int32_t> cell_rep((size_t)ncells);
+    int64_t cb = 0, pb = 0;
+    for (int32_t r = 0; r < nrep; ++r) {
+        const dsmc_replica &q = reps[r];
+        RepConst &R = x->reps[r];
+        const int64_t nc = (int64_t)q.nx * q.ny;
+        R.G.nx = q.nx;
+        R.G.ny = q.ny;
+        R.G.Lx = (double)q.nx;
+        R.G.H = (double)q.ny;
+        R.dt = q.dt;
+        R.g = q.body_force_x;
+        // Eq. (MFP): lambda = 1/(sqrt(2) pi d^2 n), n = ppc F_N / V_c
+        R.K = 1.0 / (std::sqrt(2.0) * (q.kn * (double)q.ny) * (double)q.ppc);
+        R.k0 = (uint32_t)q.seed;
+        R.k1 = (uint32_t)(q.seed >> 32);
+        R.cbase = (int32_t)cb;
+        R.cend = (int32_t)(cb + nc);
+        R.pbase = (int32_t)pb;
+        R.ppc = q.ppc;
+        for (int64_t c = cb; c < cb + nc; ++c) cell_rep[(size_t)c] = r;
+        cb += nc;
+        pb += nc * q.ppc;
+    }
+    x->K = x->reps[0].K;
+    x->G = x->reps[0].G;
     x->cur = 0;
     x->step = 0;
     x->nsamples = 0;
     x->reseed_events = 0;
     x->classified = false;
-    // step tiles, one wave each: FP64 state, about 200 particles in an LDS
-    // stage of 256 slots; FP32 state (half the stage bytes), about 400
-    // particles in 512 slots (measured best for each at 100 particles per
-    // cell); denser gases get single-cell tiles with 512 slots
-    if (state32(*cfg)) {
-        x->tc = cfg->ppc <= 100 ? 4 : (cfg->ppc <= 200 ? 2 : 1);
-        x->ch = 4 * cfg->ppc * 5 / 4 <= 256 ? 4 : 8;
-        if (x->tc < 4) x->ch = 8;
-    } else {
-        x->tc = cfg->ppc <= 50 ? 4 : (cfg->ppc <= 100 ? 2 : 1);
-        x->ch = cfg->ppc <= 200 ? 4 : 8;
-    }
-    x->ntiles = (int)((ncells + x->tc - 1) / x->tc);
     x->prof = false;
-    hipStream_t s = S(stream);
     x->last = s;
 
     int rc = DSMC_OK;
-    k_zero_counters<<<1, 64, 0, s>>>(x->ctr);
-    if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
+    if (hipMemcpyAsync(x->rep, x->reps.data(), sizeof(RepConst) * (size_t)nrep, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(x->cell_rep, cell_rep.data(), 4 * (size_t)ncells, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        rc = DSMC_EHIP;
+    if (rc == DSMC_OK) rc = set_tiling(x, 0, s);
+    if (rc == DSMC_OK) {
+        k_zero_counters<<<1, 64, 0, s>>>(x->ctr);
+        if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
+    }
     if (rc == DSMC_OK) rc = fill_f64(x->mom, (size_t)NMOM * ncells, 0.0, s);
     if (rc == DSMC_OK) rc = fill_i32(x->farcnt, 2 * (size_t)ncells, 0, s);
     if (rc == DSMC_OK) rc = fill_i32(x->mark, (size_t)ncells, 0, s);
-    if (rc == DSMC_OK) rc = fill_i32((int32_t *)x->tstat, 6 * (size_t)x->ntiles, 0, s);
+    if (rc == DSMC_OK) rc = fill_i32((int32_t *)x->tstat, 6 * (size_t)ncells, 0, s);
     if (rc == DSMC_OK) rc = upload_tile_const(x, s);
     if (rc == DSMC_OK && mode == 0) {
-        InitArgs a;
-        for (int k = 0; k < 5; ++k) a.st[k] = x->st[0][k];
-        a.cs = x->cs[0];
-        a.nbar = x->nbar;
-        a.sigcmax = x->sigcmax;
-        a.rem = x->rem;
-        a.nx = cfg->nx;
-        a.ncells = x->ncells;
-        a.ppc = cfg->ppc;
-        a.s_th = x->s_th;
-        a.sigcr0 = cfg->sigcr_max0;
-        a.k0 = (uint32_t)cfg->seed;
-        a.k1 = (uint32_t)(cfg->seed >> 32);
-        const size_t n = (size_t)ncells * cfg->ppc;
-        const size_t nthreads = n > (size_t)ncells + 1 ? n : (size_t)ncells + 1;
-        if (state32(*cfg))
-            k_init_maxwell<float><<<grid_threads(nthreads), 256, 0, s>>>(a);
-        else
-            k_init_maxwell<double><<<grid_threads(nthreads), 256, 0, s>>>(a);
-        if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
+        // one launch per channel: its cells, its particles, its seed
+        const size_t es = state32(*cfg) ? 4 : 8;
+        for (int32_t r = 0; r < nrep && rc == DSMC_OK; ++r) {
+            const RepConst &R = x->reps[r];
+            InitArgs a;
+            for (int k = 0; k < 5; ++k) a.st[k] = (char *)x->st[0][k] + (size_t)R.pbase * es;
+            a.cs = x->cs[0] + R.cbase;
+            a.nbar = x->nbar + R.cbase;
+            a.sigcmax = x->sigcmax + R.cbase;
+            a.rem = x->rem + R.cbase;
+            a.nx = R.G.nx;
+            a.ncells = R.cend - R.cbase;
+            a.ppc = R.ppc;
+            a.pbase = R.pbase;
+            a.s_th = x->s_th;
+            a.sigcr0 = cfg->sigcr_max0;
+            a.k0 = R.k0;
+            a.k1 = R.k1;
+            const size_t n = (size_t)a.ncells * R.ppc;
+            const size_t nthreads = n > (size_t)a.ncells + 1 ? n : (size_t)a.ncells + 1;
+            if (state32(*cfg))
+                k_init_maxwell<float><<<grid_threads(nthreads), 256, 0, s>>>(a);
+            else
+                k_init_maxwell<double><<<grid_threads(nthreads), 256, 0, s>>>(a);
+            if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
+        }
         x->cur = 0;
     } else if (rc == DSMC_OK) {
         // adopt: stable sort of buffer 0 into buffer 1 by cell
@@ -777,20 +914,128 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
     return DSMC_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int64_t n_load, void *stream,
+              dsmc_ctx **out)
+{
+    if (!out || !valid_config(cfg) || !buf || !buf->workspace) return DSMC_EINVAL;
+    *out = nullptr;
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < 5; ++k)
+            if (!buf->state[b][k]) return DSMC_EINVAL;
+    if (((uintptr_t)buf->workspace & 255u) != 0) return DSMC_EINVAL;
+    const dsmc_replica one = replica_of(*cfg);
+    return init_ctx(cfg, &one, 1, buf, mode, n_load, S(stream), out);
+}
+
+int dsmc_batch_query_sizes(const dsmc_config *common, const dsmc_replica *reps, int32_t nrep, dsmc_sizes *out)
+{
+    int64_t nc = 0, np = 0;
+    if (!out || !valid_batch(common, reps, nrep, &nc, &np)) return DSMC_EINVAL;
+    const Layout L = make_layout(*common, (size_t)nc, (size_t)nrep);
+    out->ncells = nc;
+    out->capacity = common->capacity;
+    out->state_array_bytes = (size_t)common->capacity * (state32(*common) ? 4 : 8);
+    out->workspace_bytes = L.total;
+    return DSMC_OK;
+}
+
+int dsmc_batch_init(const dsmc_config *common, const dsmc_replica *reps, int32_t nrep, const dsmc_buffers *buf,
+                    void *stream, dsmc_ctx **out)
+{
+    if (!out || !buf || !buf->workspace) return DSMC_EINVAL;
+    *out = nullptr;
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < 5; ++k)
+            if (!buf->state[b][k]) return DSMC_EINVAL;
+    if (((uintptr_t)buf->workspace & 255u) != 0) return DSMC_EINVAL;
+    return init_ctx(common, reps, nrep, buf, 0, 0, S(stream), out);
+}
+
+int dsmc_set_tiling(dsmc_ctx *x, int32_t particles_per_tile, void *stream)
+{
+    if (!x || particles_per_tile < 0 || particles_per_tile > (1 << 20)) return DSMC_EINVAL;
+    hipStream_t s = S(stream);
+    x->last = s;
+    return set_tiling(x, particles_per_tile, s);
+}
+
+int dsmc_autotune(dsmc_ctx *x, int32_t steps_per_trial, int32_t sample_every, dsmc_tuning *out, void *stream)
+{
+    if (!x || steps_per_trial < 1 || sample_every < 0) return DSMC_EINVAL;
+    hipStream_t s = S(stream);
+    x->last = s;
+    const bool f32 = state32(x->cfg);
+    const int cand_64[] = {100, 200, 400, 800};
+    const int cand_32[] = {200, 400, 800, 1600};
+    const int *cand = f32 ? cand_32 : cand_64;
+    const int ncand = 4;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return DSMC_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return DSMC_EHIP;
+    }
+    int rc = DSMC_OK, best = -1;
+    double best_ms = 0.0;
+    dsmc_tuning t;
+    std::memset(&t, 0, sizeof(t));
+    t.ncand = ncand;
+    for (int k = 0; k < ncand && rc == DSMC_OK; ++k) {
+        rc = set_tiling(x, cand[k], s);
+        if (rc != DSMC_OK) break;
+        // real steps of the run: every tiling gives the same results
+        if (hipEventRecord(e0, s) != hipSuccess) rc = DSMC_EHIP;
+        if (rc == DSMC_OK) rc = dsmc_step(x, steps_per_trial, sample_every, stream);
+        if (rc == DSMC_OK && hipEventRecord(e1, s) != hipSuccess) rc = DSMC_EHIP;
+        if (rc == DSMC_OK && hipEventSynchronize(e1) != hipSuccess) rc = DSMC_EHIP;
+        float ms = 0.0f;
+        if (rc == DSMC_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = DSMC_EHIP;
+        t.particles_per_tile[k] = cand[k];
+        t.ms_per_step[k] = (double)ms / steps_per_trial;
+        if (rc == DSMC_OK && (best < 0 || t.ms_per_step[k] < best_ms)) {
+            best = k;
+            best_ms = t.ms_per_step[k];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != DSMC_OK) return rc;
+    t.chosen = best;
+    rc = set_tiling(x, cand[best], s);
+    if (out) *out = t;
+    return rc;
+}
+
+int dsmc_replica_counters(dsmc_ctx *x, uint64_t *out, void *stream)
+{
+    if (!x || !out) return DSMC_EINVAL;
+    hipStream_t s = S(stream);
+    x->last = s;
+    k_replica_stats<<<(unsigned)x->nrep, 256, 0, s>>>(x->tstat, x->rep, x->rstat);
+    if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
+    if (hipMemcpyAsync(out, x->rstat, 3 * sizeof(uint64_t) * (size_t)x->nrep, hipMemcpyDeviceToHost, s) !=
+        hipSuccess)
+        return DSMC_EHIP;
+    return hipStreamSynchronize(s) == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
 int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
 {
     if (!x || nsteps < 0 || sample_every < 0) return DSMC_EINVAL;
     hipStream_t s = S(stream);
     x->last = s;
     const int nc = x->ncells;
-    const unsigned ntiles = (unsigned)x->ntiles;
     if (nsteps > 0 && !x->classified) {
         // moves of the coming step for a state set or changed from outside
         const int p = (int)(x->step & 1);
         TRY(fill_i32(x->farcnt, 2 * (size_t)nc, 0, s));
         k_far_reset<<<1, 64, 0, s>>>(x->ctr, p);
         const StepArgs a = step_args(x, x->cur, x->step, false, true);
-        TRY(launch(x, DSMC_K_CLASSIFY, s, [&] { launch_tiles(x, 0, true, ntiles, s, a); }));
+        TRY(launch(x, DSMC_K_CLASSIFY, s, [&] { launch_tiles(x, 0, true, s, a); }));
         x->classified = true;
     }
     for (int32_t it = 0; it < nsteps; ++it) {
@@ -801,8 +1046,8 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
         c.farcnt = x->farcnt + (size_t)p * nc;
         c.countnew = x->countnew;
         c.blocksum = x->blocksum;
-        c.nx = x->cfg.nx;
-        c.ny = x->cfg.ny;
+        c.rep = x->rep;
+        c.cell_rep = x->cell_rep;
         c.ncells = nc;
         TRY(launch(x, DSMC_K_CELL_COUNT, s, [&] { k_cell_count<<<x->nblk, 256, 0, s>>>(c); }));
         TRY(launch(x, DSMC_K_SCAN, s, [&] {
@@ -815,7 +1060,7 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
         const bool sample = sample_every > 0 && ((x->step + 1) % sample_every) == 0;
         const bool move = it + 1 < nsteps;  // the call's last step leaves the state settled
         const StepArgs a = step_args(x, cur, x->step, sample, false);
-        TRY(launch(x, DSMC_K_STEP, s, [&] { launch_tiles(x, 1, move, ntiles, s, a); }));
+        TRY(launch(x, DSMC_K_STEP, s, [&] { launch_tiles(x, 1, move, s, a); }));
         x->cur = nxt;
         if (sample) x->nsamples += 1;
         x->step += 1;
@@ -862,6 +1107,7 @@ static int project(dsmc_ctx *x, const double *mom, double S_, int64_t ncells, in
 int map_dsmc_to_lbm(dsmc_ctx *x, int32_t lattice, int32_t order, double *f_out, void *stream)
 {
     if (!x) return DSMC_EINVAL;
+    if (x->nrep != 1) return DSMC_ESTATE;  // one channel only
     if (!lattice_of(lattice) || order < 0 || order > 3 || !f_out) return DSMC_EINVAL;
     hipStream_t s = S(stream);
     x->last = s;
@@ -880,6 +1126,7 @@ int map_lbm_to_dsmc(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f
                     int32_t nsel, void *stream)
 {
     if (!x) return DSMC_EINVAL;
+    if (x->nrep != 1) return DSMC_ESTATE;  // one channel only
     const Lattice *L = lattice_of(lattice);
     if (!L || (order != 2 && order != 3) || !f_in || nsel < 0 || (nsel > 0 && !cell_ids)) return DSMC_EINVAL;
     if (nsel > x->ncells) return DSMC_EINVAL;
@@ -1088,7 +1335,7 @@ int dsmc_read_status(dsmc_ctx *x, dsmc_status *out, int32_t clear, void *stream)
     hipStream_t s = S(stream);
     Counters h;
     int32_t n = 0;
-    k_tile_stats<<<1, 1024, 0, s>>>(x->tstat, x->ntiles, x->ctr);
+    k_tile_stats<<<1, 1024, 0, s>>>(x->tstat, x->ncells, x->ctr);
     if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
     if (hipMemcpyAsync(&h, x->ctr, sizeof(Counters), hipMemcpyDeviceToHost, s) != hipSuccess) return DSMC_EHIP;
     if (hipMemcpyAsync(&n, x->cs[x->cur] + x->ncells, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)

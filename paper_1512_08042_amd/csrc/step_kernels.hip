@@ -39,60 +39,6 @@ __device__ __forceinline__ void add_moments(double *acc, double vx, double vy, d
     acc[10] += vz * vz;
 }
 
-// ---- NTC collisions of one cell (Eq. (collisionnumber)) -----------------------
-// Update the running mean of N, form the candidate count
-// 1/2 N Nbar K sigcmax dt + rem (K = F_N sigma_T / V_c), draw candidate
-// pairs uniformly (i != j), accept with probability c_r / sigcmax (hard
-// spheres), scatter isotropically in the centre-of-mass frame.  Candidate k
-// of cell c at step s draws from counters (2k, c, s, COLL) and, when
-// accepted, (2k+1, c, s, COLL).  v* address the cell's velocities (LDS or
-// global).
-__device__ __forceinline__ void ntc_cell(double *vx, double *vy, double *vz, int N, uint32_t c, const NtcParams &P,
-                                         double &nbar, double &sig, double &rem, unsigned long long &ncoll,
-                                         unsigned long long &ncand)
-{
-    const double Nd = (double)N;
-    nbar = nbar + (Nd - nbar) / (double)(P.step + 1);
-    const double pairf = (P.nbar_mode == 1) ? (Nd - 1.0) : nbar;
-    double X = 0.5 * Nd * pairf * P.K * sig * P.dt + rem;
-    if (!(X > 0.0)) X = 0.0;
-    const double Mf = floor(X);
-    rem = X - Mf;
-    if (N < 2) return;
-    const long long M = (long long)Mf;
-    for (long long k = 0; k < M; ++k) {
-        const U4 u = draw(P.k0, P.k1, (uint32_t)(2 * k), c, P.step, TAG_COLL, 0u);
-        const uint32_t i = (uint32_t)(((uint64_t)u.x * (uint64_t)(uint32_t)N) >> 32);
-        uint32_t j = (uint32_t)(((uint64_t)u.y * (uint64_t)(uint32_t)(N - 1)) >> 32);
-        if (j >= i) j += 1;
-        const double vxi = vx[i], vyi = vy[i], vzi = vz[i];
-        const double vxj = vx[j], vyj = vy[j], vzj = vz[j];
-        const double dx = vxi - vxj, dy = vyi - vyj, dz = vzi - vzj;
-        const double cr = sqrt(dx * dx + dy * dy + dz * dz);
-        if (cr > sig) sig = cr;
-        const double R = u53(u.z, u.w);
-        ncand += 1;
-        if (cr / sig > R) {
-            const U4 w = draw(P.k0, P.k1, (uint32_t)(2 * k + 1), c, P.step, TAG_COLL, 0u);
-            const double cth = 2.0 * u53(w.x, w.y) - 1.0;
-            const double sth = sqrt(1.0 - cth * cth);
-            double sphi, cphi;
-            sincos_turn(u53(w.z, w.w), sphi, cphi);  // phi = 2 pi R
-            const double rx = cr * cth;
-            const double ry = cr * sth * cphi;
-            const double rz = cr * sth * sphi;
-            const double mx = 0.5 * (vxi + vxj);
-            const double my = 0.5 * (vyi + vyj);
-            const double mz = 0.5 * (vzi + vzj);
-            const double ax = mx + 0.5 * rx, ay = my + 0.5 * ry, az = mz + 0.5 * rz;
-            const double bx = mx - 0.5 * rx, by = my - 0.5 * ry, bz = mz - 0.5 * rz;
-            vx[i] = ax, vy[i] = ay, vz[i] = az;
-            vx[j] = bx, vy[j] = by, vz[j] = bz;
-            ncoll += 1;
-        }
-    }
-}
-
 // ---- block-level integer scan helpers (256 threads) -------------------------
 __device__ __forceinline__ int block_reduce_256(int v, int *lds)
 {
@@ -258,13 +204,14 @@ __device__ __forceinline__ void tile_raw_group(const StepArgs &a, int c0, int nt
     if (lane >= TC * NDIR) return;
     const int t = lane / NDIR, d = lane - t * NDIR;
     if (t >= ntc) return;
-    const int nx = a.K().G.nx, c = c0 + t, ciy = c / nx, cix = c - ciy * nx;
-    const int sc = source_cell(nx, a.K().G.ny, cix, ciy, d);
+    const int cb = a.R().cbase, nx = a.R().G.nx;
+    const int c = c0 + t - cb, ciy = c / nx, cix = c - ciy * nx;
+    const int sc = source_cell(nx, a.R().G.ny, cix, ciy, d);  // inside the channel
     if (sc < 0) return;
-    const int32_t *g = a.grp_in() + (size_t)sc * GSTRIDE + d;
+    const int32_t *g = a.grp_in() + (size_t)(cb + sc) * GSTRIDE + d;
     src = g[0];
     n = g[1] - g[0];
-    if (n > 0) s = sc;
+    if (n > 0) s = cb + sc;
 }
 
 // The groups arriving in every cell of the tile, in the order of the stable
@@ -317,7 +264,7 @@ __device__ void tile_groups(const StepArgs &a, TileLds<TC, CH, S> &L, int ntc, i
     __syncthreads();
     if (lane < ntc && nfin > 0) {
         L.anyfar = 1;
-        tile_far_shift<TC, CH, S>(a, L, lane, L.tiy[lane] * nx + L.tix[lane], nfin);
+        tile_far_shift<TC, CH, S>(a, L, lane, a.R().cbase + L.tiy[lane] * nx + L.tix[lane], nfin);
     }
     __syncthreads();
 }
@@ -340,7 +287,7 @@ __device__ __forceinline__ void ntc_draws(TileLds<TC, CH, S> &L, const NtcParams
     const long long k = k0 + (lane - t * KC);
     if (lane < NTC_ROUND && t < ntc && k < L.mc[t]) {
         const uint32_t N = (uint32_t)(L.csn[t + 1] - L.csn[t]);
-        const uint32_t c = (uint32_t)(c0 + t);
+        const uint32_t c = (uint32_t)(c0 + t - P.cbase);  // the cell's index inside its channel
         const U4 u = draw(P.k0, P.k1, (uint32_t)(2 * k), c, P.step, TAG_COLL, 0u);
         const uint32_t i = (uint32_t)(((uint64_t)u.x * (uint64_t)N) >> 32);
         uint32_t j = (uint32_t)(((uint64_t)u.y * (uint64_t)(N - 1)) >> 32);
@@ -469,7 +416,7 @@ __device__ __forceinline__ bool move_chunk_free(const StepArgs &a, const TileLds
     bool wall = false;
     if (i < nt) {
         const int t = tile_cell<TC, CH, S>(L, ntc, L.csn[0], i);
-        const double dt = a.K().dt, g = a.K().g, H = a.K().G.H, Lx = a.K().G.Lx;
+        const double dt = a.R().dt, g = a.R().g, H = a.R().G.H, Lx = a.R().G.Lx;
         double x = s[0][i], vx = s[2][i];
         const double y = s[1][i], vy = s[3][i];
         // the no-wall branch of move_particle, written out
@@ -507,7 +454,8 @@ __device__ void move_chunk_walls(const StepArgs &a, const TileLds<TC, CH, S> &L,
     if (i < nt && kr[i] == KEY_WALL) {
         const int t = tile_cell<TC, CH, S>(L, ntc, L.csn[0], i);
         double x = s[0][i], y = s[1][i], vx = s[2][i], vy = s[3][i], vz = s[4][i];
-        walls += move_particle(a.geo(), a.M1(), (uint32_t)(L.csn[0] + i), x, y, vx, vy, vz, limit);
+        // wall draws are keyed by the slot inside the channel
+        walls += move_particle(a.geo(), a.M1(), (uint32_t)(L.csn[0] + i - a.R().pbase), x, y, vx, vy, vz, limit);
         const S xs = (S)x, ys = (S)y;
         s[0][i] = xs;
         s[1][i] = ys;
@@ -719,12 +667,13 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
         const int q = L.csn[t] + L.excl[key] + (k6 >> 6);
         int nix, niy;
         cell_xy(a.geo(), STAGED ? L.v[0][i] : a.template out<S>(0)[q], STAGED ? L.v[1][i] : a.template out<S>(1)[q], nix, niy);
-        record_far(a.far_out(), a.farcnt_out(), a.K().ctr, a.far_out_slot(), a.K().far_cap, q, c0 + t, niy * a.geo().nx + nix);
+        record_far(a.far_out(), a.farcnt_out(), a.K().ctr, a.far_out_slot(), a.K().far_cap, q, c0 + t,
+                   a.R().cbase + niy * a.geo().nx + nix);
     }
 }
 
 template <int TC, int CH, class S, bool GATHER, bool MOVE>
-__device__ __forceinline__ void tile_kernel(const StepArgs &a)
+__device__ __forceinline__ void tile_kernel(const StepArgs &a0)
 {
     static_assert(TC == 1 || TC == 2 || TC == 4, "tile sizes with teams of >= 16 lanes");
     static_assert(TC * NGRP <= 64 && NTC_ROUND <= 64, "");
@@ -732,14 +681,19 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a)
     __shared__ TileLds<TC, CH, S> L;
     constexpr int T = 64 / TC, SPAN = T / 16;
     const int lane = threadIdx.x;
-    const int nc = a.K().ncells, nx = a.geo().nx;
-    const int c0 = blockIdx.x * TC;
-    const int ntc = min(TC, nc - c0);
+    // the tile: up to TC consecutive cells of one channel
+    const __attribute__((address_space(4))) int32_t *td =
+        (const __attribute__((address_space(4))) int32_t *)a0.tiles + 2 * (size_t)blockIdx.x;
+    const int c0 = td[0];
+    StepArgs a = a0;
+    a.r = td[1];
+    const int nc = a.K().ncells, nx = a.geo().nx, cb = a.R().cbase, ce = a.R().cend;
+    const int ntc = min(TC, ce - c0);
 
     // set-up: every per-cell quantity of the tile is loaded in one round
-    if (lane <= TC) L.csn[lane] = a.cs_new()[min(c0 + lane, nc)];
+    if (lane <= TC) L.csn[lane] = a.cs_new()[min(c0 + lane, ce)];
     if (lane < TC) {
-        const int c = min(c0 + lane, nc - 1);
+        const int c = min(c0 + lane, ce - 1) - cb;  // position inside the channel
         L.tiy[lane] = c / nx;
         L.tix[lane] = c - (c / nx) * nx;
     }
@@ -758,7 +712,8 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a)
     double mprev = 0.0;
     if (mown) mprev = *mdst;
     const int n_old = GATHER ? a.cs_old()[nc] : 0;
-    unsigned long long *const tst = a.K().tstat + 3 * (size_t)blockIdx.x + (lane < 3 ? lane : 0);
+    // running counters of the tile, kept at its first cell (valid for any tiling)
+    unsigned long long *const tst = a.K().tstat + 3 * (size_t)c0 + (lane < 3 ? lane : 0);
     const unsigned long long tprev = lane < 3 ? *tst : 0ull;
     if (GATHER && lane < TC * NDIR) {
         int s, n, src;
@@ -828,11 +783,14 @@ __global__ __launch_bounds__(256) void k_cell_count(CellArgs a)
     const int c = blockIdx.x * 256 + threadIdx.x;
     int total = 0;
     if (c < a.ncells) {
-        const int cix = c % a.nx, ciy = c / a.nx;
+        const RepConst &R = a.rep[a.cell_rep[c]];
+        const int nx = R.G.nx, ny = R.G.ny, cb = R.cbase;
+        const int cix = (c - cb) % nx, ciy = (c - cb) / nx;
 #pragma unroll
         for (int d = 0; d < NDIR; ++d) {
-            const int src = source_cell(a.nx, a.ny, cix, ciy, d);
-            if (src >= 0) total += a.grp[(size_t)src * GSTRIDE + d + 1] - a.grp[(size_t)src * GSTRIDE + d];
+            const int src = source_cell(nx, ny, cix, ciy, d);  // inside the channel
+            if (src >= 0)
+                total += a.grp[(size_t)(cb + src) * GSTRIDE + d + 1] - a.grp[(size_t)(cb + src) * GSTRIDE + d];
         }
         total += a.farcnt[c];
         a.countnew[c] = total;
@@ -891,7 +849,7 @@ template <class S>
 __global__ __launch_bounds__(256) void k_init_maxwell(InitArgs a)
 {
     const size_t g = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (g <= (size_t)a.ncells) a.cs[g] = (int32_t)(g * (size_t)a.ppc);
+    if (g <= (size_t)a.ncells) a.cs[g] = (int32_t)((size_t)a.pbase + g * (size_t)a.ppc);
     if (g < (size_t)a.ncells) {
         a.nbar[g] = 0.0;
         a.sigcmax[g] = a.sigcr0;
@@ -1028,11 +986,12 @@ __global__ void k_clear_status(Counters *c)
 }
 
 // totals of the per-tile counters (one workgroup of 1024)
-__global__ __launch_bounds__(1024) void k_tile_stats(const unsigned long long *tstat, int ntiles, Counters *c)
+// totals of the tile counters (kept at the tiles' first cells: n entries)
+__global__ __launch_bounds__(1024) void k_tile_stats(const unsigned long long *tstat, int n, Counters *c)
 {
     __shared__ unsigned long long part[3][16];
     unsigned long long v[3] = {0ull, 0ull, 0ull};
-    for (int t = threadIdx.x; t < ntiles; t += 1024) {
+    for (int t = threadIdx.x; t < n; t += 1024) {
         v[0] += tstat[3 * (size_t)t];
         v[1] += tstat[3 * (size_t)t + 1];
         v[2] += tstat[3 * (size_t)t + 2];
@@ -1051,6 +1010,31 @@ __global__ __launch_bounds__(1024) void k_tile_stats(const unsigned long long *t
         c->ncoll = tot[0];
         c->ncand = tot[1];
         c->nwall = tot[2];
+    }
+}
+
+// per channel: the sums of its cells' tile counters -> out[r][3]
+__global__ __launch_bounds__(256) void k_replica_stats(const unsigned long long *tstat, const RepConst *rep,
+                                                       unsigned long long *out)
+{
+    __shared__ unsigned long long part[3][4];
+    const RepConst &R = rep[blockIdx.x];
+    unsigned long long v[3] = {0ull, 0ull, 0ull};
+    for (int c = R.cbase + (int)threadIdx.x; c < R.cend; c += 256) {
+        v[0] += tstat[3 * (size_t)c];
+        v[1] += tstat[3 * (size_t)c + 1];
+        v[2] += tstat[3 * (size_t)c + 2];
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[k] = wave_sum_u64(v[k]);
+        if (lane == 0) part[k][w] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        out[3 * (size_t)blockIdx.x + k] = part[k][0] + part[k][1] + part[k][2] + part[k][3];
     }
 }
 

@@ -14,6 +14,22 @@ struct NtcParams {
     uint32_t k0, k1;    // Philox key
     uint32_t step;      // index of the step whose collisions these are
     int nbar_mode;
+    int cbase;          // first cell of the channel (draws are keyed by the cell's index inside it)
+};
+
+// One channel of a context.  A context holds one channel, or a batch of
+// independent channels (replicas) stored one after the other in the cell
+// and particle arrays; every replica keeps its own geometry, time step,
+// force, collision constant and Philox key, and its random draws are keyed
+// by cell and slot indices inside the replica, so each replica evolves
+// exactly as the same channel alone would.
+struct RepConst {
+    Geometry G;
+    double dt, g, K;       // time step, acceleration, F_N sigma_T / V_c
+    uint32_t k0, k1;       // Philox key (the replica's seed)
+    int32_t cbase, cend;   // its cells [cbase, cend) in the context's cell arrays
+    int32_t pbase;         // its first particle slot (fixed: no particle leaves its channel)
+    int32_t ppc;
 };
 
 // Per-cell partition of a moved state: inside every old cell's slot range
@@ -38,10 +54,9 @@ struct TileConst {
     unsigned long long *tstat;  // [tiles][3] running collisions, candidates and wall hits of every tile
     double *mom;             // [11][ncells] sums
     double *nbar, *sigcmax, *rem;
-    Geometry G;
-    double dt, g, s_th, K;   // time step, acceleration, sqrt(kT/m), F_N sigma_T / V_c
-    uint32_t k0, k1;         // Philox key
-    int nbar_mode, ncells, far_cap;
+    const RepConst *rep;     // [nrep] the channels
+    double s_th;             // sqrt(kT/m)
+    int nbar_mode, ncells, far_cap, nrep;
 };
 
 // One launch of a step kernel.  k_step: the DSMC step `step` (collisions
@@ -51,23 +66,29 @@ struct TileConst {
 // the partition read by the step's sort.
 struct StepArgs {
     const TileConst *kc;
+    const int32_t *tiles;  // [tiles][2]: first cell and replica of every tile of the launch
     uint32_t step;
     int cur, sample, classify;
+    int r;                 // replica of the tile (set by the tile kernel)
 
-    // the block is read through the constant address space: it does not
-    // change while a kernel runs, so its fields come in by scalar loads
+    // the blocks are read through the constant address space: they do not
+    // change while a kernel runs, so their fields come in by scalar loads
     __device__ const __attribute__((address_space(4))) TileConst &K() const
     {
         return *(const __attribute__((address_space(4))) TileConst *)kc;
+    }
+    __device__ const __attribute__((address_space(4))) RepConst &R() const
+    {
+        return ((const __attribute__((address_space(4))) RepConst *)K().rep)[r];
     }
 
     __device__ Geometry geo() const
     {
         Geometry g;
-        g.nx = K().G.nx;
-        g.ny = K().G.ny;
-        g.Lx = K().G.Lx;
-        g.H = K().G.H;
+        g.nx = R().G.nx;
+        g.ny = R().G.ny;
+        g.Lx = R().G.Lx;
+        g.H = R().G.H;
         return g;
     }
     __device__ int po() const { return classify ? (int)(step & 1u) : (int)((step + 1u) & 1u); }
@@ -88,23 +109,24 @@ struct StepArgs {
     __device__ MoveParams M1() const
     {
         MoveParams M;
-        M.dt = K().dt;
-        M.g = K().g;
+        M.dt = R().dt;
+        M.g = R().g;
         M.s_th = K().s_th;
-        M.k0 = K().k0;
-        M.k1 = K().k1;
+        M.k0 = R().k0;
+        M.k1 = R().k1;
         M.step = classify ? step : step + 1u;
         return M;
     }
     __device__ NtcParams N() const
     {
         NtcParams P;
-        P.K = K().K;
-        P.dt = K().dt;
-        P.k0 = K().k0;
-        P.k1 = K().k1;
+        P.K = R().K;
+        P.dt = R().dt;
+        P.k0 = R().k0;
+        P.k1 = R().k1;
         P.step = step;
         P.nbar_mode = K().nbar_mode;
+        P.cbase = R().cbase;
         return P;
     }
 };
@@ -114,14 +136,19 @@ struct CellArgs {
     const int32_t *farcnt;   // [ncells] long jumps arriving per cell
     int32_t *countnew;
     int32_t *blocksum;
-    int nx, ny, ncells;
+    const RepConst *rep;     // the channels
+    const int32_t *cell_rep; // [ncells] channel of every cell
+    int ncells;
 };
 
+// the initial Maxwellian of one channel: its cells start at cs, nbar, ...
+// (already offset to its first cell), its particles at st (offset to its
+// first slot); cell starts are written as pbase + c * ppc
 struct InitArgs {
     void *st[5];  // double or float
     int32_t *cs;
     double *nbar, *sigcmax, *rem;
-    int nx, ncells, ppc;
+    int nx, ncells, ppc, pbase;
     double s_th, sigcr0;
     uint32_t k0, k1;
 };
@@ -296,6 +323,7 @@ __global__ void k_fill_i32(int32_t *p, size_t n, int32_t v);
 __global__ void k_zero_counters(Counters *c);
 __global__ void k_clear_status(Counters *c);
 __global__ void k_tile_stats(const unsigned long long *tstat, int ntiles, Counters *c);
+__global__ void k_replica_stats(const unsigned long long *tstat, const RepConst *rep, unsigned long long *out);
 __global__ void k_far_reset(Counters *c, int slot);
 
 __global__ void k_project(ProjectArgs a);

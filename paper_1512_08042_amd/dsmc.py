@@ -152,6 +152,107 @@ class Channel:
         return ms.value, n.value
 
 
+class Batch(Channel):
+    """Independent channels (replicas) of different size, particles per cell,
+    Knudsen number, time step, force and seed, stepped together: every
+    replica evolves bit for bit as a Channel with its parameters would.
+
+    replicas: a list of dicts with nx, ny, ppc, kn and optionally dt,
+    body_force_x (or mach), seed; common: ChannelConfig-like settings shared
+    by all (kT_over_m, sigcr_max0, nbar_mode, state_bits, capacity)."""
+
+    def __init__(self, replicas, kT_over_m: float = 1.0, sigcr_max0: float = 6.0, nbar_mode: int = 0,
+                 state_bits: int = 64, capacity: int | None = None, far_capacity: int = 0, device: str = "cuda",
+                 stream=None):
+        from .config import body_force, time_step
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1512_08042_amd needs a ROCm GPU; no CPU fallback exists")
+        self.device = torch.device(device)
+        self.nrep = len(replicas)
+        reps = (_lib.Replica * self.nrep)()
+        self.replicas = []
+        npart = 0
+        for i, r in enumerate(replicas):
+            nx, ny, ppc, kn = int(r.get("nx", 1)), int(r["ny"]), int(r["ppc"]), float(r["kn"])
+            dt = float(r["dt"]) if r.get("dt") is not None else time_step(kn, ny, kT_over_m)
+            g = r.get("body_force_x")
+            if g is None:
+                g = body_force(kn, ny, float(r["mach"]), kT_over_m) if r.get("mach") else 0.0
+            seed = int(r.get("seed", 1000 + i))
+            reps[i] = _lib.Replica(nx, ny, ppc, 0, kn, dt, float(g), seed)
+            self.replicas.append(dict(nx=nx, ny=ny, ppc=ppc, kn=kn, dt=dt, body_force_x=float(g), seed=seed))
+            npart += nx * ny * ppc
+        if capacity is None:
+            capacity = int(npart * 1.05) + 1024
+        self.cfg = None
+        self._reps = reps
+        self._c = _lib.Config(1, 1, 1, int(nbar_mode), int(capacity), 1.0, 1.0, 0.0, float(kT_over_m),
+                              float(sigcr_max0), 0, 0, int(far_capacity), int(state_bits), 0)
+        sz = _lib.Sizes()
+        check(lib().dsmc_batch_query_sizes(ctypes.byref(self._c), reps, self.nrep, ctypes.byref(sz)),
+              "dsmc_batch_query_sizes")
+        self.ncells = int(sz.ncells)
+        self.capacity = int(sz.capacity)
+        self.state_dtype = torch.float32 if int(state_bits) == 32 else torch.float64
+        self.state = torch.zeros((2, 5, self.capacity), dtype=self.state_dtype, device=self.device)
+        self.workspace = torch.zeros(int(sz.workspace_bytes) + 256, dtype=torch.uint8, device=self.device)
+        self._ws = (_ptr(self.workspace) + 255) & ~255
+        b = _lib.Buffers()
+        for i in range(2):
+            for k in range(5):
+                b.state[i][k] = _ptr(self.state[i, k])
+        b.workspace = self._ws
+        b.workspace_bytes = int(sz.workspace_bytes)
+        self._h = ctypes.c_void_p()
+        check(lib().dsmc_batch_init(ctypes.byref(self._c), reps, self.nrep, ctypes.byref(b), _stream(stream),
+                                    ctypes.byref(self._h)), "dsmc_batch_init")
+        # cell ranges of the replicas (their particle ranges follow cell_start)
+        self.cell_base = []
+        c = 0
+        for r in self.replicas:
+            self.cell_base.append(c)
+            c += r["nx"] * r["ny"]
+        self.cell_base.append(c)
+
+    def replica_cells(self, r: int):
+        return self.cell_base[r], self.cell_base[r + 1]
+
+    def replica_particles(self, r: int):
+        """(x, y, vx, vy, vz) device views of replica r's particles, cell-sorted."""
+        c0, c1 = self.replica_cells(r)
+        cs = self.cell_start()
+        p0, p1 = int(cs[c0]), int(cs[c1])
+        cur = self.views().current
+        return tuple(self.state[cur, k, p0:p1] for k in range(5))
+
+    def replica_cell_start(self, r: int) -> torch.Tensor:
+        """cell_start of replica r relative to its first particle."""
+        c0, c1 = self.replica_cells(r)
+        cs = self.cell_start()[c0:c1 + 1]
+        return cs - cs[0]
+
+    def replica_counters(self, stream=None):
+        """[(ncoll, ncand, nwall)] per replica since init."""
+        import numpy as np
+
+        out = np.zeros((self.nrep, 3), dtype=np.uint64)
+        check(lib().dsmc_replica_counters(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                          _stream(stream)), "dsmc_replica_counters")
+        return out
+
+    def set_tiling(self, particles_per_tile: int = 0, stream=None):
+        check(lib().dsmc_set_tiling(self._h, int(particles_per_tile), _stream(stream)), "dsmc_set_tiling")
+
+    def autotune(self, steps_per_trial: int = 2, sample_every: int = 0, stream=None) -> dict:
+        t = _lib.Tuning()
+        check(lib().dsmc_autotune(self._h, int(steps_per_trial), int(sample_every), ctypes.byref(t),
+                                  _stream(stream)), "dsmc_autotune")
+        return {"particles_per_tile": [t.particles_per_tile[i] for i in range(t.ncand)],
+                "ms_per_step": [t.ms_per_step[i] for i in range(t.ncand)],
+                "chosen": t.particles_per_tile[t.chosen]}
+
+
 def project_moments(avg: torch.Tensor, ppc: int, lattice_q: int, order: int, kT_over_m: float = 1.0,
                     stream=None) -> torch.Tensor:
     """DSMC2LB projection of given per-cell averages avg[11][ncells] (device FP64)."""

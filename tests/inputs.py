@@ -50,3 +50,15 @@ def strip_cells(nx: int, ny: int, width: int):
     ix = np.arange(width)
     iy = np.arange(ny)
     return (iy[:, None] * nx + ix[None, :]).ravel().astype(np.int32)
+
+
+def replica_params(seed: int, n: int, ny_range=(32, 512), ppc_range=(20, 200), kn_range=(0.01, 1.0)):
+    """n independent channel replicas of one cell across x: ny and ppc uniform
+    integers over the closed ranges, Kn log-uniform over kn_range, seeds
+    1000 + index."""
+    rng = np.random.default_rng(seed)
+    ny = rng.integers(ny_range[0], ny_range[1] + 1, n)
+    ppc = rng.integers(ppc_range[0], ppc_range[1] + 1, n)
+    kn = np.exp(rng.uniform(np.log(kn_range[0]), np.log(kn_range[1]), n))
+    return [dict(nx=1, ny=int(a), ppc=int(b), kn=float(c), seed=1000 + i)
+            for i, (a, b, c) in enumerate(zip(ny, ppc, kn))]

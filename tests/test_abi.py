@@ -114,3 +114,25 @@ def test_adjoint_entries_validate_without_gpu():
     assert L.dsmc_project_moments_adjoint(p, p, 0, 100, 1.0, 37, 3, p, None) == 0
     assert L.dsmc_project_moments_adjoint(p, p, 10, 0, 1.0, 37, 3, p, None) == _lib.EINVAL
     assert L.dsmc_project_moments_adjoint(p, p, 10, 100, -1.0, 37, 3, p, None) == _lib.EINVAL
+
+
+def test_batch_sizes_validate_without_gpu():
+    L = _lib.lib()
+    common = _lib.Config(1, 1, 1, 0, 100000, 1.0, 1.0, 0.0, 1.0, 6.0, 0, 0, 0)
+    reps = (_lib.Replica * 3)(_lib.Replica(1, 40, 50, 0, 0.1, 0.05, 1e-3, 7),
+                              _lib.Replica(2, 10, 20, 0, 0.5, 0.1, 0.0, 8),
+                              _lib.Replica(1, 64, 30, 0, 0.02, 0.01, 1e-4, 9))
+    s = _lib.Sizes()
+    assert L.dsmc_batch_query_sizes(ctypes.byref(common), reps, 3, ctypes.byref(s)) == 0
+    assert s.ncells == 40 + 20 + 64 and s.workspace_bytes > 0
+    one = _lib.Sizes()
+    assert L.dsmc_batch_query_sizes(ctypes.byref(common), reps, 1, ctypes.byref(one)) == 0
+    assert one.ncells == 40 and one.workspace_bytes < s.workspace_bytes
+    assert L.dsmc_batch_query_sizes(ctypes.byref(common), reps, 0, ctypes.byref(s)) == _lib.EINVAL
+    bad = (_lib.Replica * 1)(_lib.Replica(1, 40, 50, 0, 0.0, 0.05, 0.0, 7))  # Kn must be positive
+    assert L.dsmc_batch_query_sizes(ctypes.byref(common), bad, 1, ctypes.byref(s)) == _lib.EINVAL
+    bad[0] = _lib.Replica(1, 0, 50, 0, 0.1, 0.05, 0.0, 7)  # no rows
+    assert L.dsmc_batch_query_sizes(ctypes.byref(common), bad, 1, ctypes.byref(s)) == _lib.EINVAL
+    assert L.dsmc_set_tiling(None, 100, None) == _lib.EINVAL
+    assert L.dsmc_autotune(None, 2, 1, None, None) == _lib.EINVAL
+    assert L.dsmc_replica_counters(None, None, None) == _lib.EINVAL
