@@ -30,6 +30,13 @@ Printed JSON line: metric, value, ..., plus
             time per gradient, the adjoint and forward lattice kernels against
             the HBM roofline, and the gradient against central differences of
             the library's own forward;
+  batched:  256 independent Poiseuille channels of one cell across x, ny
+            uniform in 32..512, particles per cell uniform in 20..200, Kn
+            log-uniform in [0.01, 1], Ma 0.1, seeds 1000 + r, FP64, 500 steps
+            sampled every step: stepped together (tiling chosen by the
+            autotuner, steps replayed from a HIP graph) against the plain
+            form, one channel context per replica run one after another;
+            every replica's moments are compared bit for bit between the two;
   precision: the FP32-state form against plain FP64 on a 2048 x 1024 x 50
             channel (Kn 0.02, Ma 0.1): particle-steps/s of each, and per
             moment order the RMS and mean over cells of z = (m32 - m64) / SE,
@@ -73,11 +80,11 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_512x256x100_fp64_traffi
 TRACE_SUMMARY = os.path.join(ROOT, "profiles", "dsmc_cycle_512x256x100_fp64_kernel_trace.md")
 # the commands whose output the summaries condense (run from the repository root)
 TRACE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace -o trace -- "
-             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-precision --no-adjoint")
+             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-precision --no-adjoint --no-batched")
 PMC_CMDS = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --copy-calibration",
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --copy-calibration",
             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --copy-calibration")
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --copy-calibration")
 # kernel-name prefixes of the library's kernels, by profiling id
 KERNEL_PREFIX = {"step": "void dsmc::k_step<", "classify": "void dsmc::k_classify<"}
 ADJ_TRACE_SUMMARY = os.path.join(ROOT, "profiles", "lbm_adjoint_1024x512_d2q37_kernel_trace.md")
@@ -300,6 +307,103 @@ def adjoint_benchmark(reps=3):
     }
 
 
+# the batched workload
+BATCH = dict(seed=3, nrep=256, mach=0.1, steps=500, graph_steps=10, tune_steps=2)
+
+
+def batched_comparison():
+    """Batched vs plain FP64 on the batched workload: particle-steps/s of
+    each over the same 500 sampled steps, and the replicas' moments compared
+    bit for bit (equal moment error)."""
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import inputs
+
+    from paper_1512_08042_amd import ChannelConfig
+    from paper_1512_08042_amd import dsmc as D
+
+    B = BATCH
+    reps = inputs.replica_params(B["seed"], B["nrep"])
+    for r in reps:
+        r["mach"] = B["mach"]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    b = D.Batch(reps, stream=stream)
+    n = b.status(stream=stream)["n"]
+    t0 = time.perf_counter()
+    tune = b.autotune(B["tune_steps"], 1, stream=stream)  # real steps: 4 candidates
+    stream.synchronize()
+    t_tune = time.perf_counter() - t0
+    done = B["tune_steps"] * len(tune["particles_per_tile"])
+    b.reset_moments(stream=stream)  # average over the steps after tuning
+    b.graph_create(B["graph_steps"], 1, stream=stream)
+    nrep_launch = (B["steps"] - done) // B["graph_steps"]
+    rest = B["steps"] - done - nrep_launch * B["graph_steps"]
+    stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nrep_launch):
+        b.graph_launch(stream=stream)
+    if rest:
+        b.step(rest, 1, stream=stream)
+    stream.synchronize()
+    t_batched = time.perf_counter() - t0
+    steps_timed = nrep_launch * B["graph_steps"] + rest
+    avg_b = b.sample_moments(stream=stream).cpu().numpy()
+    st = b.status(stream=stream)
+    stream.synchronize()
+
+    # plain: one context per replica (with the tiling the autotuner chose, so
+    # that even the moment sums add in the same order), each run for the same
+    # 500 steps in turn
+    chans = []
+    for r in reps:
+        c = D.Channel(ChannelConfig(nx=r["nx"], ny=r["ny"], ppc=r["ppc"], kn=r["kn"], mach=r["mach"], seed=r["seed"]))
+        c.set_tiling(tune["chosen"])
+        chans.append(c)
+    for c in chans:  # the autotuner's steps, then the same sampled steps
+        c.step(done, sample_every=1)
+        c.reset_moments()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in chans:
+        c.step(steps_timed, sample_every=1)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = 0
+    for i, c in enumerate(chans):
+        c0, c1 = b.replica_cells(i)
+        eq = np.array_equal(c.sample_moments().cpu().numpy(), avg_b[:, c0:c1])
+        eq = eq and all(torch.equal(p, q) for p, q in zip(c.particles(), b.replica_particles(i)))
+        same += int(eq)
+        c.close()
+    del chans
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    v_b = n * steps_timed / t_batched
+    v_p = n * steps_timed / t_plain
+    return {
+        "workload": "%d channel replicas (nx 1, ny U{32..512}, ppc U{20..200}, Kn log-U[0.01,1], Ma %.1f, seeds "
+                    "1000+r), %d particles, FP64, %d steps sampled every step" % (B["nrep"], B["mach"], n, B["steps"]),
+        "batched_particle_steps_per_s": float("%.4g" % v_b),
+        "plain_particle_steps_per_s": float("%.4g" % v_p),
+        "batched_speedup": round(v_b / v_p, 2),
+        "batched_ms_per_step": round(1e3 * t_batched / steps_timed, 4),
+        "plain_ms_per_step": round(1e3 * t_plain / steps_timed, 4),
+        "batched_timed": "%d graph replays of %d steps%s after %d autotuner steps" % (
+            nrep_launch, B["graph_steps"], (" + %d eager" % rest) if rest else "", done),
+        "autotune": {"particles_per_tile": tune["particles_per_tile"],
+                     "ms_per_step": [round(v, 4) for v in tune["ms_per_step"]], "chosen": tune["chosen"],
+                     "seconds": round(t_tune, 3)},
+        "replicas_bitwise_equal_to_plain": "%d/%d (particles, and moment sums over the %d timed steps)" % (
+            same, B["nrep"], steps_timed),
+        "step_roofline_frac": round(80.0 * v_b / 1e9 / HBM_PEAK_GBPS, 4),
+        "status_bits": st["bits"],
+    }
+
+
 def source_hash() -> str:
     """sha256 over the library's kernel sources and its C header."""
     h = hashlib.sha256()
@@ -432,6 +536,9 @@ def _parse():
     ap.add_argument("--cpu-cycles", type=int, default=8, help="coupling cycles the CPU oracle is timed on")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32-vs-FP64 comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-replica workload")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched-replica workload and print its JSON object")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the differentiation workload and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -502,6 +609,9 @@ def main():
         del src, dst
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_benchmark()}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": batched_comparison()}), flush=True)
         return
     cfg = ChannelConfig(nx=NX, ny=NY, ppc=PPC, kn=KN, mach=MACH, seed=SEED).resolved()
     ch = D.Channel(cfg)
@@ -590,6 +700,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_benchmark()
+        torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = batched_comparison()
         torch.cuda.empty_cache()
     if not args.no_precision:
         out["precision"] = precision_comparison()

@@ -23,7 +23,8 @@ EXPORTS = ("dsmc_query_sizes", "dsmc_init", "dsmc_step", "dsmc_sample_moments", 
            "dsmc_get_views", "dsmc_profile_enable", "dsmc_profile_read", "dsmc_destroy", "dsmc_strerror",
            "lbm_step_checkpointed", "lbm_adjoint_workspace", "lbm_adjoint_step", "lbm_adjoint",
            "lbm_hermite_moments", "lbm_hermite_moments_adjoint", "dsmc_project_moments_adjoint",
-           "dsmc_batch_query_sizes", "dsmc_batch_init", "dsmc_set_tiling", "dsmc_autotune", "dsmc_replica_counters")
+           "dsmc_batch_query_sizes", "dsmc_batch_init", "dsmc_set_tiling", "dsmc_autotune", "dsmc_replica_counters",
+           "dsmc_graph_create", "dsmc_graph_launch")
 
 
 class Config(ctypes.Structure):
@@ -103,6 +104,8 @@ def lib():
         L.dsmc_set_tiling.argtypes = [c_p, c_i32, c_p]
         L.dsmc_autotune.argtypes = [c_p, c_i32, c_i32, P(Tuning), c_p]
         L.dsmc_replica_counters.argtypes = [c_p, P(c_u64), c_p]
+        L.dsmc_graph_create.argtypes = [c_p, c_i32, c_i32, c_p]
+        L.dsmc_graph_launch.argtypes = [c_p, c_p]
         L.dsmc_get_views.argtypes = [c_p, P(Views)]
         L.dsmc_profile_enable.argtypes = [c_p, c_i32]
         L.dsmc_profile_read.argtypes = [c_p, c_i32, P(c_d), P(c_i64)]

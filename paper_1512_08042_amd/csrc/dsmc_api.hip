@@ -339,6 +339,12 @@ struct dsmc_ctx {
     std::vector<TileGroup> groups;
     std::vector<int32_t> tiles_host;
     int particles_per_tile;
+    // a captured step graph: nsteps steps (a dsmc_step call) replayable from
+    // any even step aligned with its sampling period
+    bool capturing;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    int32_t g_nsteps, g_sample_every, g_cur;
     int64_t step, nsamples, reseed_events;
     // Inside a dsmc_step call the state between steps is kept already moved
     // for the coming step and partitioned by direction inside every cell
@@ -397,6 +403,7 @@ StepArgs step_args(const dsmc_ctx *x, int32_t cur, int64_t step, bool sample, bo
     a.kc = x->kc;
     a.tiles = x->tiles;
     a.r = 0;
+    a.dev_step = x->capturing ? 1 : 0;
     a.step = (uint32_t)step;
     a.cur = cur;
     a.sample = sample ? 1 : 0;
@@ -822,6 +829,10 @@ int init_ctx(const dsmc_config *cfg, const dsmc_replica *reps, int32_t nrep, con
     x->classified = false;
     x->prof = false;
     x->last = s;
+    x->capturing = false;
+    x->graph = nullptr;
+    x->gexec = nullptr;
+    x->g_nsteps = 0;
 
     int rc = DSMC_OK;
     if (hipMemcpyAsync(x->rep, x->reps.data(), sizeof(RepConst) * (size_t)nrep, hipMemcpyHostToDevice, s) !=
@@ -1402,9 +1413,73 @@ int dsmc_profile_read(dsmc_ctx *x, int32_t kernel, double *ms_total, int64_t *la
     return DSMC_OK;
 }
 
+int dsmc_graph_create(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
+{
+    if (!x || nsteps < 2 || (nsteps & 1) || sample_every < 0) return DSMC_EINVAL;
+    if (sample_every > 0 && nsteps % sample_every != 0) return DSMC_EINVAL;
+    hipStream_t s = S(stream);
+    if (s == nullptr) return DSMC_EINVAL;  // capture needs a created stream
+    if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
+    if (x->graph) (void)hipGraphDestroy(x->graph);
+    x->gexec = nullptr;
+    x->graph = nullptr;
+    x->g_nsteps = 0;
+    // capture one dsmc_step call with steps counted from 0; the host-side
+    // bookkeeping of the capture is undone afterwards (nothing ran)
+    const int64_t step = x->step, nsamples = x->nsamples;
+    const int cur = x->cur;
+    const bool prof = x->prof;
+    x->step = 0;
+    x->prof = false;
+    x->capturing = true;
+    int rc = DSMC_OK;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = DSMC_EHIP;
+    const int rc_step = rc == DSMC_OK ? dsmc_step(x, nsteps, sample_every, stream) : DSMC_OK;
+    hipGraph_t g = nullptr;
+    if (rc == DSMC_OK && hipStreamEndCapture(s, &g) != hipSuccess) rc = DSMC_EHIP;
+    if (rc == DSMC_OK) rc = rc_step;
+    if (rc == DSMC_OK && hipGraphInstantiate(&x->gexec, g, nullptr, nullptr, 0) != hipSuccess) rc = DSMC_EHIP;
+    x->capturing = false;
+    x->step = step;
+    x->nsamples = nsamples;
+    x->cur = cur;
+    x->prof = prof;
+    x->classified = false;
+    if (rc != DSMC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        x->gexec = nullptr;
+        return rc;
+    }
+    x->graph = g;
+    x->g_nsteps = nsteps;
+    x->g_sample_every = sample_every;
+    x->g_cur = cur;
+    return DSMC_OK;
+}
+
+int dsmc_graph_launch(dsmc_ctx *x, void *stream)
+{
+    if (!x) return DSMC_EINVAL;
+    if (!x->gexec) return DSMC_ESTATE;
+    // the captured parities and sampling pattern must hold from this step
+    if ((x->step & 1) || x->cur != x->g_cur) return DSMC_ESTATE;
+    if (x->g_sample_every > 0 && x->step % x->g_sample_every != 0) return DSMC_ESTATE;
+    if (x->step + x->g_nsteps > (int64_t)0xFFFFFFFF) return DSMC_ESTATE;
+    hipStream_t s = S(stream);
+    x->last = s;
+    k_set_step_base<<<1, 64, 0, s>>>(x->ctr, (uint32_t)x->step);
+    if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
+    if (hipGraphLaunch(x->gexec, s) != hipSuccess) return DSMC_EHIP;
+    x->step += x->g_nsteps;
+    if (x->g_sample_every > 0) x->nsamples += x->g_nsteps / x->g_sample_every;
+    return DSMC_OK;
+}
+
 void dsmc_destroy(dsmc_ctx *x)
 {
     if (!x) return;
+    if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
+    if (x->graph) (void)hipGraphDestroy(x->graph);
     for (const ProfRec &r : x->recs) {
         (void)hipEventSynchronize(r.b);
         (void)hipEventDestroy(r.a);

@@ -43,6 +43,8 @@ struct Counters {
     uint32_t nfar[2];     // long jumps of the step, double-buffered by step parity
     unsigned long long ncoll, ncand, nwall, nfar_total;
     unsigned long long reseed_new, reseed_removed;  // particle totals of the reseed in progress
+    uint32_t step_base;   // first step of a replayed step graph (added to the steps it was captured with)
+    uint32_t pad;
 };
 
 struct U4 {

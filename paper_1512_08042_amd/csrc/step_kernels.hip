@@ -687,6 +687,9 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     const int c0 = td[0];
     StepArgs a = a0;
     a.r = td[1];
+    // a step graph is captured with steps counted from 0 and replayed from
+    // the step the host sets (an even one, so every parity is unchanged)
+    if (a0.dev_step) a.step += ((const __attribute__((address_space(4))) Counters *)a.K().ctr)->step_base;
     const int nc = a.K().ncells, nx = a.geo().nx, cb = a.R().cbase, ce = a.R().cend;
     const int ntc = min(TC, ce - c0);
 
@@ -971,7 +974,14 @@ __global__ void k_zero_counters(Counters *c)
         c->ncand = 0ull;
         c->nwall = 0ull;
         c->nfar_total = 0ull;
+        c->step_base = 0u;
     }
+}
+
+// the first step of the step graph about to be replayed
+__global__ void k_set_step_base(Counters *c, uint32_t step)
+{
+    if (threadIdx.x == 0) c->step_base = step;
 }
 
 // discard the long-jump list of one parity (its classification is void)

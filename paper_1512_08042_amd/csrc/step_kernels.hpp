@@ -70,6 +70,7 @@ struct StepArgs {
     uint32_t step;
     int cur, sample, classify;
     int r;                 // replica of the tile (set by the tile kernel)
+    int dev_step;          // step graphs: add the device step base to `step`
 
     // the blocks are read through the constant address space: they do not
     // change while a kernel runs, so their fields come in by scalar loads
@@ -323,6 +324,7 @@ __global__ void k_fill_i32(int32_t *p, size_t n, int32_t v);
 __global__ void k_zero_counters(Counters *c);
 __global__ void k_clear_status(Counters *c);
 __global__ void k_tile_stats(const unsigned long long *tstat, int ntiles, Counters *c);
+__global__ void k_set_step_base(Counters *c, uint32_t step);
 __global__ void k_replica_stats(const unsigned long long *tstat, const RepConst *rep, unsigned long long *out);
 __global__ void k_far_reset(Counters *c, int slot);
 

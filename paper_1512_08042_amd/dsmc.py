@@ -142,6 +142,21 @@ class Channel:
         cur = self.views().current
         return tuple(self.state[cur, k, :n] for k in range(5))
 
+    def set_tiling(self, particles_per_tile: int = 0, stream=None):
+        """Tiles of about particles_per_tile particles (0: the default); the
+        particles do not depend on it, the moment sums only to rounding."""
+        check(lib().dsmc_set_tiling(self._h, int(particles_per_tile), _stream(stream)), "dsmc_set_tiling")
+
+    def graph_create(self, nsteps: int, sample_every: int = 0, stream=None):
+        """Capture one step(nsteps, sample_every) call into a HIP graph on
+        `stream` (a torch.cuda.Stream; capture cannot use the null stream)."""
+        check(lib().dsmc_graph_create(self._h, int(nsteps), int(sample_every), _stream(stream)),
+              "dsmc_graph_create")
+
+    def graph_launch(self, stream=None):
+        """Replay the captured steps from the current step."""
+        check(lib().dsmc_graph_launch(self._h, _stream(stream)), "dsmc_graph_launch")
+
     def profile(self, enable: bool = True):
         check(lib().dsmc_profile_enable(self._h, int(enable)), "dsmc_profile_enable")
 
@@ -240,9 +255,6 @@ class Batch(Channel):
         check(lib().dsmc_replica_counters(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                           _stream(stream)), "dsmc_replica_counters")
         return out
-
-    def set_tiling(self, particles_per_tile: int = 0, stream=None):
-        check(lib().dsmc_set_tiling(self._h, int(particles_per_tile), _stream(stream)), "dsmc_set_tiling")
 
     def autotune(self, steps_per_trial: int = 2, sample_every: int = 0, stream=None) -> dict:
         t = _lib.Tuning()

@@ -158,3 +158,39 @@ def test_256_uneven_replicas_sampled_against_the_oracle():
         ref.step(2, sample_every=1)
         _check_replica(b, i, ref, what="256-replica batch, replica %d" % i)
     b.close()
+
+
+def test_step_graph_replays_match_eager_steps():
+    # one dsmc_step(4 steps, sampling every step) captured into a HIP graph and
+    # replayed three times, with eager work and synchronisation between the
+    # replays; after every replay the state equals that of the same steps run
+    # eagerly on a second context
+    D, _ = _gpu()
+    from paper_1512_08042_amd._lib import ESTATE, DsmcError
+
+    s = torch.cuda.Stream()
+    eager = D.Batch(REPS)
+    graphed = D.Batch(REPS)
+    torch.cuda.synchronize()
+    graphed.graph_create(4, sample_every=1, stream=s)
+    for rep in range(3):
+        eager.step(4, sample_every=1)
+        graphed.graph_launch(stream=s)
+        s.synchronize()
+        _ = eager.status()  # eager work between replays
+        got = [t.cpu().numpy() for t in graphed.particles()]
+        want = [t.cpu().numpy() for t in eager.particles()]
+        for g, w in zip(got, want):
+            assert np.array_equal(g, w), "replay %d" % rep
+        assert np.array_equal(graphed.cell_start().cpu().numpy(), eager.cell_start().cpu().numpy())
+        assert np.array_equal(graphed.sample_moments().cpu().numpy(), eager.sample_moments().cpu().numpy())
+        assert np.array_equal(graphed.replica_counters(), eager.replica_counters())
+        assert graphed.views().step == eager.views().step == 4 * (rep + 1)
+    # an odd number of eager steps breaks the captured parity: refused
+    graphed.step(1, sample_every=1)
+    with pytest.raises(DsmcError) as e:
+        graphed.graph_launch(stream=s)
+    assert e.value.code == ESTATE
+    torch.cuda.synchronize()
+    eager.close()
+    graphed.close()
