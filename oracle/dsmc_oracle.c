@@ -742,22 +742,36 @@ int or_lb2dsmc(or_sim *s, int32_t Q, int32_t order, const double *xi, const doub
  * velocity shift), Hermite equilibrium to second order (Q = 9) or third
  * order (otherwise), BGK relaxation, second-order Hermite force term
  * (1 - 1/(2 tau)) w rho [xi.g + (xi.g)(xi.u) - g.u], then push along e_a.
- * x is periodic. y_mode 0: y periodic. y_mode 1: the K = max|e_y| rows at
+ * x is periodic.  y_mode 0: y periodic.  y_mode 1: the K = max|e_y| rows at
  * each edge hold caller-set populations: they are neither collided nor
- * overwritten, and stream into the interior unchanged.  Result in f. */
+ * overwritten, and stream into the interior unchanged.  y_mode 2 (lattices
+ * with |e_y| <= 1): diffuse walls half a node below row 0 and above row
+ * ny-1; a population that would stream through a wall is taken up by it,
+ * and the wall gives back to the same node the populations that point away
+ * from it as the rest equilibrium w_a rho_w, with rho_w such that the node
+ * gets back the mass it sent into the wall (full accommodation, wall at
+ * rest).  x_buffer: the columns 0 .. x_buffer-1 hold caller-set populations
+ * like buffer rows (not collided, not overwritten, streamed on into their
+ * neighbours, across the periodic seam too); what streams into them is
+ * dropped.  Result in f. */
 void or_lbm_step(int32_t nx, int32_t ny, int32_t Q, const int32_t *ex, const int32_t *ey, const double *w,
-                 const double *xi, double tau, double gx, int32_t y_mode, double *f, double *ftmp, int32_t nsteps)
+                 const double *xi, double tau, double gx, int32_t y_mode, int32_t x_buffer, double *f, double *ftmp,
+                 int32_t nsteps)
 {
     int64_t nn = (int64_t)nx * ny;
     int32_t K = 0;
     for (int32_t a = 0; a < Q; ++a) if (abs(ey[a]) > K) K = abs(ey[a]);
     double *fe = (double *)xalloc((size_t)Q * 8);
+    /* mass each node sends into the lower and the upper wall (y_mode 2) */
+    double *wall_lo = (double *)xalloc((size_t)nn * 8);
+    double *wall_hi = (double *)xalloc((size_t)nn * 8);
     for (int32_t st = 0; st < nsteps; ++st) {
+        for (int64_t node = 0; node < nn; ++node) wall_lo[node] = wall_hi[node] = 0.0;
         for (int32_t iy = 0; iy < ny; ++iy) {
             for (int32_t ix = 0; ix < nx; ++ix) {
                 int64_t node = (int64_t)iy * nx + ix;
-                int buffer = (y_mode == 1) && (iy < K || iy >= ny - K);
-                if (buffer) {
+                int held = ((y_mode == 1) && (iy < K || iy >= ny - K)) || ix < x_buffer;
+                if (held) {
                     for (int32_t a = 0; a < Q; ++a) ftmp[(size_t)a * nn + node] = f[(size_t)a * nn + node];
                 }
             }
@@ -765,8 +779,8 @@ void or_lbm_step(int32_t nx, int32_t ny, int32_t Q, const int32_t *ex, const int
         for (int32_t iy = 0; iy < ny; ++iy) {
             for (int32_t ix = 0; ix < nx; ++ix) {
                 int64_t node = (int64_t)iy * nx + ix;
-                int buffer = (y_mode == 1) && (iy < K || iy >= ny - K);
-                if (buffer) {
+                int held = ((y_mode == 1) && (iy < K || iy >= ny - K)) || ix < x_buffer;
+                if (held) {
                     for (int32_t a = 0; a < Q; ++a) fe[a] = f[(size_t)a * nn + node];
                 } else {
                     double rho = 0.0, jx = 0.0, jy = 0.0;
@@ -796,14 +810,62 @@ void or_lbm_step(int32_t nx, int32_t ny, int32_t Q, const int32_t *ex, const int
                     jx2 = ((jx2 % nx) + nx) % nx;
                     if (y_mode == 1) {
                         if (jy2 < K || jy2 >= ny - K) continue;
+                    } else if (y_mode == 2) {
+                        if (jy2 < 0) { wall_lo[node] += fe[a]; continue; }
+                        if (jy2 >= ny) { wall_hi[node] += fe[a]; continue; }
                     } else {
                         jy2 = ((jy2 % ny) + ny) % ny;
                     }
+                    if (jx2 < x_buffer) continue;
                     ftmp[(size_t)a * nn + (int64_t)jy2 * nx + jx2] = fe[a];
+                }
+            }
+        }
+        if (y_mode == 2) {
+            double wsum_up = 0.0, wsum_dn = 0.0;  /* weight of the directions pointing away from each wall */
+            for (int32_t a = 0; a < Q; ++a) {
+                if (ey[a] > 0) wsum_up += w[a];
+                if (ey[a] < 0) wsum_dn += w[a];
+            }
+            for (int32_t ix = x_buffer; ix < nx; ++ix) {
+                int64_t lo = ix, hi = (int64_t)(ny - 1) * nx + ix;
+                double rlo = wall_lo[lo] / wsum_up, rhi = wall_hi[hi] / wsum_dn;
+                for (int32_t a = 0; a < Q; ++a) {
+                    if (ey[a] > 0) ftmp[(size_t)a * nn + lo] = w[a] * rlo;
+                    if (ey[a] < 0) ftmp[(size_t)a * nn + hi] = w[a] * rhi;
                 }
             }
         }
         memcpy(f, ftmp, (size_t)Q * nn * 8);
     }
     free(fe);
+    free(wall_lo);
+    free(wall_hi);
+}
+
+/* The equilibrium mapping of Section 4, Eq. (feq_dsmc): from each cell's
+ * averages only rho = <N>/ppc and u = <sum v>/<N> (in units of sqrt(kT/m))
+ * enter, f_a = w_a rho [1 + xi.u + ((xi.u)^2 - u.u)/2], plus
+ * xi.u ((xi.u)^2 - 3 u.u)/6 when order is 3 (a lattice that carries it).
+ * Empty cells give zero populations.  avg: [11][ncells]; f: [Q][ncells]. */
+void or_dsmc2lb_eq(const double *avg, int32_t ncells, int32_t ppc, double kT, int32_t Q, int32_t order,
+                   const double *w, const double *xi, double *f)
+{
+    double s1 = sqrt(kT);
+    for (int32_t c = 0; c < ncells; ++c) {
+        double m0 = avg[c];
+        if (!(m0 > 0.0)) {
+            for (int32_t a = 0; a < Q; ++a) f[(size_t)a * ncells + c] = 0.0;
+            continue;
+        }
+        double rho = m0 / (double)ppc;
+        double ux = (avg[(size_t)ncells + c] / m0) / s1, uy = (avg[2 * (size_t)ncells + c] / m0) / s1;
+        double uu = ux * ux + uy * uy;
+        for (int32_t a = 0; a < Q; ++a) {
+            double cu = xi[2 * a] * ux + xi[2 * a + 1] * uy;
+            double eq = 1.0 + cu + 0.5 * (cu * cu - uu);
+            if (order >= 3) eq += cu * (cu * cu - 3.0 * uu) / 6.0;
+            f[(size_t)a * ncells + c] = w[a] * rho * eq;
+        }
+    }
 }

@@ -90,7 +90,8 @@ def lib():
         L.or_ar_sample_batch.restype = i64
         L.or_lb2dsmc.argtypes = [P, i32, i32, P, P, P, i32]
         L.or_lb2dsmc.restype = ctypes.c_int
-        L.or_lbm_step.argtypes = [i32, i32, i32, P, P, P, P, d, d, i32, P, P, i32]
+        L.or_lbm_step.argtypes = [i32, i32, i32, P, P, P, P, d, d, i32, i32, P, P, i32]
+        L.or_dsmc2lb_eq.argtypes = [P, i32, i32, d, i32, i32, P, P, P]
         _lib = L
     return _lib
 
@@ -408,7 +409,7 @@ def ar_sample(prm, n, seed=1, cell=0, event=0, max_tries=65536):
     return xi, int(tries), int(st[0])
 
 
-def lbm_step(f, lat, nx, ny, tau, gx, y_mode, nsteps):
+def lbm_step(f, lat, nx, ny, tau, gx, y_mode, nsteps, x_buffer=0):
     f = np.array(f, dtype=np.float64, copy=True, order="C")
     assert f.shape == (lat["Q"], nx * ny)
     tmp = np.zeros_like(f)
@@ -416,5 +417,16 @@ def lbm_step(f, lat, nx, ny, tau, gx, y_mode, nsteps):
     ex = np.ascontiguousarray(e[:, 0], dtype=np.int32)
     ey = np.ascontiguousarray(e[:, 1], dtype=np.int32)
     lib().or_lbm_step(int(nx), int(ny), lat["Q"], _ptr(ex), _ptr(ey), _ptr(lat["w"]), _ptr(lat["xi"]), float(tau),
-                      float(gx), int(y_mode), _ptr(f), _ptr(tmp), int(nsteps))
+                      float(gx), int(y_mode), int(x_buffer), _ptr(f), _ptr(tmp), int(nsteps))
+    return f
+
+
+def dsmc2lb_eq(avg, ppc, lat, order=2, kT=1.0):
+    """The equilibrium mapping of Eq. (feq_dsmc) (order 2; order 3 adds the
+    third-order equilibrium term)."""
+    avg = np.ascontiguousarray(avg, dtype=np.float64)
+    ncells = avg.shape[1]
+    f = np.zeros((lat["Q"], ncells))
+    lib().or_dsmc2lb_eq(_ptr(avg), ncells, int(ppc), float(kT), lat["Q"], int(order), _ptr(lat["w"]),
+                        _ptr(lat["xi"]), _ptr(f))
     return f
