@@ -37,6 +37,13 @@ Printed JSON line: metric, value, ..., plus
             autotuner, steps replayed from a HIP graph) against the plain
             form, one channel context per replica run one after another;
             every replica's moments are compared bit for bit between the two;
+  hybrid:   the coupling of Section 4 on a 1024 x 128 channel (Kn 0.05, Ma
+            0.1): the DSMC subdomain (512 x 128 cells, 100 particles per
+            cell) feeds the buffer-layer column of a D2Q9 lattice subdomain
+            with diffuse walls (1 + 512 columns) every 10 lattice steps (40
+            DSMC steps), by the equilibrium mapping of Eq. (feq_dsmc) and by
+            the full projection: cycles per second, and the velocity profiles
+            at x = L0/4 (DSMC), the buffer layer and x = 3 L0/4 (lattice);
   precision: the FP32-state form against plain FP64 on a 2048 x 1024 x 50
             channel (Kn 0.02, Ma 0.1): particle-steps/s of each, and per
             moment order the RMS and mean over cells of z = (m32 - m64) / SE,
@@ -80,11 +87,11 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_512x256x100_fp64_traffi
 TRACE_SUMMARY = os.path.join(ROOT, "profiles", "dsmc_cycle_512x256x100_fp64_kernel_trace.md")
 # the commands whose output the summaries condense (run from the repository root)
 TRACE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace -o trace -- "
-             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-precision --no-adjoint --no-batched")
+             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-precision --no-adjoint --no-batched --no-hybrid")
 PMC_CMDS = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --copy-calibration",
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --no-hybrid --copy-calibration",
             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --copy-calibration")
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --no-hybrid --copy-calibration")
 # kernel-name prefixes of the library's kernels, by profiling id
 KERNEL_PREFIX = {"step": "void dsmc::k_step<", "classify": "void dsmc::k_classify<"}
 ADJ_TRACE_SUMMARY = os.path.join(ROOT, "profiles", "lbm_adjoint_1024x512_d2q37_kernel_trace.md")
@@ -404,6 +411,86 @@ def batched_comparison():
     }
 
 
+# the hybrid workload (Section 4)
+HYB = dict(L0=1024, H=128, ppc=100, kn=0.05, mach=0.1, seed=6, lbm_steps=10, dsmc_per_lbm=4, warm=5, timed=50,
+           observe=100)
+
+
+def hybrid_benchmark():
+    """Coupling cycles of the hybrid workload with both mappings: rates and
+    the velocity profiles of the two subdomains."""
+    import numpy as np
+    import torch
+
+    from paper_1512_08042_amd import ChannelConfig, body_force, hard_sphere_viscosity
+    from paper_1512_08042_amd import dsmc as D
+
+    Hh = HYB
+    H, nx_d = Hh["H"], Hh["L0"] // 2
+    nx_l = Hh["L0"] // 2 + 1  # the buffer column, then the lattice subdomain
+    e, w, r = D.lattice(9)
+    dt = 1.0 / (Hh["dsmc_per_lbm"] * r)  # lattice step = 1/r in units of dx / sqrt(kT/m)
+    g = body_force(Hh["kn"], H, Hh["mach"])
+    nu = hard_sphere_viscosity(Hh["kn"], H)
+    tau = 0.5 + r * nu  # lattice viscosity (tau - 1/2)/r matched to the gas
+    ds = Hh["lbm_steps"] * Hh["dsmc_per_lbm"]
+    xi_x = torch.tensor(r * e[:, 0], dtype=torch.float64, device="cuda")[:, None]
+    out = {"workload": "channel 1024x128, Kn 0.05, Ma 0.1: DSMC subdomain 512x128 cells x 100 particles/cell, D2Q9 "
+                       "subdomain (buffer column + 512 columns) x 128 rows with diffuse walls, tau %.3f (viscosity "
+                       "matched), %d DSMC steps (dt = lattice step / %d) and %d lattice steps per cycle; %d warm-up, "
+                       "%d timed and %d observed cycles from rest" % (tau, ds, Hh["dsmc_per_lbm"], Hh["lbm_steps"],
+                                                                      Hh["warm"], Hh["timed"], Hh["observe"])}
+    for mapping, name in ((0, "equilibrium"), (1, "full")):
+        ch = D.Channel(ChannelConfig(nx=nx_d, ny=H, ppc=Hh["ppc"], kn=Hh["kn"], dt=dt, body_force_x=g,
+                                     seed=Hh["seed"]))
+        f = torch.tensor(w, dtype=torch.float64, device="cuda")[:, None].repeat(1, nx_l * H).contiguous()
+        tmp = torch.empty_like(f)
+        avg = torch.empty((11, nx_d * H), dtype=torch.float64, device="cuda")
+
+        def cycle(a=None):
+            ch.hybrid_cycle(f, tmp, nx_l, tau, g / r, dsmc_steps=ds, lbm_steps=Hh["lbm_steps"], mapping=mapping,
+                            order=2, avg_out=a)
+
+        for _ in range(Hh["warm"]):
+            cycle()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(Hh["timed"]):
+            cycle()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        n = ch.status()["n"]
+        sums = torch.zeros((4, H), dtype=torch.float64, device="cuda")
+        for _ in range(Hh["observe"]):
+            cycle(avg)
+            m = avg.view(11, H, nx_d)
+            sums[0] += m[1, :, nx_d // 4] / m[0, :, nx_d // 4]  # x = L0/4
+            sums[1] += m[1, :, nx_d - 1] / m[0, :, nx_d - 1]  # the buffer layer
+            fl = f.view(9, H, nx_l)[:, :, nx_l // 2]  # x = 3 L0/4
+            rho = fl.sum(0)
+            sums[2] += ((fl * xi_x).sum(0) + 0.5 * rho * g / r) / rho
+            sums[3] += m[1].sum(1) / m[0].sum(1)  # every DSMC column (the subdomain is periodic along x)
+        prof = (sums / Hh["observe"]).cpu().numpy()
+        dsmc, buf, lb, dsmc_all = prof
+        out[name] = {
+            "ms_per_cycle": round(1e3 * t / Hh["timed"], 3),
+            "dsmc_particle_steps_per_s": float("%.4g" % (n * ds * Hh["timed"] / t)),
+            "lattice_node_steps_per_s": float("%.4g" % (nx_l * H * Hh["lbm_steps"] * Hh["timed"] / t)),
+            "centreline_ux": {"dsmc_L0/4": round(float(dsmc[H // 2 - 1: H // 2 + 1].mean()), 5),
+                              "buffer_L0/2": round(float(buf[H // 2 - 1: H // 2 + 1].mean()), 5),
+                              "lattice_3L0/4": round(float(lb[H // 2 - 1: H // 2 + 1].mean()), 5),
+                              "dsmc_all_columns": round(float(dsmc_all[H // 2 - 1: H // 2 + 1].mean()), 5)},
+            "profile_rms_lattice_vs_dsmc_L0/4": round(float(np.sqrt(np.mean((lb - dsmc) ** 2)) / abs(dsmc).max()), 4),
+            "profile_rms_lattice_vs_dsmc_all_columns": round(
+                float(np.sqrt(np.mean((lb - dsmc_all) ** 2)) / abs(dsmc_all).max()), 4),
+            "status_bits": ch.status()["bits"],
+        }
+        ch.close()
+        del ch, f, tmp, avg
+        torch.cuda.empty_cache()
+    return out
+
+
 def source_hash() -> str:
     """sha256 over the library's kernel sources and its C header."""
     h = hashlib.sha256()
@@ -537,6 +624,9 @@ def _parse():
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32-vs-FP64 comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-replica workload")
+    ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid-coupling workload")
+    ap.add_argument("--hybrid-only", action="store_true",
+                    help="run only the hybrid-coupling workload and print its JSON object")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched-replica workload and print its JSON object")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -612,6 +702,9 @@ def main():
         return
     if args.batched_only:
         print(json.dumps({"batched": batched_comparison()}), flush=True)
+        return
+    if args.hybrid_only:
+        print(json.dumps({"hybrid": hybrid_benchmark()}), flush=True)
         return
     cfg = ChannelConfig(nx=NX, ny=NY, ppc=PPC, kn=KN, mach=MACH, seed=SEED).resolved()
     ch = D.Channel(cfg)
@@ -703,6 +796,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = batched_comparison()
+        torch.cuda.empty_cache()
+    if not args.no_hybrid:
+        out["hybrid"] = hybrid_benchmark()
         torch.cuda.empty_cache()
     if not args.no_precision:
         out["precision"] = precision_comparison()

@@ -194,9 +194,16 @@ int map_lbm_to_dsmc(dsmc_ctx *ctx, int32_t lattice, int32_t order, const double 
 typedef struct lbm_config {
     int32_t nx, ny;       /* nodes; x periodic */
     int32_t lattice;      /* 9 or 37 */
-    int32_t y_mode;       /* 0: y periodic; 1: the max|e_y| rows at each y edge hold caller-set populations */
+    int32_t y_mode;       /* 0: y periodic; 1: the max|e_y| rows at each y edge hold caller-set populations;
+                             2 (D2Q9): diffuse walls half a node below row 0 and above row ny-1 (Section 4's
+                             kinetic walls: what streams through a wall is taken up and given back to the same
+                             node as the rest equilibrium w_a rho_w of the mass it took) */
     double tau;           /* BGK relaxation time in lattice steps (> 1/2), e.g. from Eq. (tau) */
     double body_force_x;  /* velocity gain along x per lattice step, in units of sqrt(kT/m) */
+    int32_t x_buffer;     /* held inflow columns 0 .. x_buffer-1 (Section 4's buffer layer): like buffer rows
+                             they keep caller-set populations, stream them on into their neighbours (across the
+                             periodic seam too) and drop what streams into them; 0 <= x_buffer <= nx */
+    int32_t reserved;     /* 0 */
 } lbm_config;
 
 /* nsteps BGK steps (Section 3.1) on populations f (device, [Q][nx*ny],
@@ -265,6 +272,38 @@ int lbm_hermite_moments_adjoint(int32_t lattice, int32_t order, const double *a_
  * avg_bar: device [11][ncells], overwritten.  Errors: DSMC_EINVAL. */
 int dsmc_project_moments_adjoint(const double *f_bar, const double *avg, int64_t ncells, int32_t ppc,
                                  double kT_over_m, int32_t lattice, int32_t order, double *avg_bar, void *stream);
+
+/* The equilibrium mapping of Section 4, Eq. (feq_dsmc), from caller-given
+ * averages (device, [11][ncells]): only rho = <N>/ppc and u = <sum v>/<N>
+ * enter, f_a = w_a rho [1 + xi.u + ((xi.u)^2 - u.u)/2], plus the third-order
+ * equilibrium term xi.u ((xi.u)^2 - 3 u.u)/6 when order is 3 (D2Q37 only).
+ * Empty cells give zero populations.  f_out: device [Q][ncells].
+ * Errors: DSMC_EINVAL. */
+int dsmc_project_equilibrium(const double *avg, int64_t ncells, int32_t ppc, double kT_over_m, int32_t lattice,
+                             int32_t order, double *f_out, void *stream);
+
+/* One cycle of the hybrid coupling of Section 4: the context's channel is
+ * the DSMC subdomain, f_lb (device, [Q][lbm.nx * lbm.ny], lbm.ny equal to
+ * the channel's ny) the lattice subdomain, whose inflow columns
+ * 0 .. lbm.x_buffer-1 form the buffer layer.  The cycle runs dsmc_steps DSMC
+ * steps sampled every step; projects the averages over those steps of DSMC
+ * column dsmc_column onto every buffer column (mapping 0: the equilibrium of
+ * Eq. (feq_dsmc); 1: the full projection of Eq. (discretefunctions), with
+ * the sampled non-equilibrium moments up to `order`); writes the cycle's
+ * averages of every DSMC cell to avg_out (device [11][ncells], may be NULL);
+ * resets the sums; and runs lbm_steps lattice steps (f_tmp: scratch of
+ * f_lb's size).  Errors: DSMC_EINVAL, DSMC_ESTATE (batch contexts). */
+typedef struct dsmc_hybrid {
+    lbm_config lbm;
+    int32_t dsmc_steps;
+    int32_t lbm_steps;
+    int32_t mapping;
+    int32_t order;
+    int32_t dsmc_column;
+    int32_t reserved;
+} dsmc_hybrid;
+int dsmc_hybrid_cycle(dsmc_ctx *ctx, const dsmc_hybrid *h, double *f_lb, double *f_tmp, double *avg_out,
+                      void *stream);
 
 /* Host copy of a lattice table: e_out int[Q][2], w_out double[Q], r_out. */
 int dsmc_lattice(int32_t lattice, int32_t *e_out, double *w_out, double *r_out);

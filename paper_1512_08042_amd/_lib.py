@@ -24,7 +24,7 @@ EXPORTS = ("dsmc_query_sizes", "dsmc_init", "dsmc_step", "dsmc_sample_moments", 
            "lbm_step_checkpointed", "lbm_adjoint_workspace", "lbm_adjoint_step", "lbm_adjoint",
            "lbm_hermite_moments", "lbm_hermite_moments_adjoint", "dsmc_project_moments_adjoint",
            "dsmc_batch_query_sizes", "dsmc_batch_init", "dsmc_set_tiling", "dsmc_autotune", "dsmc_replica_counters",
-           "dsmc_graph_create", "dsmc_graph_launch")
+           "dsmc_graph_create", "dsmc_graph_launch", "dsmc_project_equilibrium", "dsmc_hybrid_cycle")
 
 
 class Config(ctypes.Structure):
@@ -63,7 +63,12 @@ class Status(ctypes.Structure):
 
 class LbmConfig(ctypes.Structure):
     _fields_ = [("nx", c_i32), ("ny", c_i32), ("lattice", c_i32), ("y_mode", c_i32), ("tau", c_d),
-                ("body_force_x", c_d)]
+                ("body_force_x", c_d), ("x_buffer", c_i32), ("reserved", c_i32)]
+
+
+class Hybrid(ctypes.Structure):
+    _fields_ = [("lbm", LbmConfig), ("dsmc_steps", c_i32), ("lbm_steps", c_i32), ("mapping", c_i32),
+                ("order", c_i32), ("dsmc_column", c_i32), ("reserved", c_i32)]
 
 
 _lib = None
@@ -106,6 +111,8 @@ def lib():
         L.dsmc_replica_counters.argtypes = [c_p, P(c_u64), c_p]
         L.dsmc_graph_create.argtypes = [c_p, c_i32, c_i32, c_p]
         L.dsmc_graph_launch.argtypes = [c_p, c_p]
+        L.dsmc_project_equilibrium.argtypes = [c_p, c_i64, c_i32, c_d, c_i32, c_i32, c_p, c_p]
+        L.dsmc_hybrid_cycle.argtypes = [c_p, P(Hybrid), c_p, c_p, c_p, c_p]
         L.dsmc_get_views.argtypes = [c_p, P(Views)]
         L.dsmc_profile_enable.argtypes = [c_p, c_i32]
         L.dsmc_profile_read.argtypes = [c_p, c_i32, P(c_d), P(c_i64)]

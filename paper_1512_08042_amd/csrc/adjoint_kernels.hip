@@ -84,7 +84,7 @@ __device__ __forceinline__ void lbm_adj_node(const LbmAdjArgs &a, int node, doub
     const bool buffer = YB && (iy < a.K || iy >= ny - a.K);
     const double r = a.L.r;
     Nbr<R> nb;
-    neighbours<R, YB, NARROW>(ix, iy, nx, ny, a.K, nb);
+    neighbours<R, YB ? 1 : 0, NARROW>(ix, iy, nx, ny, a.K, nb);
     // every address is in the grid (rows clamped), so all Q loads issue
     // together; what streams into a buffer row is then dropped
     double lp[Q];

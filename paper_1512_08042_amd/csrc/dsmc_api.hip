@@ -580,7 +580,8 @@ bool lbm_args(const lbm_config *cfg, LbmArgs &a)
     if ((int64_t)cfg->nx * cfg->ny >= ((int64_t)1 << 29)) return false;  // 32-bit byte offsets within a plane
     const Lattice *L = lattice_of(cfg->lattice);
     if (!L || !(cfg->tau > 0.5) || !std::isfinite(cfg->tau) || !std::isfinite(cfg->body_force_x)) return false;
-    if (cfg->y_mode != 0 && cfg->y_mode != 1) return false;
+    if (cfg->y_mode < 0 || cfg->y_mode > 2) return false;
+    if (cfg->x_buffer < 0 || cfg->x_buffer > cfg->nx) return false;
     const LatticeTables &t = tables();
     std::memset(&a, 0, sizeof(a));
     a.L.Q = L->Q;
@@ -591,28 +592,45 @@ bool lbm_args(const lbm_config *cfg, LbmArgs &a)
         a.L.ws[cfg->lattice == 9 ? VelSet<9>::sh[q] : VelSet<37>::sh[q]] = L->w[q];
         if (std::abs(ey) > K) K = std::abs(ey);
     }
+    if (cfg->y_mode == 2 && K != 1) return false;  // walls: lattices with |e_y| <= 1
     a.nx = cfg->nx;
     a.ny = cfg->ny;
     a.y_mode = cfg->y_mode;
     a.K = K;
+    a.xb = cfg->x_buffer;
     a.tau = cfg->tau;
     a.gx = cfg->body_force_x;
     return true;
 }
+
+// the reverse pass covers periodic y and buffer rows without inflow columns
+bool adjoint_supported(const lbm_config *cfg) { return cfg->y_mode != 2 && cfg->x_buffer == 0; }
 
 // launches the lattice step / its adjoint instance that fits the grid
 void launch_lbm(const LbmArgs &a, hipStream_t s)
 {
     const size_t nn = (size_t)a.nx * a.ny;
     const int R = a.L.Q == 9 ? 1 : 3;
-    const bool yb = a.y_mode == 1, narrow = a.nx < R || a.ny < R;
-#define DSMC_LBM(Q, YB, NW) k_lbm<Q, YB, NW><<<grid_threads(nn), 256, 0, s>>>(a)
+    const bool narrow = a.nx < R || a.ny < R;
+#define DSMC_LBM(Q, YM)                                                    \
+    do {                                                                   \
+        if (narrow)                                                        \
+            k_lbm<Q, YM, true><<<grid_threads(nn), 256, 0, s>>>(a);        \
+        else                                                               \
+            k_lbm<Q, YM, false><<<grid_threads(nn), 256, 0, s>>>(a);       \
+    } while (0)
     if (a.L.Q == 9) {
-        if (yb) { if (narrow) DSMC_LBM(9, true, true); else DSMC_LBM(9, true, false); }
-        else { if (narrow) DSMC_LBM(9, false, true); else DSMC_LBM(9, false, false); }
+        if (a.y_mode == 2)
+            DSMC_LBM(9, 2);
+        else if (a.y_mode == 1)
+            DSMC_LBM(9, 1);
+        else
+            DSMC_LBM(9, 0);
     } else {
-        if (yb) { if (narrow) DSMC_LBM(37, true, true); else DSMC_LBM(37, true, false); }
-        else { if (narrow) DSMC_LBM(37, false, true); else DSMC_LBM(37, false, false); }
+        if (a.y_mode == 1)
+            DSMC_LBM(37, 1);
+        else
+            DSMC_LBM(37, 0);
     }
 #undef DSMC_LBM
 }
@@ -1098,11 +1116,15 @@ int dsmc_sample_moments(dsmc_ctx *x, double *out, int32_t reset, void *stream)
     return DSMC_OK;
 }
 
+// DSMC2LB of n cells c_off + i c_stride into nodes n_off + i n_stride of
+// f_out ([Q][nn_out]); all cells into the same layout by default
 static int project(dsmc_ctx *x, const double *mom, double S_, int64_t ncells, int32_t ppc, double kT, int32_t lattice,
-                   int32_t order, double *f_out, hipStream_t s)
+                   int32_t order, double *f_out, hipStream_t s, int equilibrium = 0, int n = -1, int c_off = 0,
+                   int c_stride = 1, int n_off = 0, int n_stride = 1, int64_t nn_out = -1)
 {
     const Lattice *L = lattice_of(lattice);
     if (!L || order < 0 || order > 3 || !f_out || !mom || ncells < 1 || ppc < 1 || !(kT > 0.0)) return DSMC_EINVAL;
+    if (equilibrium && order == 3 && lattice == 9) return DSMC_EINVAL;  // D2Q9 does not carry it
     ProjectArgs a;
     a.mom = mom;
     a.S = S_;
@@ -1112,7 +1134,15 @@ static int project(dsmc_ctx *x, const double *mom, double S_, int64_t ncells, in
     a.ppc = ppc;
     a.order = order;
     a.s1 = std::sqrt(kT);
-    return launch(x, DSMC_K_PROJECT, s, [&] { k_project<<<grid_threads((size_t)ncells), 256, 0, s>>>(a); });
+    a.equilibrium = equilibrium;
+    a.n = n < 0 ? (int)ncells : n;
+    a.c_off = c_off;
+    a.c_stride = c_stride;
+    a.n_off = n_off;
+    a.n_stride = n_stride;
+    a.nn_out = nn_out < 0 ? ncells : nn_out;
+    if (a.n == 0) return DSMC_OK;
+    return launch(x, DSMC_K_PROJECT, s, [&] { k_project<<<grid_threads((size_t)a.n), 256, 0, s>>>(a); });
 }
 
 int map_dsmc_to_lbm(dsmc_ctx *x, int32_t lattice, int32_t order, double *f_out, void *stream)
@@ -1131,6 +1161,40 @@ int dsmc_project_moments(const double *avg, int64_t ncells, int32_t ppc, double 
 {
     if (ncells > (int64_t)0x3FFFFFFF) return DSMC_EINVAL;
     return project(nullptr, avg, 1.0, ncells, ppc, kT_over_m, lattice, order, f_out, S(stream));
+}
+
+int dsmc_project_equilibrium(const double *avg, int64_t ncells, int32_t ppc, double kT_over_m, int32_t lattice,
+                             int32_t order, double *f_out, void *stream)
+{
+    if (ncells > (int64_t)0x3FFFFFFF || order < 0 || order > 3) return DSMC_EINVAL;
+    return project(nullptr, avg, 1.0, ncells, ppc, kT_over_m, lattice, order, f_out, S(stream), 1);
+}
+
+int dsmc_hybrid_cycle(dsmc_ctx *x, const dsmc_hybrid *h, double *f_lb, double *f_tmp, double *avg_out, void *stream)
+{
+    if (!x || !h || !f_lb || !f_tmp) return DSMC_EINVAL;
+    if (x->nrep != 1) return DSMC_ESTATE;  // one channel only
+    LbmArgs la;
+    if (!lbm_args(&h->lbm, la)) return DSMC_EINVAL;
+    if (h->lbm.ny != x->cfg.ny || h->lbm.x_buffer < 1) return DSMC_EINVAL;
+    if (h->dsmc_steps < 1 || h->lbm_steps < 0 || (h->mapping != 0 && h->mapping != 1)) return DSMC_EINVAL;
+    if (h->order < 1 || h->order > 3 || (h->mapping == 0 && h->order == 3 && h->lbm.lattice == 9))
+        return DSMC_EINVAL;
+    if (h->dsmc_column < 0 || h->dsmc_column >= x->cfg.nx) return DSMC_EINVAL;
+    hipStream_t s = S(stream);
+    x->last = s;
+    // the DSMC subdomain, sampled every step over the cycle
+    TRY(dsmc_step(x, h->dsmc_steps, 1, stream));
+    // its buffer-layer column, averaged over the cycle, onto every held
+    // inflow column of the lattice
+    const int ny = x->cfg.ny;
+    for (int32_t col = 0; col < h->lbm.x_buffer; ++col)
+        TRY(project(x, x->mom, (double)x->nsamples, x->ncells, x->cfg.ppc, x->cfg.kT_over_m, h->lbm.lattice, h->order,
+                    f_lb, s, h->mapping == 0 ? 1 : 0, ny, h->dsmc_column, x->cfg.nx, col, h->lbm.nx,
+                    (int64_t)h->lbm.nx * ny));
+    TRY(dsmc_sample_moments(x, avg_out, 1, stream));
+    // the lattice subdomain
+    return lbm_step(&h->lbm, f_lb, f_tmp, h->lbm_steps, stream);
 }
 
 int map_lbm_to_dsmc(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f_in, const int32_t *cell_ids,
@@ -1227,7 +1291,7 @@ int lbm_step_checkpointed(const lbm_config *cfg, double *f, double *f_tmp, doubl
 int lbm_adjoint_workspace(const lbm_config *cfg, int32_t every, size_t *bytes)
 {
     LbmArgs a;
-    if (!lbm_args(cfg, a) || every < 0 || !bytes) return DSMC_EINVAL;
+    if (!lbm_args(cfg, a) || !adjoint_supported(cfg) || every < 0 || !bytes) return DSMC_EINVAL;
     *bytes = adj_layout(cfg, a.L.Q, every).total;
     return DSMC_OK;
 }
@@ -1236,7 +1300,8 @@ int lbm_adjoint_step(const lbm_config *cfg, const double *f_n, const double *lam
                      double *grad, void *work, void *stream)
 {
     LbmArgs a;
-    if (!lbm_args(cfg, a) || !f_n || !lam_next || !lam_out || !grad || !work) return DSMC_EINVAL;
+    if (!lbm_args(cfg, a) || !adjoint_supported(cfg) || !f_n || !lam_next || !lam_out || !grad || !work)
+        return DSMC_EINVAL;
     if (lam_next == lam_out) return DSMC_EINVAL;
     const AdjLayout W = adj_layout(cfg, a.L.Q, 0);
     hipStream_t s = S(stream);
@@ -1251,7 +1316,8 @@ int lbm_adjoint(const lbm_config *cfg, const double *ckpt, int32_t nsteps, int32
                 double *grad, void *work, void *stream)
 {
     LbmArgs a;
-    if (!lbm_args(cfg, a) || !ckpt || !lam || !grad || !work || nsteps < 0 || every < 1) return DSMC_EINVAL;
+    if (!lbm_args(cfg, a) || !adjoint_supported(cfg) || !ckpt || !lam || !grad || !work || nsteps < 0 || every < 1)
+        return DSMC_EINVAL;
     if (nsteps == 0) return DSMC_OK;
     const AdjLayout W = adj_layout(cfg, a.L.Q, every);
     hipStream_t s = S(stream);

@@ -14,20 +14,35 @@ namespace dsmc {
 // left out there.
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
 {
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= a.ncells) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const int c = a.c_off + i * a.c_stride;
+    const size_t node = (size_t)a.n_off + (size_t)i * a.n_stride;
     const int nc = a.ncells;
     double m[NMOM];
 #pragma unroll
     for (int k = 0; k < NMOM; ++k) m[k] = a.mom[(size_t)k * nc + c] / a.S;
     const int Q = a.L.Q;
     if (!(m[0] > 0.0)) {
-        for (int q = 0; q < Q; ++q) a.f[(size_t)q * nc + c] = 0.0;
+        for (int q = 0; q < Q; ++q) a.f[(size_t)q * a.nn_out + node] = 0.0;
         return;
     }
     const double s1 = a.s1;
     const double rho = m[0] / (double)a.ppc;
     const double ex = (m[1] / m[0]) / s1, ey = (m[2] / m[0]) / s1;
+    const int order = a.order;
+    if (a.equilibrium) {
+        // Eq. (feq_dsmc): w rho [1 + xi.u + ((xi.u)^2 - u.u)/2] (+ the
+        // third-order equilibrium term on a lattice that carries it)
+        const double uu = ex * ex + ey * ey;
+        for (int q = 0; q < Q; ++q) {
+            const double cu = a.L.xi[q][0] * ex + a.L.xi[q][1] * ey;
+            double eq = 1.0 + cu + 0.5 * (cu * cu - uu);
+            if (order >= 3) eq += cu * (cu * cu - 3.0 * uu) / 6.0;
+            a.f[(size_t)q * a.nn_out + node] = a.L.w[q] * rho * eq;
+        }
+        return;
+    }
     const double s2 = s1 * s1, s3 = s2 * s1;
     const double exx = (m[3] / m[0]) / s2, exy = (m[4] / m[0]) / s2, eyy = (m[5] / m[0]) / s2;
     const double exxx = (m[6] / m[0]) / s3, exxy = (m[7] / m[0]) / s3;
@@ -36,7 +51,6 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
     const double a2xx = rho * (exx - 1.0), a2xy = rho * exy, a2yy = rho * (eyy - 1.0);
     const double a3xxx = rho * (exxx - 3.0 * ex), a3xxy = rho * (exxy - ey);
     const double a3xyy = rho * (exyy - ex), a3yyy = rho * (eyyy - 3.0 * ey);
-    const int order = a.order;
     for (int q = 0; q < Q; ++q) {
         const double x = a.L.xi[q][0], y = a.L.xi[q][1];
         double v = rho;
@@ -54,7 +68,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
             }
             v += t3 / 6.0;
         }
-        a.f[(size_t)q * nc + c] = a.L.w[q] * v;
+        a.f[(size_t)q * a.nn_out + node] = a.L.w[q] * v;
     }
 }
 
@@ -345,9 +359,10 @@ __device__ __forceinline__ int wrap_index(int v, int n)
 
 // The node's neighbour columns and rows for offsets -R..R: wrapped column
 // index, start of the row (row * nx) and whether the row keeps what streams
-// into it.  YB (y_mode 1): only interior rows keep anything; rows beyond the
-// grid are clamped to it so that an address formed from them stays in bounds.
-// NARROW: the grid is narrower than R in x or y and needs a full modulo.
+// into it.  YM 1 (buffer rows): only interior rows keep anything; YM 2
+// (walls): rows beyond the grid are walls; YM 0: y is periodic.  Rows beyond
+// the grid are clamped to it so that an address formed from them stays in
+// bounds.  NARROW: the grid is narrower than R in x or y (full modulo).
 template <int R>
 struct Nbr {
     int col[2 * R + 1];
@@ -355,7 +370,7 @@ struct Nbr {
     bool in[2 * R + 1];
 };
 
-template <int R, bool YB, bool NARROW>
+template <int R, int YM, bool NARROW>
 __device__ __forceinline__ void neighbours(int ix, int iy, int nx, int ny, int K, Nbr<R> &n)
 {
 #pragma unroll
@@ -369,8 +384,8 @@ __device__ __forceinline__ void neighbours(int ix, int iy, int nx, int ny, int K
         }
         n.col[d + R] = c;
         int y = iy + d;
-        if (YB) {
-            n.in[d + R] = y >= K && y < ny - K;
+        if (YM != 0) {
+            n.in[d + R] = YM == 1 ? (y >= K && y < ny - K) : (y >= 0 && y < ny);
             y = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
         } else {
             n.in[d + R] = true;
@@ -385,7 +400,7 @@ __device__ __forceinline__ void neighbours(int ix, int iy, int nx, int ny, int K
     }
 }
 
-template <int Q, bool YB, bool NARROW>
+template <int Q, int YM, bool NARROW>
 __device__ __forceinline__ void lbm_node(const LbmArgs &a, int node)
 {
 #pragma clang fp contract(fast)
@@ -394,7 +409,8 @@ __device__ __forceinline__ void lbm_node(const LbmArgs &a, int node)
     const int nx = a.nx, ny = a.ny;
     const size_t nn = (size_t)nx * ny;
     const int ix = node % nx, iy = node / nx;
-    const bool buffer = YB && (iy < a.K || iy >= ny - a.K);
+    // held nodes (buffer rows, inflow columns) are neither collided nor overwritten
+    const bool held = (YM == 1 && (iy < a.K || iy >= ny - a.K)) || ix < a.xb;
     const double r = a.L.r;
     double fe[Q];
 #pragma unroll
@@ -403,7 +419,7 @@ __device__ __forceinline__ void lbm_node(const LbmArgs &a, int node)
 #pragma unroll
         for (int q = 0; q < Q; ++q) *plane_ptr(a.keep, nn, q, (uint32_t)node) = fe[q];
     }
-    if (!buffer) {
+    if (!held) {
         // rho and the momentum from the integer velocity components
         double rho = 0.0, ex = 0.0, ey = 0.0;
         static_for<Q>([&](auto qc) {
@@ -439,33 +455,61 @@ __device__ __forceinline__ void lbm_node(const LbmArgs &a, int node)
             fe[q] = k1 * fe[q] + wr[s] * eq + fr[s] * (cg + cg * cu - gux);
         });
     }
-    // buffer rows keep their populations (written back unchanged) and send
-    // them on; nothing streamed into a buffer row is kept
+    // push along e_q; held nodes also keep their own populations.  What
+    // streams into a held node is dropped; with walls (YM 2, |e_y| <= 1) what
+    // streams through a wall is taken up by it and given back to the same
+    // node as the rest equilibrium of the mass it took
     Nbr<R> nb;
-    neighbours<R, YB, NARROW>(ix, iy, nx, ny, a.K, nb);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        if (YB && buffer) *plane_ptr(a.ft, nn, q, (uint32_t)node) = fe[q];
-        if (!YB || nb.in[V::ey[q] + R])
-            *plane_ptr(a.ft, nn, q, (uint32_t)(nb.row[V::ey[q] + R] + nb.col[V::ex[q] + R])) = fe[q];
+    neighbours<R, YM, NARROW>(ix, iy, nx, ny, a.K, nb);
+    double wall_lo = 0.0, wall_hi = 0.0;
+    static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if (held) *plane_ptr(a.ft, nn, q, (uint32_t)node) = fe[q];
+        const int jx2 = nb.col[V::ex[q] + R];
+        const bool in = YM == 0 || nb.in[V::ey[q] + R];
+        if (YM == 2 && !in) {
+            if constexpr (V::ey[q] < 0)
+                wall_lo += fe[q];
+            else
+                wall_hi += fe[q];
+        }
+        if (in && jx2 >= a.xb)
+            *plane_ptr(a.ft, nn, q, (uint32_t)(nb.row[V::ey[q] + R] + jx2)) = fe[q];
+    });
+    if (YM == 2 && !held && (iy == 0 || iy == ny - 1)) {
+        double wup = 0.0, wdn = 0.0;  // weight of the directions pointing up / down
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (V::ey[q] > 0) wup += a.L.ws[V::sh[q]];
+            if constexpr (V::ey[q] < 0) wdn += a.L.ws[V::sh[q]];
+        });
+        const double rlo = wall_lo / wup, rhi = wall_hi / wdn;
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (V::ey[q] > 0)
+                if (iy == 0) *plane_ptr(a.ft, nn, q, (uint32_t)node) = a.L.ws[V::sh[q]] * rlo;
+            if constexpr (V::ey[q] < 0)
+                if (iy == ny - 1) *plane_ptr(a.ft, nn, q, (uint32_t)node) = a.L.ws[V::sh[q]] * rhi;
+        });
     }
 }
 
-template <int Q, bool YB, bool NARROW>
+template <int Q, int YM, bool NARROW>
 __global__ __launch_bounds__(256) void k_lbm(LbmArgs a)
 {
     const int node = blockIdx.x * 256 + threadIdx.x;
     if (node >= a.nx * a.ny) return;
-    lbm_node<Q, YB, NARROW>(a, node);
+    lbm_node<Q, YM, NARROW>(a, node);
 }
 
-#define DSMC_LBM_INSTANCES(Q)                                          \
-    template __global__ void k_lbm<Q, false, false>(LbmArgs);          \
-    template __global__ void k_lbm<Q, false, true>(LbmArgs);           \
-    template __global__ void k_lbm<Q, true, false>(LbmArgs);           \
-    template __global__ void k_lbm<Q, true, true>(LbmArgs);
-DSMC_LBM_INSTANCES(9)
-DSMC_LBM_INSTANCES(37)
+#define DSMC_LBM_INSTANCES(Q, YM)                                 \
+    template __global__ void k_lbm<Q, YM, false>(LbmArgs);        \
+    template __global__ void k_lbm<Q, YM, true>(LbmArgs);
+DSMC_LBM_INSTANCES(9, 0)
+DSMC_LBM_INSTANCES(9, 1)
+DSMC_LBM_INSTANCES(9, 2)
+DSMC_LBM_INSTANCES(37, 0)
+DSMC_LBM_INSTANCES(37, 1)
 #undef DSMC_LBM_INSTANCES
 
 }  // namespace dsmc

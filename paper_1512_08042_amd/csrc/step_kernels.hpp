@@ -166,10 +166,14 @@ struct AdoptArgs {
 struct ProjectArgs {
     const double *mom;  // sums [11][ncells]
     double S;           // number of samples the sums hold (1 for averages)
-    double *f;          // [Q][ncells]
+    double *f;          // [Q][nn_out]
     Lattice L;
     int ncells, ppc, order;
     double s1;          // sqrt(kT/m)
+    int equilibrium;    // 1: only rho and u enter (Eq. (feq_dsmc)); 0: the full projection
+    // cells c_off + i c_stride (i < n) project to nodes n_off + i n_stride of f
+    int n, c_off, c_stride, n_off, n_stride;
+    int64_t nn_out;
 };
 
 struct ReseedArgs {
@@ -265,6 +269,7 @@ struct LbmArgs {
     double *keep;  // when not null, also receives f (a checkpoint of the step's input)
     LatShells L;
     int nx, ny, y_mode, K;
+    int xb;        // held inflow columns 0 .. xb-1
     double tau, gx;
 };
 
@@ -337,9 +342,10 @@ __global__ void k_reseed_copy(ReseedArgs a);
 template <class S>
 __global__ void k_reseed_gen(ReseedArgs a);
 __global__ void k_reseed_unmark(ReseedArgs a);
-// lattice step and its adjoint for Q velocities; YB: y_mode 1 (buffer rows);
+// lattice step (YM: y_mode 0 periodic, 1 buffer rows, 2 diffuse walls) and
+// its adjoint (YB: y_mode 1) for Q velocities;
 // NARROW: the grid is narrower than the largest velocity component
-template <int Q, bool YB, bool NARROW>
+template <int Q, int YM, bool NARROW>
 __global__ void k_lbm(LbmArgs a);
 template <int Q, bool YB, bool NARROW>
 __global__ void k_lbm_adjoint(LbmAdjArgs a);

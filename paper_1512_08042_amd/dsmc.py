@@ -147,6 +147,27 @@ class Channel:
         particles do not depend on it, the moment sums only to rounding."""
         check(lib().dsmc_set_tiling(self._h, int(particles_per_tile), _stream(stream)), "dsmc_set_tiling")
 
+    def hybrid_cycle(self, f_lb: torch.Tensor, f_tmp: torch.Tensor, lbm_nx: int, tau: float, body_force_x: float,
+                     dsmc_steps: int, lbm_steps: int, mapping: int = 0, order: int = 2, dsmc_column: int | None = None,
+                     lattice_q: int = 9, x_buffer: int = 1, avg_out: torch.Tensor | None = None, stream=None):
+        """One cycle of the Section 4 coupling: this channel is the DSMC
+        subdomain; f_lb[Q][lbm_nx * ny] the lattice subdomain with diffuse
+        walls, its first x_buffer columns the buffer layer fed from DSMC column
+        dsmc_column (default: the last) by the equilibrium mapping (mapping 0)
+        or the full projection (mapping 1).  avg_out ([11][ncells], optional)
+        receives the cycle's DSMC averages."""
+        ny = self.cfg.ny
+        assert f_lb.dtype == torch.float64 and f_lb.is_contiguous() and f_lb.shape == (lattice_q, lbm_nx * ny)
+        col = self.cfg.nx - 1 if dsmc_column is None else int(dsmc_column)
+        h = _lib.Hybrid(_lib.LbmConfig(int(lbm_nx), int(ny), int(lattice_q), 2 if lattice_q == 9 else 1, float(tau),
+                                       float(body_force_x), int(x_buffer), 0),
+                        int(dsmc_steps), int(lbm_steps), int(mapping), int(order), col, 0)
+        if avg_out is not None:
+            assert avg_out.dtype == torch.float64 and avg_out.is_contiguous() and avg_out.shape == (NMOM, self.ncells)
+        check(lib().dsmc_hybrid_cycle(self._h, ctypes.byref(h), _ptr(f_lb), _ptr(f_tmp),
+                                      _ptr(avg_out) if avg_out is not None else None, _stream(stream)),
+              "dsmc_hybrid_cycle")
+
     def graph_create(self, nsteps: int, sample_every: int = 0, stream=None):
         """Capture one step(nsteps, sample_every) call into a HIP graph on
         `stream` (a torch.cuda.Stream; capture cannot use the null stream)."""
@@ -265,6 +286,17 @@ class Batch(Channel):
                 "chosen": t.particles_per_tile[t.chosen]}
 
 
+def project_equilibrium(avg: torch.Tensor, ppc: int, lattice_q: int, order: int = 2, kT_over_m: float = 1.0,
+                        stream=None) -> torch.Tensor:
+    """The equilibrium mapping of Eq. (feq_dsmc) of averages avg[11][ncells] (device FP64)."""
+    assert avg.dtype == torch.float64 and avg.is_contiguous() and avg.shape[0] == NMOM
+    ncells = avg.shape[1]
+    out = torch.empty((lattice_q, ncells), dtype=torch.float64, device=avg.device)
+    check(lib().dsmc_project_equilibrium(_ptr(avg), ncells, int(ppc), float(kT_over_m), int(lattice_q), int(order),
+                                         _ptr(out), _stream(stream)), "dsmc_project_equilibrium")
+    return out
+
+
 def project_moments(avg: torch.Tensor, ppc: int, lattice_q: int, order: int, kT_over_m: float = 1.0,
                     stream=None) -> torch.Tensor:
     """DSMC2LB projection of given per-cell averages avg[11][ncells] (device FP64)."""
@@ -277,11 +309,15 @@ def project_moments(avg: torch.Tensor, ppc: int, lattice_q: int, order: int, kT_
 
 
 def lbm_step(f: torch.Tensor, nx: int, ny: int, lattice_q: int, tau: float, body_force_x: float = 0.0,
-             y_mode: int = 0, nsteps: int = 1, f_tmp: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """nsteps BGK steps on f[Q][nx*ny] in place (returns f)."""
+             y_mode: int = 0, nsteps: int = 1, f_tmp: torch.Tensor | None = None, stream=None,
+             x_buffer: int = 0) -> torch.Tensor:
+    """nsteps BGK steps on f[Q][nx*ny] in place (returns f).  y_mode 0
+    periodic, 1 held edge rows, 2 diffuse walls (D2Q9); x_buffer held inflow
+    columns."""
     assert f.dtype == torch.float64 and f.is_contiguous() and f.shape == (lattice_q, nx * ny)
     if f_tmp is None:
         f_tmp = torch.empty_like(f)
-    cfg = _lib.LbmConfig(int(nx), int(ny), int(lattice_q), int(y_mode), float(tau), float(body_force_x))
+    cfg = _lib.LbmConfig(int(nx), int(ny), int(lattice_q), int(y_mode), float(tau), float(body_force_x),
+                         int(x_buffer), 0)
     check(lib().lbm_step(ctypes.byref(cfg), _ptr(f), _ptr(f_tmp), int(nsteps), _stream(stream)), "lbm_step")
     return f

@@ -28,7 +28,7 @@ def _stream() -> int:
 
 
 def _cfg(nx, ny, q, y_mode, tau, g):
-    return _lib.LbmConfig(int(nx), int(ny), int(q), int(y_mode), float(tau), float(g))
+    return _lib.LbmConfig(int(nx), int(ny), int(q), int(y_mode), float(tau), float(g), 0, 0)
 
 
 def _f64(t: torch.Tensor, shape=None) -> torch.Tensor:

@@ -136,3 +136,25 @@ def test_batch_sizes_validate_without_gpu():
     assert L.dsmc_set_tiling(None, 100, None) == _lib.EINVAL
     assert L.dsmc_autotune(None, 2, 1, None, None) == _lib.EINVAL
     assert L.dsmc_replica_counters(None, None, None) == _lib.EINVAL
+
+
+def test_wall_and_inflow_modes_validate_without_gpu():
+    L = _lib.lib()
+    size = ctypes.c_size_t()
+    walls = _lib.LbmConfig(10, 8, 9, 2, 0.8, 1e-3, 1, 0)
+    p = ctypes.c_void_p(256)  # never dereferenced
+    assert L.lbm_step(ctypes.byref(walls), p, p, 0, None) == 0  # zero steps: valid, nothing to do
+    bad = _lib.LbmConfig(10, 8, 37, 2, 0.8, 1e-3, 0, 0)  # walls need |e_y| <= 1
+    assert L.lbm_step(ctypes.byref(bad), p, p, 0, None) == _lib.EINVAL
+    bad = _lib.LbmConfig(10, 8, 9, 3, 0.8, 1e-3, 0, 0)
+    assert L.lbm_step(ctypes.byref(bad), p, p, 0, None) == _lib.EINVAL
+    bad = _lib.LbmConfig(10, 8, 9, 0, 0.8, 1e-3, 11, 0)  # more inflow columns than columns
+    assert L.lbm_step(ctypes.byref(bad), p, p, 0, None) == _lib.EINVAL
+    # the reverse pass covers neither walls nor inflow columns
+    assert L.lbm_adjoint_workspace(ctypes.byref(walls), 20, ctypes.byref(size)) == _lib.EINVAL
+    inflow = _lib.LbmConfig(10, 8, 9, 0, 0.8, 1e-3, 1, 0)
+    assert L.lbm_adjoint_workspace(ctypes.byref(inflow), 20, ctypes.byref(size)) == _lib.EINVAL
+    assert L.dsmc_project_equilibrium(p, 10, 100, 1.0, 9, 3, p, None) == _lib.EINVAL  # D2Q9 has no 3rd order
+    assert L.dsmc_project_equilibrium(p, 0, 100, 1.0, 9, 2, p, None) == _lib.EINVAL
+    h = _lib.Hybrid(walls, 4, 2, 0, 2, 0, 0)
+    assert L.dsmc_hybrid_cycle(None, ctypes.byref(h), p, p, None, None) == _lib.EINVAL
