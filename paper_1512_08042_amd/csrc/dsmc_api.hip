@@ -250,9 +250,9 @@ Layout make_layout(const dsmc_config &c, size_t nc, size_t nrep)
     L.nnew = take(nc * 4);
     L.perm = take(cap * 12);  // adoption: permutation + cell ids; steps: scratch of oversized tiles
     L.tstat = take(3 * nc * 8);  // per step tile, at its first cell
-    L.kc = take(sizeof(TileConst));
+    L.kc = take(REP_OFFSET + nrep * sizeof(RepConst));  // TileConst, then the channels' constants
     L.ctr = take(sizeof(Counters));
-    L.rep = take(nrep * sizeof(RepConst));
+    L.rep = L.kc + REP_OFFSET;
     L.tiles = take(2 * nc * 4);  // at most one tile per cell
     L.cell_rep = take(nc * 4);
     L.rstat = take(3 * nrep * 8);
@@ -335,6 +335,7 @@ struct dsmc_ctx {
     unsigned long long *rstat;
     struct TileGroup {
         int tc, ch, tile0, ntiles;
+        int rep;  // the group's one channel, or -1 when it spans several
     };
     std::vector<TileGroup> groups;
     std::vector<int32_t> tiles_host;
@@ -403,6 +404,7 @@ StepArgs step_args(const dsmc_ctx *x, int32_t cur, int64_t step, bool sample, bo
     a.kc = x->kc;
     a.tiles = x->tiles;
     a.r = 0;
+    a.c_first = -1;
     a.dev_step = x->capturing ? 1 : 0;
     a.step = (uint32_t)step;
     a.cur = cur;
@@ -489,6 +491,11 @@ int set_tiling(dsmc_ctx *x, int ppt, hipStream_t s)
             }
         }
         g.ntiles = (int)(x->tiles_host.size() / 2) - g.tile0;
+        g.rep = -1;
+        for (int r = 0, n = 0; r < x->nrep; ++r) {
+            if (shape_of[r] != k) continue;
+            g.rep = (n++ == 0) ? r : -1;
+        }
         if (g.ntiles > 0) x->groups.push_back(g);
     }
     x->ntiles = (int)(x->tiles_host.size() / 2);
@@ -507,6 +514,10 @@ void launch_tiles(const dsmc_ctx *x, int kind, bool move, hipStream_t s, const S
     for (const dsmc_ctx::TileGroup &g : x->groups) {
         StepArgs a = a0;
         a.tiles = x->tiles + 2 * (size_t)g.tile0;
+        if (g.rep >= 0) {  // one channel: tiles follow from the block index
+            a.r = g.rep;
+            a.c_first = x->reps[g.rep].cbase;
+        }
         const unsigned n = (unsigned)g.ntiles;
 #define DSMC_LAUNCH(TC, CH, S)                                  \
     do {                                                        \

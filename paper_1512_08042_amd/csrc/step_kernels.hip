@@ -681,12 +681,18 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     __shared__ TileLds<TC, CH, S> L;
     constexpr int T = 64 / TC, SPAN = T / 16;
     const int lane = threadIdx.x;
-    // the tile: up to TC consecutive cells of one channel
-    const __attribute__((address_space(4))) int32_t *td =
-        (const __attribute__((address_space(4))) int32_t *)a0.tiles + 2 * (size_t)blockIdx.x;
-    const int c0 = td[0];
+    // the tile: up to TC consecutive cells of one channel (from the launch's
+    // arguments when it covers one channel, else from the tile table)
     StepArgs a = a0;
-    a.r = td[1];
+    int c0;
+    if (a0.c_first >= 0) {
+        c0 = a0.c_first + (int)blockIdx.x * TC;
+    } else {
+        const __attribute__((address_space(4))) int32_t *td =
+            (const __attribute__((address_space(4))) int32_t *)a0.tiles + 2 * (size_t)blockIdx.x;
+        c0 = td[0];
+        a.r = td[1];
+    }
     // a step graph is captured with steps counted from 0 and replayed from
     // the step the host sets (an even one, so every parity is unchanged)
     if (a0.dev_step) a.step += ((const __attribute__((address_space(4))) Counters *)a.K().ctr)->step_base;

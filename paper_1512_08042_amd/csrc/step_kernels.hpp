@@ -54,10 +54,14 @@ struct TileConst {
     unsigned long long *tstat;  // [tiles][3] running collisions, candidates and wall hits of every tile
     double *mom;             // [11][ncells] sums
     double *nbar, *sigcmax, *rem;
-    const RepConst *rep;     // [nrep] the channels
+    const RepConst *rep;     // [nrep] the channels (stored right after this block, at REP_OFFSET)
     double s_th;             // sqrt(kT/m)
     int nbar_mode, ncells, far_cap, nrep;
 };
+
+// the channels' constants follow the TileConst block in device memory, so a
+// tile reaches its channel's fields with one scalar load from the argument
+constexpr size_t REP_OFFSET = (sizeof(TileConst) + 63) & ~size_t(63);
 
 // One launch of a step kernel.  k_step: the DSMC step `step` (collisions
 // of that step, then the move of step + 1), reading buffer cur and writing
@@ -69,7 +73,8 @@ struct StepArgs {
     const int32_t *tiles;  // [tiles][2]: first cell and replica of every tile of the launch
     uint32_t step;
     int cur, sample, classify;
-    int r;                 // replica of the tile (set by the tile kernel)
+    int r;                 // replica of the tile (the launch's, or set by the tile kernel from the table)
+    int c_first;           // >= 0: every tile is in replica r, tile b starts at cell c_first + b * TC
     int dev_step;          // step graphs: add the device step base to `step`
 
     // the blocks are read through the constant address space: they do not
@@ -80,7 +85,8 @@ struct StepArgs {
     }
     __device__ const __attribute__((address_space(4))) RepConst &R() const
     {
-        return ((const __attribute__((address_space(4))) RepConst *)K().rep)[r];
+        return ((const __attribute__((address_space(4))) RepConst *)((const __attribute__((address_space(4))) char *)kc +
+                                                                     REP_OFFSET))[r];
     }
 
     __device__ Geometry geo() const
