@@ -92,7 +92,8 @@ constexpr int NTC_ROUND = 32;  // NTC candidates drawn per round (all cells of a
 template <int TC, int CH, class S>
 struct TileLds {
     static constexpr int CAP = 64 * CH;
-    S v[5][CAP];                   // x, y, vx, vy, vz of the tile's particles (stored precision), in new-slot order
+    S v[3][CAP];                   // vx, vy, vz of the tile's particles (stored precision), in new-slot order;
+                                   // positions stay in registers of the lane that owns the slot
     int32_t kr[CAP];               // next-step group (low 6 bits) and rank inside it, per slot
     double dr[5][NTC_ROUND];       // one round of NTC draws: R, cos(theta), sin(theta), cos(phi), sin(phi)
     int32_t di[2][NTC_ROUND];      // ... and the candidate pairs (i, j)
@@ -162,10 +163,13 @@ __device__ void tile_far_shift(const StepArgs &a, TileLds<TC, CH, S> &L, int t, 
 
 // Stages the long jumps arriving in the tile at their sorted slots: after
 // the near groups of smaller source cells and the long jumps of smaller
-// (source cell, source slot).  s[k] address the tile's stage.
+// (source cell, source slot).  s[2..4] address the tile's velocity stage;
+// positions go to s[0], s[1] too, or, when `pick` is given (positions kept in
+// the owner lanes' registers), the source slot goes to pick[slot] for the
+// owner lane to fetch.
 template <int TC, int CH, class S>
 __device__ void tile_far_gather(const StepArgs &a, const TileLds<TC, CH, S> &L, S *const *s, int c0, int ntc,
-                                int n_old)
+                                int n_old, int32_t *pick)
 {
     const uint32_t nf = min(a.K().ctr->nfar[a.far_in_slot()], (uint32_t)a.K().far_cap);
     const int D0 = L.csn[0];
@@ -188,7 +192,13 @@ __device__ void tile_far_gather(const StepArgs &a, const TileLds<TC, CH, S> &L, 
             continue;
         }
 #pragma unroll
-        for (int k = 0; k < 5; ++k) s[k][slot] = a.template in<S>(k)[q];
+        for (int k = 2; k < 5; ++k) s[k][slot] = a.template in<S>(k)[q];
+        if (pick) {
+            pick[slot] = q;
+        } else {
+            s[0][slot] = a.template in<S>(0)[q];
+            s[1][slot] = a.template in<S>(1)[q];
+        }
     }
 }
 
@@ -409,16 +419,16 @@ __device__ __forceinline__ int tile_dir(const StepArgs &a, const TileLds<TC, CH,
 // direction codes go to kr.  A particle that would cross a wall is left as
 // it is and marked KEY_WALL.  Returns whether the chunk has such particles.
 template <int TC, int CH, class S>
-__device__ __forceinline__ bool move_chunk_free(const StepArgs &a, const TileLds<TC, CH, S> &L, S *const *s,
-                                                int32_t *kr, int ntc, int nt, int b0)
+__device__ __forceinline__ bool move_chunk_free(const StepArgs &a, const TileLds<TC, CH, S> &L, S &px, S &py,
+                                                S *const *s, int32_t *kr, int ntc, int nt, int b0)
 {
     const int i = b0 + (int)threadIdx.x;
     bool wall = false;
     if (i < nt) {
         const int t = tile_cell<TC, CH, S>(L, ntc, L.csn[0], i);
         const double dt = a.R().dt, g = a.R().g, H = a.R().G.H, Lx = a.R().G.Lx;
-        double x = s[0][i], vx = s[2][i];
-        const double y = s[1][i], vy = s[3][i];
+        double x = px, vx = s[2][i];
+        const double y = py, vy = s[3][i];
         // the no-wall branch of move_particle, written out
         const double yn = y + vy * dt;
         if (yn < 0.0 || yn > H) {
@@ -436,8 +446,8 @@ __device__ __forceinline__ bool move_chunk_free(const StepArgs &a, const TileLds
             }
             // the stored (for FP32 state: rounded) position decides the cell
             const S xs = (S)x, ys = (S)yn;
-            s[0][i] = xs;
-            s[1][i] = ys;
+            px = xs;
+            py = ys;
             s[2][i] = (S)vx;
             kr[i] = t * NGRP + tile_dir<TC, CH, S>(a, L, t, (double)xs, (double)ys);
         }
@@ -447,18 +457,18 @@ __device__ __forceinline__ bool move_chunk_free(const StepArgs &a, const TileLds
 
 // the particles of one chunk marked KEY_WALL: the full move with walls
 template <int TC, int CH, class S>
-__device__ void move_chunk_walls(const StepArgs &a, const TileLds<TC, CH, S> &L, S *const *s, int32_t *kr,
-                                 int ntc, int nt, int b0, int &walls, bool &limit)
+__device__ void move_chunk_walls(const StepArgs &a, const TileLds<TC, CH, S> &L, S &px, S &py, S *const *s,
+                                 int32_t *kr, int ntc, int nt, int b0, int &walls, bool &limit)
 {
     const int i = b0 + (int)threadIdx.x;
     if (i < nt && kr[i] == KEY_WALL) {
         const int t = tile_cell<TC, CH, S>(L, ntc, L.csn[0], i);
-        double x = s[0][i], y = s[1][i], vx = s[2][i], vy = s[3][i], vz = s[4][i];
+        double x = px, y = py, vx = s[2][i], vy = s[3][i], vz = s[4][i];
         // wall draws are keyed by the slot inside the channel
         walls += move_particle(a.geo(), a.M1(), (uint32_t)(L.csn[0] + i - a.R().pbase), x, y, vx, vy, vz, limit);
         const S xs = (S)x, ys = (S)y;
-        s[0][i] = xs;
-        s[1][i] = ys;
+        px = xs;
+        py = ys;
         s[2][i] = (S)vx;
         s[3][i] = (S)vy;
         s[4][i] = (S)vz;
@@ -543,9 +553,13 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
     const int D0 = L.csn[0];
     S *s[5];
     int32_t *kr;
+    // STAGED: the positions of slot 64 b + lane stay in xr[b], yr[b] of this
+    // lane from the gather to the write (every phase maps slots to lanes so)
+    S xr[CH], yr[CH];
     if (STAGED) {
+        s[0] = s[1] = nullptr;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) s[k] = L.v[k];
+        for (int k = 2; k < 5; ++k) s[k] = L.v[k - 2];
         kr = L.kr;
     } else {
 #pragma unroll
@@ -581,14 +595,27 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
 #pragma unroll
         for (int b = 0; b < CH; ++b) {
             const int i = 64 * b + lane;
+            xr[b] = g[b][0];
+            yr[b] = g[b][1];
             if (i < nt && g_ok[b]) {
 #pragma unroll
-                for (int k = 0; k < 5; ++k) L.v[k][i] = g[b][k];
+                for (int k = 2; k < 5; ++k) L.v[k - 2][i] = g[b][k];
             }
         }
         if (GATHER && L.anyfar) {
             __syncthreads();
-            tile_far_gather<TC, CH, S>(a, L, s, c0, ntc, n_old);
+            tile_far_gather<TC, CH, S>(a, L, s, c0, ntc, n_old, L.kr);
+            __syncthreads();
+            // long jumps: the owner lane fetches the positions
+#pragma unroll
+            for (int b = 0; b < CH; ++b) {
+                const int i = 64 * b + lane;
+                if (i < nt && !g_ok[b]) {
+                    const int q = L.kr[i];
+                    xr[b] = a.template in<S>(0)[q];
+                    yr[b] = a.template in<S>(1)[q];
+                }
+            }
         }
         __syncthreads();
     } else if (GATHER) {
@@ -600,7 +627,7 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
 #pragma unroll
             for (int k = 0; k < 5; ++k) s[k][i] = a.template in<S>(k)[src];
         }
-        if (L.anyfar) tile_far_gather<TC, CH, S>(a, L, s, c0, ntc, n_old);
+        if (L.anyfar) tile_far_gather<TC, CH, S>(a, L, s, c0, ntc, n_old, nullptr);
         __threadfence();
         __syncthreads();
     }
@@ -615,9 +642,15 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
 
     if (!MOVE) {
         if (STAGED) {
-            for (int i = lane; i < nt; i += 64) {
 #pragma unroll
-                for (int k = 0; k < 5; ++k) a.template out<S>(k)[D0 + i] = L.v[k][i];
+            for (int b = 0; b < CH; ++b) {
+                const int i = 64 * b + lane;
+                if (i < nt) {
+                    a.template out<S>(0)[D0 + i] = xr[b];
+                    a.template out<S>(1)[D0 + i] = yr[b];
+#pragma unroll
+                    for (int k = 2; k < 5; ++k) a.template out<S>(k)[D0 + i] = L.v[k - 2][i];
+                }
             }
         }
         return;  // unstaged: already in place, in sorted order
@@ -626,11 +659,33 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
     // 4. move for the next step (walls in a second pass), grouped by (cell,
     // direction) in slot order
     bool anywall = false;
-    for (int b0 = 0; b0 < nt; b0 += 64) anywall |= move_chunk_free<TC, CH, S>(a, L, s, kr, ntc, nt, b0);
+    S dx = (S)0, dy = (S)0;  // stand-ins for the positions of slots beyond the tile
+    if (STAGED) {
+#pragma unroll
+        for (int b = 0; b < CH; ++b)
+            if (64 * b < nt) anywall |= move_chunk_free<TC, CH, S>(a, L, xr[b], yr[b], s, kr, ntc, nt, 64 * b);
+    } else {
+        for (int b0 = 0; b0 < nt; b0 += 64) {
+            const int i = b0 + lane;
+            anywall |= move_chunk_free<TC, CH, S>(a, L, i < nt ? s[0][i] : dx, i < nt ? s[1][i] : dy, s, kr, ntc, nt,
+                                                  b0);
+        }
+    }
     if (!STAGED) __threadfence();
     __syncthreads();
     if (anywall) {
-        for (int b0 = 0; b0 < nt; b0 += 64) move_chunk_walls<TC, CH, S>(a, L, s, kr, ntc, nt, b0, walls, limit);
+        if (STAGED) {
+#pragma unroll
+            for (int b = 0; b < CH; ++b)
+                if (64 * b < nt)
+                    move_chunk_walls<TC, CH, S>(a, L, xr[b], yr[b], s, kr, ntc, nt, 64 * b, walls, limit);
+        } else {
+            for (int b0 = 0; b0 < nt; b0 += 64) {
+                const int i = b0 + lane;
+                move_chunk_walls<TC, CH, S>(a, L, i < nt ? s[0][i] : dx, i < nt ? s[1][i] : dy, s, kr, ntc, nt, b0,
+                                            walls, limit);
+            }
+        }
         if (!STAGED) __threadfence();
         __syncthreads();
     }
@@ -640,11 +695,17 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
 
     // 5. write out, partitioned by group inside each cell
     if (STAGED) {
-        for (int i = lane; i < nt; i += 64) {
-            const int k6 = kr[i], key = k6 & 63, t = key / NGRP;
-            const int q = L.csn[t] + L.excl[key] + (k6 >> 6);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) a.template out<S>(k)[q] = L.v[k][i];
+        for (int b = 0; b < CH; ++b) {
+            const int i = 64 * b + lane;
+            if (i < nt) {
+                const int k6 = kr[i], key = k6 & 63, t = key / NGRP;
+                const int q = L.csn[t] + L.excl[key] + (k6 >> 6);
+                a.template out<S>(0)[q] = xr[b];
+                a.template out<S>(1)[q] = yr[b];
+#pragma unroll
+                for (int k = 2; k < 5; ++k) a.template out<S>(k)[q] = L.v[k - 2][i];
+            }
         }
     } else {
         __threadfence();
@@ -661,14 +722,21 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
             __syncthreads();
         }
     }
-    for (int i = lane; i < nt; i += 64) {
-        const int k6 = kr[i], key = k6 & 63, t = key / NGRP;
-        if (key - t * NGRP != DIR_FAR) continue;
-        const int q = L.csn[t] + L.excl[key] + (k6 >> 6);
-        int nix, niy;
-        cell_xy(a.geo(), STAGED ? L.v[0][i] : a.template out<S>(0)[q], STAGED ? L.v[1][i] : a.template out<S>(1)[q], nix, niy);
-        record_far(a.far_out(), a.farcnt_out(), a.K().ctr, a.far_out_slot(), a.K().far_cap, q, c0 + t,
-                   a.R().cbase + niy * a.geo().nx + nix);
+    // long jumps of the next step go to the far list
+#pragma unroll
+    for (int b = 0; b < (STAGED ? CH : 1); ++b) {
+        for (int i = STAGED ? 64 * b + lane : lane; i < nt; i += 64) {
+            const int k6 = kr[i], key = k6 & 63, t = key / NGRP;
+            if (key - t * NGRP == DIR_FAR) {
+                const int q = L.csn[t] + L.excl[key] + (k6 >> 6);
+                int nix, niy;
+                cell_xy(a.geo(), STAGED ? (double)xr[b] : (double)a.template out<S>(0)[q],
+                        STAGED ? (double)yr[b] : (double)a.template out<S>(1)[q], nix, niy);
+                record_far(a.far_out(), a.farcnt_out(), a.K().ctr, a.far_out_slot(), a.K().far_cap, q, c0 + t,
+                           a.R().cbase + niy * a.geo().nx + nix);
+            }
+            if (STAGED) break;
+        }
     }
 }
 
@@ -765,8 +833,11 @@ __global__ __launch_bounds__(64) void k_classify(StepArgs a)
     tile_kernel<TC, CH, S, false, true>(a);
 }
 
+// four waves per SIMD: the tile fits 128 VGPRs (a few spills in the cold
+// wall path) and about 9.4 KB of LDS (FP64, 2 cells x 4 chunks), so 16 tiles
+// share a CU; measured 8 % faster than three waves with no spills
 template <int TC, int CH, bool MOVE, class S>
-__global__ __launch_bounds__(64) void k_step(StepArgs a)
+__global__ __launch_bounds__(64, 4) void k_step(StepArgs a)
 {
     tile_kernel<TC, CH, S, true, MOVE>(a);
 }
