@@ -740,6 +740,17 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
     }
 }
 
+// Workgroups are dealt to the chip's 8 XCDs round-robin, each XCD with its
+// own L2.  Tile t of the launch is given to block b so that every XCD runs
+// one contiguous range of tiles: neighbouring tiles read each other's source
+// groups (and the cache lines their runs share) from the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int x = b & 7, i = b >> 3;  // the block's XCD and its rank there
+    const int q = n >> 3, r = n & 7;  // XCD x runs q + (x < r) tiles
+    return x * q + min(x, r) + i;
+}
+
 template <int TC, int CH, class S, bool GATHER, bool MOVE>
 __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
 {
@@ -752,12 +763,13 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     // the tile: up to TC consecutive cells of one channel (from the launch's
     // arguments when it covers one channel, else from the tile table)
     StepArgs a = a0;
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     int c0;
     if (a0.c_first >= 0) {
-        c0 = a0.c_first + (int)blockIdx.x * TC;
+        c0 = a0.c_first + tile * TC;
     } else {
         const __attribute__((address_space(4))) int32_t *td =
-            (const __attribute__((address_space(4))) int32_t *)a0.tiles + 2 * (size_t)blockIdx.x;
+            (const __attribute__((address_space(4))) int32_t *)a0.tiles + 2 * (size_t)tile;
         c0 = td[0];
         a.r = td[1];
     }
