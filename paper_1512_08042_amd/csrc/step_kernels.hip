@@ -635,6 +635,11 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
     // 2. collisions and 3. sample
     if (GATHER) {
         tile_ntc<TC, CH, S>(s[2], s[3], s[4], L, a.N(), c0, ntc, own_ntc, nbar, sig, rem, ncoll, ncand);
+        if (own_ntc) {  // the cells' NTC state is final here (stored now: nothing stays live to the end)
+            a.K().nbar[c0 + lane] = nbar;
+            a.K().sigcmax[c0 + lane] = sig;
+            a.K().rem[c0 + lane] = rem;
+        }
         if (!STAGED) __threadfence();
         __syncthreads();
         if (a.sample) tile_sample<TC, CH, S>(s[2], s[3], s[4], L, ntc, mown, mprev, mdst);
@@ -803,7 +808,6 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     const int n_old = GATHER ? a.cs_old()[nc] : 0;
     // running counters of the tile, kept at its first cell (valid for any tiling)
     unsigned long long *const tst = a.K().tstat + 3 * (size_t)c0 + (lane < 3 ? lane : 0);
-    const unsigned long long tprev = lane < 3 ? *tst : 0ull;
     if (GATHER && lane < TC * NDIR) {
         int s, n, src;
         tile_raw_group<TC>(a, c0, ntc, lane, s, n, src);
@@ -826,16 +830,11 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
         tile_body<TC, CH, S, GATHER, MOVE, false>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev,
                                                mdst, ncoll, ncand, walls, limit);
 
-    if (own_ntc) {
-        a.K().nbar[c0 + lane] = nbar;
-        a.K().sigcmax[c0 + lane] = sig;
-        a.K().rem[c0 + lane] = rem;
-    }
     // the tile's running counters (no atomics: every tile owns its entry)
     ncoll = wave_sum_u64(ncoll);
     ncand = wave_sum_u64(ncand);
     const unsigned long long wsum = wave_sum_u64((unsigned long long)walls);
-    if (lane < 3) *tst = tprev + (lane == 0 ? ncoll : (lane == 1 ? ncand : wsum));
+    if (lane < 3) *tst += (lane == 0 ? ncoll : (lane == 1 ? ncand : wsum));
     if (MOVE && ballot64(limit) != 0 && lane == 0) atomicOr(&a.K().ctr->status, ST_WALL_LIMIT);
 }
 
