@@ -399,8 +399,8 @@ int dsmc_get_views(dsmc_ctx *ctx, dsmc_views *out);
  * number of timed launches, then clears the records of that kernel. */
 #define DSMC_K_CLASSIFY 0   /* moves of a settled state for the coming step (first step of a dsmc_step call) */
 #define DSMC_K_CELL_COUNT 1 /* particles arriving per cell */
-#define DSMC_K_SCAN 2       /* scan of the block sums */
-#define DSMC_K_CELL_FINAL 3 /* new cell_start */
+#define DSMC_K_SCAN 2       /* (not used by dsmc_step: its scan is part of DSMC_K_CELL_FINAL) */
+#define DSMC_K_CELL_FINAL 3 /* new cell_start: block offsets and scan in one pass */
 #define DSMC_K_STEP 4       /* gather + collide + sample + next move + partitioned write */
 #define DSMC_K_PROJECT 5    /* DSMC2LB projection */
 #define DSMC_K_RESEED 6     /* LB2DSMC reseed (all of its kernels) */

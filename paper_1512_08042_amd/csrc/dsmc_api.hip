@@ -1090,11 +1090,8 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
         c.cell_rep = x->cell_rep;
         c.ncells = nc;
         TRY(launch(x, DSMC_K_CELL_COUNT, s, [&] { k_cell_count<<<x->nblk, 256, 0, s>>>(c); }));
-        TRY(launch(x, DSMC_K_SCAN, s, [&] {
-            k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, x->cs[nxt], nc, x->ctr, p ^ 1);
-        }));
         TRY(launch(x, DSMC_K_CELL_FINAL, s, [&] {
-            k_block_scan<<<x->nblk, 256, 0, s>>>(x->countnew, nc, x->blocksum, x->cs[nxt]);
+            k_cell_final<<<x->nblk, 256, 0, s>>>(x->countnew, nc, x->blocksum, x->cs[nxt], x->ctr, p ^ 1);
         }));
 
         const bool sample = sample_every > 0 && ((x->step + 1) % sample_every) == 0;

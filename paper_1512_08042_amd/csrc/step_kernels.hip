@@ -990,6 +990,30 @@ __global__ __launch_bounds__(256) void k_block_sums(const int32_t *counts, int n
 }
 
 // generic exclusive scan of per-cell counts given scanned block sums
+// Cell starts of the coming sort in one pass: block b adds up the block sums
+// of blocks 0 .. b-1 itself (at most a few hundred integers, exact in any
+// order), then scans its own 256 counts; the last block writes the total.
+// Block 0 also retires the long-jump list of parity reset_slot (the previous
+// step's, already sorted), which the coming step refills.
+__global__ __launch_bounds__(256) void k_cell_final(const int32_t *counts, int ncells, const int32_t *blocksum,
+                                                    int32_t *cs, Counters *ctr, int reset_slot)
+{
+    __shared__ int lds[4];
+    const int b = blockIdx.x;
+    if (b == 0 && threadIdx.x == 0 && reset_slot >= 0) {
+        ctr->nfar_total += ctr->nfar[reset_slot];
+        ctr->nfar[reset_slot] = 0u;
+    }
+    int part = 0;
+    for (int i = threadIdx.x; i < b; i += 256) part += blocksum[i];
+    const int off = block_reduce_256(part, lds);
+    const int c = b * 256 + threadIdx.x;
+    const int v = c < ncells ? counts[c] : 0;
+    const int ex = block_exscan_256(v, lds);
+    if (c < ncells) cs[c] = off + ex;
+    if (b == (int)gridDim.x - 1 && threadIdx.x == 255) cs[ncells] = off + ex + v;
+}
+
 __global__ __launch_bounds__(256) void k_block_scan(const int32_t *counts, int ncells, const int32_t *blockoff,
                                                     int32_t *cs)
 {

@@ -325,6 +325,8 @@ __global__ void k_init_maxwell(InitArgs a);
 template <class S>
 __global__ void k_adopt_count(AdoptArgs a);
 __global__ void k_block_sums(const int32_t *counts, int ncells, int32_t *blocksum);
+__global__ void k_cell_final(const int32_t *counts, int ncells, const int32_t *blocksum, int32_t *cs, Counters *ctr,
+                             int reset_slot);
 __global__ void k_block_scan(const int32_t *counts, int ncells, const int32_t *blockoff, int32_t *cs);
 __global__ void k_adopt_place(AdoptArgs a);
 __global__ void k_adopt_sortcell(AdoptArgs a);
