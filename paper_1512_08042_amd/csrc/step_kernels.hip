@@ -830,11 +830,13 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
         tile_body<TC, CH, S, GATHER, MOVE, false>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev,
                                                mdst, ncoll, ncand, walls, limit);
 
-    // the tile's running counters (no atomics: every tile owns its entry)
+    // the tile's running counters.  Every tile owns its entry; the add is an
+    // atomic without return only so that the wave need not wait for a read,
+    // which would queue behind all of the tile's stores
     ncoll = wave_sum_u64(ncoll);
     ncand = wave_sum_u64(ncand);
     const unsigned long long wsum = wave_sum_u64((unsigned long long)walls);
-    if (lane < 3) *tst += (lane == 0 ? ncoll : (lane == 1 ? ncand : wsum));
+    if (lane < 3) atomicAdd(tst, lane == 0 ? ncoll : (lane == 1 ? ncand : wsum));
     if (MOVE && ballot64(limit) != 0 && lane == 0) atomicOr(&a.K().ctr->status, ST_WALL_LIMIT);
 }
 
