@@ -76,12 +76,18 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
 // Table 1 steps 1-3 on node populations f[q * stride]: rho, u, comoving and
 // density-normalised a(2), a(3) about u, M = max |component|, C = 1 + 30 M.
 // prm: rho, ux, uy, a2xx, a2xy, a2yy, a3xxx, a3xxy, a3xyy, a3yyy, M, C.
+// Q is fixed at compile time so that the node's Q loads are all issued at
+// once; the sums run over q in order.
+template <int Q>
 __device__ void grad_params(const double *f, size_t stride, const Lattice &L, int order, double *prm)
 {
-    const int Q = L.Q;
+    double fq[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fq[q] = f[(size_t)q * stride];
     double rho = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const double fa = f[(size_t)q * stride];
+        const double fa = fq[q];
         rho += fa;
         jx += fa * L.xi[q][0];
         jy += fa * L.xi[q][1];
@@ -91,8 +97,9 @@ __device__ void grad_params(const double *f, size_t stride, const Lattice &L, in
     if (!(rho > 0.0)) return;
     const double ux = jx / rho, uy = jy / rho;
     double sxx = 0, sxy = 0, syy = 0, sxxx = 0, sxxy = 0, sxyy = 0, syyy = 0;
+#pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const double fa = f[(size_t)q * stride];
+        const double fa = fq[q];
         const double cx = L.xi[q][0] - ux, cy = L.xi[q][1] - uy;
         sxx += fa * (cx * cx - 1.0);
         sxy += fa * (cx * cy);
@@ -167,7 +174,10 @@ __global__ __launch_bounds__(256) void k_reseed_prep(ReseedArgs a)
         return;
     }
     double *pr = a.prm + (size_t)i * 12;
-    grad_params(a.f + c, (size_t)a.ncells, a.L, a.order, pr);
+    if (a.L.Q == 9)
+        grad_params<9>(a.f + c, (size_t)a.ncells, a.L, a.order, pr);
+    else
+        grad_params<37>(a.f + c, (size_t)a.ncells, a.L, a.order, pr);
     const U4 r = draw(a.k0, a.k1, 0u, (uint32_t)c, a.event, TAG_RESEED_N, 0u);
     const double target = pr[0] * (double)a.ppc + u53(r.x, r.y);
     bool finite = true;
@@ -265,20 +275,25 @@ template __global__ void k_reseed_copy<double>(ReseedArgs);
 template __global__ void k_reseed_copy<float>(ReseedArgs);
 
 // Listed cells: one wave per listed cell generates its new particles
-// (Table 1 steps 4-6) into the cell's new slots.
+// (Table 1 steps 4-6) into the cell's new slots.  Four waves per SIMD: the
+// cell's Grad parameters are read from LDS (the same address on every lane)
+// rather than held in registers, so that a strip of up to 4 cells per SIMD
+// runs in one round.
 template <class S>
-__global__ __launch_bounds__(256) void k_reseed_gen(ReseedArgs a)
+__global__ __launch_bounds__(256, 4) void k_reseed_gen(ReseedArgs a)
 {
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= a.nsel) return;
+    __shared__ double s_prm[4][12];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 4 + w;
+    if (i >= a.nsel) return;  // (whole waves: no barrier follows)
     if (a.ctr->reseed_err != 0u) return;
     const int c = a.cells[i];
     const int nn = a.nnew[i];
     const int d0 = a.cs_new[c];
-    double prm[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) prm[k] = a.prm[(size_t)i * 12 + k];
+    if (lane < 12) s_prm[w][lane] = a.prm[(size_t)i * 12 + lane];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const double *prm = s_prm[w];
     const double C = prm[11];
     const int ix = c % a.nx, iy = c / a.nx;
     bool limit = false;
@@ -310,17 +325,10 @@ __global__ __launch_bounds__(256) void k_reseed_gen(ReseedArgs a)
                 limit = true;
                 fin = true;
             }
-            if (fin) {
-                double zz0, zz1;
-                const U4 Pp = draw(a.k0, a.k1, 0u, (uint32_t)c, a.event, TAG_RESEED_POS, (uint32_t)k);
-                const U4 V = draw(a.k0, a.k1, 1u, (uint32_t)c, a.event, TAG_RESEED_POS, (uint32_t)k);
-                box_muller(u53(V.x, V.y), u53(V.z, V.w), zz0, zz1);
+            if (fin) {  // the in-plane velocity (Table 1 step 6) is final here
                 const int q = d0 + k;
-                ((S *)a.out[0])[q] = (S)inside_cell(ix, u53(Pp.x, Pp.y));
-                ((S *)a.out[1])[q] = (S)inside_cell(iy, u53(Pp.z, Pp.w));
                 ((S *)a.out[2])[q] = (S)(a.s_th * (z0 + prm[1]));
                 ((S *)a.out[3])[q] = (S)(a.s_th * (z1 + prm[2]));
-                ((S *)a.out[4])[q] = (S)(a.s_th * zz0);
             }
         }
         const uint64_t m = ballot64(fin);
@@ -329,6 +337,18 @@ __global__ __launch_bounds__(256) void k_reseed_gen(ReseedArgs a)
             t = 0;
         }
         next += __popcll(m);
+    }
+    // position (uniform in the cell) and out-of-plane velocity (Maxwellian)
+    // of every new particle, one ordinal per lane: no rejection step here
+    for (int kk = lane; kk < nn; kk += 64) {
+        double zz0, zz1;
+        const U4 Pp = draw(a.k0, a.k1, 0u, (uint32_t)c, a.event, TAG_RESEED_POS, (uint32_t)kk);
+        const U4 V = draw(a.k0, a.k1, 1u, (uint32_t)c, a.event, TAG_RESEED_POS, (uint32_t)kk);
+        box_muller(u53(V.x, V.y), u53(V.z, V.w), zz0, zz1);
+        const int q = d0 + kk;
+        ((S *)a.out[0])[q] = (S)inside_cell(ix, u53(Pp.x, Pp.y));
+        ((S *)a.out[1])[q] = (S)inside_cell(iy, u53(Pp.z, Pp.w));
+        ((S *)a.out[4])[q] = (S)(a.s_th * zz0);
     }
     if (__ballot(limit) != 0 && lane == 0) atomicOr(&a.ctr->status, ST_AR_LIMIT);
 }
