@@ -187,7 +187,12 @@ int dsmc_project_moments(const double *avg, int64_t ncells, int32_t ppc, double 
  * The cell's previous particles are removed; every other cell keeps its
  * particles in order.  order 2 or 3.  A cell list with bad ids, or a result
  * above capacity, skips the whole reseed and sets a status bit.
- * Errors: DSMC_EINVAL. */
+ * The call writes only the new particles; the other cells' particles move to
+ * their new slots in the next dsmc_step's first pass over the state (which
+ * reads every particle anyway), or, if another call that reads the state
+ * comes first (dsmc_get_views, dsmc_read_status, map_lbm_to_dsmc, the graph
+ * calls), in a copy that call enqueues.  cell_ids is not read after the call's
+ * work has run.  Errors: DSMC_EINVAL. */
 int map_lbm_to_dsmc(dsmc_ctx *ctx, int32_t lattice, int32_t order, const double *f_in, const int32_t *cell_ids,
                     int32_t nsel, void *stream);
 
@@ -387,10 +392,13 @@ int dsmc_graph_create(dsmc_ctx *ctx, int32_t nsteps, int32_t sample_every, void 
 int dsmc_graph_launch(dsmc_ctx *ctx, void *stream);
 
 /* Synchronise the context's last stream and read the status word and
- * counters; clear != 0 resets the status bits.  Errors: DSMC_EHIP. */
+ * counters; clear != 0 resets the status bits.  Completes a pending reseed
+ * first (see map_lbm_to_dsmc).  Errors: DSMC_EHIP. */
 int dsmc_read_status(dsmc_ctx *ctx, dsmc_status *out, int32_t clear, void *stream);
 
-/* Pointers into the caller's buffers describing the current state. */
+/* Pointers into the caller's buffers describing the current state.  A
+ * pending reseed (see map_lbm_to_dsmc) is completed first, on the stream of
+ * the context's last call. */
 int dsmc_get_views(dsmc_ctx *ctx, dsmc_views *out);
 
 /* Kernel timing with HIP events on the launch stream.  dsmc_profile_enable

@@ -354,6 +354,13 @@ struct dsmc_ctx {
     // their cells, collided and sampled).  `classified` is true only inside
     // a call.
     bool classified;
+    // A reseed leaves the state pending: buffer cur still holds the old
+    // particles (cell starts cs[cur]), buffer 1 - cur the marked cells' new
+    // particles at their slots after the reseed (cell starts cs[1 - cur]),
+    // and the marks and the reseed's error flag are set.  The next step's
+    // classify pass completes it (it reads every particle anyway); any other
+    // call that reads particles or cell starts settles it first with a copy.
+    bool pending;
     hipStream_t last;
     bool prof;
     std::vector<ProfRec> recs;
@@ -406,6 +413,7 @@ StepArgs step_args(const dsmc_ctx *x, int32_t cur, int64_t step, bool sample, bo
     a.r = 0;
     a.c_first = -1;
     a.dev_step = x->capturing ? 1 : 0;
+    a.reseed = 0;
     a.step = (uint32_t)step;
     a.cur = cur;
     a.sample = sample ? 1 : 0;
@@ -432,6 +440,7 @@ int upload_tile_const(dsmc_ctx *x, hipStream_t s)
     k.nbar = x->nbar;
     k.sigcmax = x->sigcmax;
     k.rem = x->rem;
+    k.mark = x->mark;
     k.rep = x->rep;
     k.s_th = x->s_th;
     k.nbar_mode = x->cfg.nbar_mode;
@@ -856,6 +865,7 @@ int init_ctx(const dsmc_config *cfg, const dsmc_replica *reps, int32_t nrep, con
     x->nsamples = 0;
     x->reseed_events = 0;
     x->classified = false;
+    x->pending = false;
     x->prof = false;
     x->last = s;
     x->capturing = false;
@@ -1063,6 +1073,42 @@ int dsmc_replica_counters(dsmc_ctx *x, uint64_t *out, void *stream)
     return hipStreamSynchronize(s) == hipSuccess ? DSMC_OK : DSMC_EHIP;
 }
 
+}  // extern "C"
+
+namespace {
+// completes a pending reseed by copying the kept cells' particles over
+int settle(dsmc_ctx *x, hipStream_t s)
+{
+    if (!x->pending) return DSMC_OK;
+    const int cur = x->cur, nxt = 1 - cur;
+    ReseedArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.mark = x->mark;
+    a.cs_old = x->cs[cur];
+    a.cs_new = x->cs[nxt];
+    for (int k = 0; k < 5; ++k) {
+        a.in[k] = x->st[cur][k];
+        a.out[k] = x->st[nxt][k];
+    }
+    a.ctr = x->ctr;
+    a.ncells = x->ncells;
+    const unsigned gcopy = (unsigned)((x->ncells + RC_TILE - 1) / RC_TILE);
+    TRY(launch(x, DSMC_K_RESEED, s, [&] {
+        if (state32(x->cfg))
+            k_reseed_copy<float><<<gcopy, 256, 0, s>>>(a);
+        else
+            k_reseed_copy<double><<<gcopy, 256, 0, s>>>(a);
+        k_reseed_done<<<1, 64, 0, s>>>(x->ctr);
+    }));
+    x->cur = nxt;
+    x->pending = false;
+    x->classified = false;
+    return DSMC_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
 {
     if (!x || nsteps < 0 || sample_every < 0) return DSMC_EINVAL;
@@ -1074,8 +1120,19 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
         const int p = (int)(x->step & 1);
         TRY(fill_i32(x->farcnt, 2 * (size_t)nc, 0, s));
         k_far_reset<<<1, 64, 0, s>>>(x->ctr, p);
-        const StepArgs a = step_args(x, x->cur, x->step, false, true);
-        TRY(launch(x, DSMC_K_CLASSIFY, s, [&] { launch_tiles(x, 0, true, s, a); }));
+        if (x->pending) {  // the classify pass completes the reseed into the other buffer
+            StepArgs a = step_args(x, 1 - x->cur, x->step, false, true);
+            a.reseed = 1;
+            TRY(launch(x, DSMC_K_CLASSIFY, s, [&] {
+                launch_tiles(x, 0, true, s, a);
+                k_reseed_done<<<1, 64, 0, s>>>(x->ctr);
+            }));
+            x->cur = 1 - x->cur;
+            x->pending = false;
+        } else {
+            const StepArgs a = step_args(x, x->cur, x->step, false, true);
+            TRY(launch(x, DSMC_K_CLASSIFY, s, [&] { launch_tiles(x, 0, true, s, a); }));
+        }
         x->classified = true;
     }
     for (int32_t it = 0; it < nsteps; ++it) {
@@ -1215,6 +1272,7 @@ int map_lbm_to_dsmc(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f
     if (nsel > x->ncells) return DSMC_EINVAL;
     hipStream_t s = S(stream);
     x->last = s;
+    TRY(settle(x, s));
     const uint32_t event = (uint32_t)x->reseed_events;
     x->reseed_events += 1;
     const int cur = x->cur, nxt = 1 - cur;
@@ -1252,17 +1310,16 @@ int map_lbm_to_dsmc(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f
         k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, x->cs[nxt], x->ncells, x->ctr, -1);
         k_block_scan<<<x->nblk, 256, 0, s>>>(x->countnew, x->ncells, x->blocksum, x->cs[nxt]);
         k_reseed_check<<<1, 64, 0, s>>>(a);
-        const unsigned gcopy = (unsigned)((x->ncells + RC_TILE - 1) / RC_TILE);
-        if (state32(x->cfg)) {
-            k_reseed_copy<float><<<gcopy, 256, 0, s>>>(a);
-            if (nsel > 0) k_reseed_gen<float><<<grid_cells_wave(nsel), 256, 0, s>>>(a);
-        } else {
-            k_reseed_copy<double><<<gcopy, 256, 0, s>>>(a);
-            if (nsel > 0) k_reseed_gen<double><<<grid_cells_wave(nsel), 256, 0, s>>>(a);
+        // the new particles go to buffer nxt; the kept ones follow when the
+        // state settles (the next step's classify pass, or settle())
+        if (nsel > 0) {
+            if (state32(x->cfg))
+                k_reseed_gen<float><<<grid_cells_wave(nsel), 256, 0, s>>>(a);
+            else
+                k_reseed_gen<double><<<grid_cells_wave(nsel), 256, 0, s>>>(a);
         }
-        k_reseed_unmark<<<gsel, 256, 0, s>>>(a);
     }));
-    x->cur = nxt;
+    x->pending = true;
     x->classified = false;
     return DSMC_OK;
 }
@@ -1418,6 +1475,7 @@ int dsmc_read_status(dsmc_ctx *x, dsmc_status *out, int32_t clear, void *stream)
 {
     if (!x || !out) return DSMC_EINVAL;
     hipStream_t s = S(stream);
+    TRY(settle(x, s));
     Counters h;
     int32_t n = 0;
     k_tile_stats<<<1, 1024, 0, s>>>(x->tstat, x->ncells, x->ctr);
@@ -1443,6 +1501,7 @@ int dsmc_read_status(dsmc_ctx *x, dsmc_status *out, int32_t clear, void *stream)
 int dsmc_get_views(dsmc_ctx *x, dsmc_views *out)
 {
     if (!x || !out) return DSMC_EINVAL;
+    TRY(settle(x, x->last));  // a pending reseed, on the stream of the last call
     out->current = x->cur;
     out->cell_start = x->cs[x->cur];
     out->nbar = x->nbar;
@@ -1493,6 +1552,7 @@ int dsmc_graph_create(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *s
     if (sample_every > 0 && nsteps % sample_every != 0) return DSMC_EINVAL;
     hipStream_t s = S(stream);
     if (s == nullptr) return DSMC_EINVAL;  // capture needs a created stream
+    TRY(settle(x, s));                     // (the graph starts from a settled state)
     if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
     if (x->graph) (void)hipGraphDestroy(x->graph);
     x->gexec = nullptr;
@@ -1535,6 +1595,7 @@ int dsmc_graph_launch(dsmc_ctx *x, void *stream)
 {
     if (!x) return DSMC_EINVAL;
     if (!x->gexec) return DSMC_ESTATE;
+    TRY(settle(x, S(stream)));
     // the captured parities and sampling pattern must hold from this step
     if ((x->step & 1) || x->cur != x->g_cur) return DSMC_ESTATE;
     if (x->g_sample_every > 0 && x->step % x->g_sample_every != 0) return DSMC_ESTATE;

@@ -232,10 +232,11 @@ __global__ void k_reseed_check(ReseedArgs a)
     }
 }
 
-// Kept cells: one workgroup per tile of RC_TILE cells streams the tile's
-// old particles and copies those of unlisted cells to their new slots (the
-// identity when the reseed was rejected, in which case cell_start is
-// restored as well).
+// Kept cells of a pending reseed (when no step completes it): one
+// workgroup per tile of RC_TILE cells streams the tile's old particles and
+// copies those of unmarked cells to their new slots (the identity when the
+// reseed was rejected, in which case cell_start is restored as well), and
+// clears the tile's marks.
 constexpr int RC_TILE = 64;
 
 template <class S>
@@ -251,7 +252,10 @@ __global__ __launch_bounds__(256) void k_reseed_copy(ReseedArgs a)
         s_old[tid] = a.cs_old[c];
         s_new[tid] = err ? a.cs_old[c] : a.cs_new[c];
     }
-    if (tid < RC_TILE) s_keep[tid] = (tid < nt) && (err || a.mark[c0 + tid] == 0);
+    if (tid < RC_TILE) {
+        s_keep[tid] = (tid < nt) && (err || a.mark[c0 + tid] == 0);
+        if (tid < nt) a.mark[c0 + tid] = 0;
+    }
     __syncthreads();
     if (err) {
         if (tid < nt) a.cs_new[c0 + tid] = s_old[tid];
@@ -356,17 +360,14 @@ __global__ __launch_bounds__(256, 4) void k_reseed_gen(ReseedArgs a)
 template __global__ void k_reseed_gen<double>(ReseedArgs);
 template __global__ void k_reseed_gen<float>(ReseedArgs);
 
-__global__ __launch_bounds__(256) void k_reseed_unmark(ReseedArgs a)
+// the end of a reseed (its cells' marks were cleared as the state settled)
+__global__ void k_reseed_done(Counters *ctr)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i == 0) {
-        a.ctr->reseed_err = 0u;
-        a.ctr->reseed_new = 0ull;
-        a.ctr->reseed_removed = 0ull;
+    if (threadIdx.x == 0) {
+        ctr->reseed_err = 0u;
+        ctr->reseed_new = 0ull;
+        ctr->reseed_removed = 0ull;
     }
-    if (i >= a.nsel) return;
-    const int c = a.cells[i];
-    if (c >= 0 && c < a.ncells) a.mark[c] = 0;
 }
 
 // ---- BGK lattice step (Section 3.1), one thread per node, push streaming ----

@@ -107,6 +107,7 @@ struct TileLds {
     int32_t gn[TC][NDIR];          // their sizes
     int32_t gstart[TC][NDIR];      // their first slots inside the cell
     int32_t raw[3][TC * NDIR];     // near groups before ordering: source cell, size, first source slot
+    int32_t rsrc[TC];              // classify after a reseed: first old slot of a kept cell, -1 for a new one
     int32_t run[TC * NGRP];        // sizes of the next step's groups of the tile's cells ...
     int32_t excl[TC * NGRP];       // ... and their offsets inside each cell
 };
@@ -588,9 +589,18 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
                     src = D0 + i;
                 }
             }
+            bool old = false;  // classify after a reseed: a kept cell's particle, from the old buffer
+            if (!GATHER && a.reseed && i < nt) {
+                const int t = tile_cell<TC, CH, S>(L, ntc, D0, i);
+                if (L.rsrc[t] >= 0) {
+                    src = L.rsrc[t] + (i - (L.csn[t] - D0));
+                    old = true;
+                }
+            }
             g_ok[b] = src >= 0;
 #pragma unroll
-            for (int k = 0; k < 5; ++k) g[b][k] = src >= 0 ? a.template in<S>(k)[src] : (S)0;
+            for (int k = 0; k < 5; ++k)
+                g[b][k] = src >= 0 ? (old ? a.template old_in<S>(k) : a.template in<S>(k))[src] : (S)0;
         }
 #pragma unroll
         for (int b = 0; b < CH; ++b) {
@@ -628,6 +638,16 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
             for (int k = 0; k < 5; ++k) s[k][i] = a.template in<S>(k)[src];
         }
         if (L.anyfar) tile_far_gather<TC, CH, S>(a, L, s, c0, ntc, n_old, nullptr);
+        __threadfence();
+        __syncthreads();
+    } else if (a.reseed) {  // classify after a reseed: the kept cells' particles into place first
+        for (int i = lane; i < nt; i += 64) {
+            const int t = tile_cell<TC, CH, S>(L, ntc, D0, i);
+            if (L.rsrc[t] < 0) continue;
+            const int q = L.rsrc[t] + (i - (L.csn[t] - D0));
+#pragma unroll
+            for (int k = 0; k < 5; ++k) s[k][i] = a.template old_in<S>(k)[q];
+        }
         __threadfence();
         __syncthreads();
     }
@@ -784,8 +804,26 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     const int nc = a.K().ncells, nx = a.geo().nx, cb = a.R().cbase, ce = a.R().cend;
     const int ntc = min(TC, ce - c0);
 
+    // classify after a reseed (one channel): a rejected reseed (error flag)
+    // keeps every cell's particles at its old slots and restores the old
+    // cell starts; otherwise a marked cell's new particles are in place and
+    // every other cell's particles move over from the old buffer
+    const bool rs = !GATHER && a.reseed;
+    const bool rerr = rs && ((const __attribute__((address_space(4))) Counters *)a.K().ctr)->reseed_err != 0u;
+    const int32_t *const cs_old = a.K().cs[1 - a.cur];
+
     // set-up: every per-cell quantity of the tile is loaded in one round
-    if (lane <= TC) L.csn[lane] = a.cs_new()[min(c0 + lane, ce)];
+    if (lane <= TC) L.csn[lane] = (rerr ? cs_old : a.cs_new())[min(c0 + lane, ce)];
+    if (rs && lane < TC) {
+        const int c = min(c0 + lane, ce - 1);
+        const bool fresh = !rerr && lane < ntc && a.K().mark[c] != 0;
+        L.rsrc[lane] = fresh ? -1 : cs_old[c];
+        if (lane < ntc) {  // the tile owns its cells' marks and starts
+            a.K().mark[c] = 0;
+            if (rerr) a.K().cs[a.cur][c] = cs_old[c];
+        }
+        if (rerr && lane == 0 && c0 + ntc == ce) a.K().cs[a.cur][ce] = cs_old[ce];
+    }
     if (lane < TC) {
         const int c = min(c0 + lane, ce - 1) - cb;  // position inside the channel
         L.tiy[lane] = c / nx;

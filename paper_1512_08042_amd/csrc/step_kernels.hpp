@@ -54,6 +54,7 @@ struct TileConst {
     unsigned long long *tstat;  // [tiles][3] running collisions, candidates and wall hits of every tile
     double *mom;             // [11][ncells] sums
     double *nbar, *sigcmax, *rem;
+    int32_t *mark;           // [ncells] cells of a pending reseed (list index + 1, else 0)
     const RepConst *rep;     // [nrep] the channels (stored right after this block, at REP_OFFSET)
     double s_th;             // sqrt(kT/m)
     int nbar_mode, ncells, far_cap, nrep;
@@ -66,7 +67,10 @@ constexpr size_t REP_OFFSET = (sizeof(TileConst) + 63) & ~size_t(63);
 // One launch of a step kernel.  k_step: the DSMC step `step` (collisions
 // of that step, then the move of step + 1), reading buffer cur and writing
 // 1 - cur.  k_classify (classify = 1): the move of step `step` for the
-// settled state in buffer cur, in place.  Buffers of parity step & 1 hold
+// settled state in buffer cur, in place; with `reseed`, the state of a
+// pending reseed instead: the kept cells' particles are read from buffer
+// 1 - cur (at its cell starts) and the marked cells' new particles from
+// buffer cur, all moved into buffer cur.  Buffers of parity step & 1 hold
 // the partition read by the step's sort.
 struct StepArgs {
     const TileConst *kc;
@@ -76,6 +80,7 @@ struct StepArgs {
     int r;                 // replica of the tile (the launch's, or set by the tile kernel from the table)
     int c_first;           // >= 0: every tile is in replica r, tile b starts at cell c_first + b * TC
     int dev_step;          // step graphs: add the device step base to `step`
+    int reseed;            // k_classify: complete a pending reseed (see above)
 
     // the blocks are read through the constant address space: they do not
     // change while a kernel runs, so their fields come in by scalar loads
@@ -103,6 +108,8 @@ struct StepArgs {
     __device__ const S *in(int k) const { return (const S *)K().st[cur][k]; }
     template <class S>
     __device__ S *out(int k) const { return (S *)K().st[classify ? cur : 1 - cur][k]; }
+    template <class S>
+    __device__ const S *old_in(int k) const { return (const S *)K().st[1 - cur][k]; }  // reseed: kept cells
     __device__ const int32_t *cs_old() const { return K().cs[cur]; }
     __device__ const int32_t *cs_new() const { return K().cs[classify ? cur : 1 - cur]; }
     __device__ const int32_t *grp_in() const { return K().grp[step & 1u]; }

@@ -201,6 +201,53 @@ def test_reseed_rejections_leave_state():
     assert ch.views().reseed_events == 2
 
 
+@pytest.mark.parametrize("q,order,ncol,scale", [(9, 2, 3, 1.0), (37, 3, 2, 1.0), (37, 3, 3, 5.0), (37, 2, 0, 1.0)])
+def test_reseed_completed_by_the_next_step(q, order, ncol, scale):
+    # nothing reads the state between the reseed and the next step, so the
+    # step's first pass completes the reseed (kept cells from the old buffer,
+    # new particles in place).  scale 5 makes the strip cells dense enough
+    # that their tiles exceed the staged size; ncol 0 is an empty cell list.
+    nx, ny, ppc = 11, 6, 40
+    ch, ref, _ = _pair(nx, ny, ppc, 0.1, seed=4, capacity=nx * ny * ppc * 4)
+    ch.step(2)
+    ref.step(2)
+    lat = O.lattice(q)
+    f = inputs.populations(q + ncol, lat["w"] * scale, nx * ny, 0.04)
+    cells = inputs.strip_cells(nx, ny, ncol) if ncol else np.zeros(0, np.int32)
+    ch.map_from_lbm(torch.as_tensor(f, device="cuda").contiguous(), torch.as_tensor(cells, device="cuda"), q, order)
+    assert ref.lb2dsmc(lat, order, f, cells) == 0
+    ch.step(3, sample_every=1)
+    ref.step(3, sample_every=1)
+    _assert_state(ch, ref, what="3 steps after reseed")
+    _assert_counters(ch, ref)
+    if scale > 1.0:
+        assert ch.cell_start().diff().max().item() > 4 * ppc  # the oversized tiles were exercised
+
+
+def test_rejected_reseed_then_step():
+    # a reseed over capacity is rejected on the device: the step that
+    # completes it keeps every particle and the cell starts as they were
+    nx, ny, ppc = 4, 4, 10
+    ch, ref, _ = _pair(nx, ny, ppc, 0.1, seed=2, capacity=nx * ny * ppc + 5)
+    lat = O.lattice(9)
+    f = np.repeat(lat["w"][:, None] * 3.0, nx * ny, axis=1)
+    cells = np.arange(4, dtype=np.int32)
+    ch.map_from_lbm(torch.as_tensor(f, device="cuda"), torch.as_tensor(cells, device="cuda"), 9, 2)
+    ref.lb2dsmc(lat, 2, f, cells)
+    ch.step(2)
+    ref.step(2)
+    _assert_state(ch, ref, what="2 steps after a rejected reseed")
+    _assert_counters(ch, ref)
+    assert ch.status()["bits"] & 0x4
+    # the next reseed runs normally
+    f2 = np.repeat(lat["w"][:, None], nx * ny, axis=1)
+    ch.map_from_lbm(torch.as_tensor(f2, device="cuda"), torch.as_tensor(cells, device="cuda"), 9, 2)
+    assert ref.lb2dsmc(lat, 2, f2, cells) == 0
+    ch.step(1)
+    ref.step(1)
+    _assert_state(ch, ref, what="a step after the next reseed")
+
+
 @pytest.mark.parametrize("q,y_mode,g,nsteps", [(9, 0, 0.0, 3), (37, 0, 1e-3, 2), (37, 1, 2e-3, 3), (9, 1, 0.0, 1)])
 def test_lbm_step_matches_oracle(q, y_mode, g, nsteps):
     D, _ = _gpu()

@@ -139,6 +139,22 @@ def test_fp32_reseed_matches_oracle():
     _assert_counters(ch, ref)
 
 
+def test_fp32_reseed_completed_by_the_next_step():
+    nx, ny, ppc = 11, 6, 40
+    ch, ref, cfg = _pair32(nx, ny, ppc, 0.1, seed=7, capacity=nx * ny * ppc * 4)
+    ch.step(2)
+    ref.step(2)
+    lat = O.lattice(37)
+    f = inputs.populations(5, lat["w"] * 4.0, nx * ny, 0.02)
+    cells = inputs.strip_cells(nx, ny, 3)
+    ch.map_from_lbm(torch.as_tensor(f, device="cuda"), torch.as_tensor(cells, device="cuda"), 37, 3)
+    assert ref.lb2dsmc(lat, 3, f, cells) == 0
+    ch.step(2)
+    ref.step(2)
+    _assert_state32(ch, ref, what="2 steps after reseed, no read in between")
+    _assert_counters(ch, ref)
+
+
 def test_fp32_full_size_one_step():
     # the 512 x 256 x 100 channel: one step from the same caller-written FP32 state
     from paper_1512_08042_amd.config import body_force
