@@ -787,8 +787,14 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     const int lane = threadIdx.x;
     // the tile: up to TC consecutive cells of one channel (from the launch's
     // arguments when it covers one channel, else from the tile table)
+    // Odd steps run the tiles in the opposite order.  The state is larger than
+    // the memory-side cache, and each step reads what the one before wrote; run
+    // backwards, a step starts on the lines written last, which are the ones
+    // still in that cache.  (Graph replays start at even steps: the parity of
+    // the launch's step is the parity of the step.)
     StepArgs a = a0;
-    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int tx = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int tile = (a0.step & 1u) ? (int)gridDim.x - 1 - tx : tx;
     int c0;
     if (a0.c_first >= 0) {
         c0 = a0.c_first + tile * TC;
