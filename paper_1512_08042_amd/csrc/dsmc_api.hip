@@ -361,6 +361,9 @@ struct dsmc_ctx {
     // classify pass completes it (it reads every particle anyway); any other
     // call that reads particles or cell starts settles it first with a copy.
     bool pending;
+    // the step kernels read the state with non-temporal loads (a state buffer
+    // of the nominal particle count below 384 MB, 1.5 x the memory-side cache)
+    bool nt_loads;
     hipStream_t last;
     bool prof;
     std::vector<ProfRec> recs;
@@ -532,10 +535,14 @@ void launch_tiles(const dsmc_ctx *x, int kind, bool move, hipStream_t s, const S
     do {                                                        \
         if (kind == 0)                                          \
             k_classify<TC, CH, S><<<n, 64, 0, s>>>(a);          \
+        else if (x->nt_loads && move)                           \
+            k_step<TC, CH, true, S, true><<<n, 64, 0, s>>>(a);  \
+        else if (x->nt_loads)                                   \
+            k_step<TC, CH, false, S, true><<<n, 64, 0, s>>>(a); \
         else if (move)                                          \
-            k_step<TC, CH, true, S><<<n, 64, 0, s>>>(a);        \
+            k_step<TC, CH, true, S, false><<<n, 64, 0, s>>>(a); \
         else                                                    \
-            k_step<TC, CH, false, S><<<n, 64, 0, s>>>(a);       \
+            k_step<TC, CH, false, S, false><<<n, 64, 0, s>>>(a); \
     } while (0)
         if (state32(x->cfg)) {
             if (g.tc == 4 && g.ch == 8)
@@ -866,6 +873,11 @@ int init_ctx(const dsmc_config *cfg, const dsmc_replica *reps, int32_t nrep, con
     x->reseed_events = 0;
     x->classified = false;
     x->pending = false;
+    {
+        const int64_t nominal = mode == 1 ? n_load : npart;
+        const int64_t bytes = nominal * 5 * (cfg->state_bits == 32 ? 4 : 8);
+        x->nt_loads = bytes <= ((int64_t)384 << 20);
+    }
     x->prof = false;
     x->last = s;
     x->capturing = false;

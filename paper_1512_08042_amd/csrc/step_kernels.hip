@@ -545,7 +545,7 @@ __device__ __forceinline__ void tile_group_offsets(const StepArgs &a, TileLds<TC
 //     and partitioned in place.
 // STAGED tiles (at most 64*CH particles) are staged in LDS; larger ones run
 // the same steps on the tile's destination range in global memory.
-template <int TC, int CH, class S, bool GATHER, bool MOVE, bool STAGED>
+template <int TC, int CH, class S, bool GATHER, bool MOVE, bool STAGED, bool NT>
 __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int ntc, int nt, int n_old, bool own_ntc,
                           double &nbar, double &sig, double &rem, bool mown, double mprev, double *mdst,
                           unsigned long long &ncoll, unsigned long long &ncand, int &walls, bool &limit)
@@ -599,8 +599,13 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
             }
             g_ok[b] = src >= 0;
 #pragma unroll
-            for (int k = 0; k < 5; ++k)
-                g[b][k] = src >= 0 ? (old ? a.template old_in<S>(k) : a.template in<S>(k))[src] : (S)0;
+            for (int k = 0; k < 5; ++k) {
+                const S *p = &(old ? a.template old_in<S>(k) : a.template in<S>(k))[src];
+                if constexpr (NT)
+                    g[b][k] = src >= 0 ? __builtin_nontemporal_load(p) : (S)0;
+                else
+                    g[b][k] = src >= 0 ? *p : (S)0;
+            }
         }
 #pragma unroll
         for (int b = 0; b < CH; ++b) {
@@ -776,7 +781,8 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return x * q + min(x, r) + i;
 }
 
-template <int TC, int CH, class S, bool GATHER, bool MOVE>
+// NT: the gather reads the state with non-temporal loads (see k_step)
+template <int TC, int CH, class S, bool GATHER, bool MOVE, bool NT>
 __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
 {
     static_assert(TC == 1 || TC == 2 || TC == 4, "tile sizes with teams of >= 16 lanes");
@@ -868,10 +874,10 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     int walls = 0;
     bool limit = false;
     if (nt <= TileLds<TC, CH, S>::CAP)
-        tile_body<TC, CH, S, GATHER, MOVE, true>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev, mdst,
+        tile_body<TC, CH, S, GATHER, MOVE, true, NT>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev, mdst,
                                               ncoll, ncand, walls, limit);
     else
-        tile_body<TC, CH, S, GATHER, MOVE, false>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev,
+        tile_body<TC, CH, S, GATHER, MOVE, false, NT>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev,
                                                mdst, ncoll, ncand, walls, limit);
 
     // the tile's running counters.  Every tile owns its entry; the add is an
@@ -887,22 +893,31 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
 template <int TC, int CH, class S>
 __global__ __launch_bounds__(64) void k_classify(StepArgs a)
 {
-    tile_kernel<TC, CH, S, false, true>(a);
+    tile_kernel<TC, CH, S, false, true, true>(a);  // whole cells, read once: non-temporal
 }
 
 // four waves per SIMD: the tile fits 128 VGPRs (a few spills in the cold
 // wall path) and about 9.4 KB of LDS (FP64, 2 cells x 4 chunks), so 16 tiles
 // share a CU; measured 8 % faster than three waves with no spills
-template <int TC, int CH, bool MOVE, class S>
+//
+// NT (chosen on the host): the state read by the gather is dead once read,
+// and the state written is what the next step reads.  When a buffer is not
+// much larger than the 256 MB memory-side cache, non-temporal loads leave
+// the written state there for the next step (measured: +4 % at 0.3 GB); at
+// twice its size and more, the L2 reuse of the lines that neighbouring tiles
+// share matters more and plain loads win (-1.5 % with NT at 0.5 GB).
+template <int TC, int CH, bool MOVE, class S, bool NT>
 __global__ __launch_bounds__(64, 4) void k_step(StepArgs a)
 {
-    tile_kernel<TC, CH, S, true, MOVE>(a);
+    tile_kernel<TC, CH, S, true, MOVE, NT>(a);
 }
 
 #define DSMC_TILE_INSTANCES(TC, CH, S)                              \
     template __global__ void k_classify<TC, CH, S>(StepArgs);       \
-    template __global__ void k_step<TC, CH, true, S>(StepArgs);     \
-    template __global__ void k_step<TC, CH, false, S>(StepArgs);
+    template __global__ void k_step<TC, CH, true, S, false>(StepArgs);  \
+    template __global__ void k_step<TC, CH, false, S, false>(StepArgs); \
+    template __global__ void k_step<TC, CH, true, S, true>(StepArgs);   \
+    template __global__ void k_step<TC, CH, false, S, true>(StepArgs);
 DSMC_TILE_INSTANCES(4, 4, double)
 DSMC_TILE_INSTANCES(2, 4, double)
 DSMC_TILE_INSTANCES(1, 4, double)

@@ -321,7 +321,7 @@ struct ProjectAdjArgs {
 // LDS; S is the stored particle type (double, or float with FP64 arithmetic)
 template <int TC, int CH, class S>
 __global__ void k_classify(StepArgs a);
-template <int TC, int CH, bool MOVE, class S>
+template <int TC, int CH, bool MOVE, class S, bool NT>
 __global__ void k_step(StepArgs a);
 __global__ void k_cell_count(CellArgs a);
 __global__ void k_scan_blocks(int32_t *blocksum, int nblk, int32_t *cs_out, int ncells, Counters *ctr,
