@@ -224,6 +224,38 @@ def test_reseed_completed_by_the_next_step(q, order, ncol, scale):
         assert ch.cell_start().diff().max().item() > 4 * ppc  # the oversized tiles were exercised
 
 
+@pytest.mark.parametrize("between", ["reseed", "status", "moments"])
+def test_reseed_followed_by_other_calls(between):
+    # what comes between a reseed and the next step: a second reseed (which
+    # completes the first with the copy), a status read (the same), or a read
+    # of the moment sums (which leaves it pending for the step)
+    nx, ny, ppc = 9, 7, 30
+    ch, ref, _ = _pair(nx, ny, ppc, 0.1, seed=12, capacity=nx * ny * ppc * 3)
+    ch.step(2, sample_every=1)
+    ref.step(2, sample_every=1)
+    lat = O.lattice(37)
+    f = inputs.populations(3, lat["w"] * 1.2, nx * ny, 0.03)
+    cells = inputs.strip_cells(nx, ny, 2)
+    ch.map_from_lbm(torch.as_tensor(f, device="cuda"), torch.as_tensor(cells, device="cuda"), 37, 3)
+    assert ref.lb2dsmc(lat, 3, f, cells) == 0
+    if between == "reseed":
+        cells2 = (cells + 4).astype(np.int32)
+        f2 = inputs.populations(8, lat["w"] * 0.9, nx * ny, 0.03)
+        ch.map_from_lbm(torch.as_tensor(f2, device="cuda"), torch.as_tensor(cells2, device="cuda"), 37, 2)
+        assert ref.lb2dsmc(lat, 2, f2, cells2) == 0
+    elif between == "status":
+        assert ch.status()["n"] == ref.counters()["n"]
+    else:
+        got = ch.sample_moments().cpu().numpy()
+        want = ref.averages()
+        scale = np.abs(want).max(axis=1, keepdims=True) + 1.0
+        assert np.all(np.abs(got - want) <= 1e-12 * scale)
+    ch.step(2, sample_every=1)
+    ref.step(2, sample_every=1)
+    _assert_state(ch, ref, what="2 steps after the reseed (%s between)" % between)
+    _assert_counters(ch, ref)
+
+
 def test_rejected_reseed_then_step():
     # a reseed over capacity is rejected on the device: the step that
     # completes it keeps every particle and the cell starts as they were
