@@ -94,9 +94,17 @@ struct TileLds {
     static constexpr int CAP = 64 * CH;
     S v[3][CAP];                   // vx, vy, vz of the tile's particles (stored precision), in new-slot order;
                                    // positions stay in registers of the lane that owns the slot
-    int32_t kr[CAP];               // next-step group (low 6 bits) and rank inside it, per slot
-    double dr[5][NTC_ROUND];       // one round of NTC draws: R, cos(theta), sin(theta), cos(phi), sin(phi)
-    int32_t di[2][NTC_ROUND];      // ... and the candidate pairs (i, j)
+    // arrays of different phases share their space (each phase ends at a
+    // barrier): the raw groups (set-up), the NTC draws (collisions) and the
+    // long jumps' source slots (gather), then the group keys (move to write)
+    union {
+        int32_t kr[CAP];           // next-step group (low 6 bits) and rank inside it, per slot
+        struct {
+            double dr[5][NTC_ROUND];   // one round of NTC draws: R, cos(theta), sin(theta), cos(phi), sin(phi)
+            int32_t di[2][NTC_ROUND];  // ... and the candidate pairs (i, j)
+        };
+        int32_t raw[3][TC * NDIR]; // near groups before ordering: source cell, size, first source slot
+    };
     long long mc[TC];              // NTC candidates of each cell this step
     int32_t csn[TC + 1];           // cell starts of the tile after the sort
     int32_t tix[TC], tiy[TC];      // cell coordinates
@@ -106,7 +114,6 @@ struct TileLds {
     int32_t gsrc[TC][NDIR];        // their first source slots
     int32_t gn[TC][NDIR];          // their sizes
     int32_t gstart[TC][NDIR];      // their first slots inside the cell
-    int32_t raw[3][TC * NDIR];     // near groups before ordering: source cell, size, first source slot
     int32_t rsrc[TC];              // classify after a reseed: first old slot of a kept cell, -1 for a new one
     int32_t run[TC * NGRP];        // sizes of the next step's groups of the tile's cells ...
     int32_t excl[TC * NGRP];       // ... and their offsets inside each cell
@@ -607,14 +614,19 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
                     g[b][k] = src >= 0 ? *p : (S)0;
             }
         }
+        // every slot of the tile is staged: a slot that no near group fills
+        // holds zeros until a long jump fills it (or stays so when the long
+        // jumps overflowed their list, which the status reports), and its
+        // long-jump source slot is marked absent
 #pragma unroll
         for (int b = 0; b < CH; ++b) {
             const int i = 64 * b + lane;
             xr[b] = g[b][0];
             yr[b] = g[b][1];
-            if (i < nt && g_ok[b]) {
+            if (i < nt) {
 #pragma unroll
                 for (int k = 2; k < 5; ++k) L.v[k - 2][i] = g[b][k];
+                if (GATHER && !g_ok[b]) L.kr[i] = -1;
             }
         }
         if (GATHER && L.anyfar) {
@@ -626,9 +638,11 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
             for (int b = 0; b < CH; ++b) {
                 const int i = 64 * b + lane;
                 if (i < nt && !g_ok[b]) {
-                    const int q = L.kr[i];
-                    xr[b] = a.template in<S>(0)[q];
-                    yr[b] = a.template in<S>(1)[q];
+                    const int q = L.kr[i];  // in [0, n_old) when written (tile_far_gather checks)
+                    if (q >= 0) {
+                        xr[b] = a.template in<S>(0)[q];
+                        yr[b] = a.template in<S>(1)[q];
+                    }
                 }
             }
         }
