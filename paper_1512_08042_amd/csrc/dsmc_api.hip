@@ -338,6 +338,12 @@ struct dsmc_ctx {
         int rep;  // the group's one channel, or -1 when it spans several
     };
     std::vector<TileGroup> groups;
+    // batches: the tile groups after the first run on side streams forked
+    // from the caller's stream and joined back into it (one launch's tail
+    // overlaps the next group's work); default priority, created at init
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
+    bool forked = false;  // side streams and events exist
     std::vector<int32_t> tiles_host;
     int particles_per_tile;
     // a captured step graph: nsteps steps (a dsmc_step call) replayable from
@@ -520,10 +526,20 @@ int set_tiling(dsmc_ctx *x, int ppt, hipStream_t s)
 }
 
 // the launches of one pass of the tile kernels, one per tile group: kind 0
-// = k_classify, 1 = k_step
-void launch_tiles(const dsmc_ctx *x, int kind, bool move, hipStream_t s, const StepArgs &a0)
+// = k_classify, 1 = k_step.  The groups touch disjoint cells; with side
+// streams the second and later groups run beside the first.
+int launch_tiles(const dsmc_ctx *x, int kind, bool move, hipStream_t s, const StepArgs &a0)
 {
-    for (const dsmc_ctx::TileGroup &g : x->groups) {
+    const int ng = (int)x->groups.size();
+    const bool fork = x->forked && ng > 1 && ng <= 4;
+    if (fork && hipEventRecord(x->ev_fork, s) != hipSuccess) return DSMC_EHIP;
+    for (int gi = 0; gi < ng; ++gi) {
+        const dsmc_ctx::TileGroup &g = x->groups[(size_t)gi];
+        hipStream_t gs = s;
+        if (fork && gi > 0) {
+            gs = x->side[gi - 1];
+            if (hipStreamWaitEvent(gs, x->ev_fork, 0) != hipSuccess) return DSMC_EHIP;
+        }
         StepArgs a = a0;
         a.tiles = x->tiles + 2 * (size_t)g.tile0;
         if (g.rep >= 0) {  // one channel: tiles follow from the block index
@@ -531,18 +547,18 @@ void launch_tiles(const dsmc_ctx *x, int kind, bool move, hipStream_t s, const S
             a.c_first = x->reps[g.rep].cbase;
         }
         const unsigned n = (unsigned)g.ntiles;
-#define DSMC_LAUNCH(TC, CH, S)                                  \
-    do {                                                        \
-        if (kind == 0)                                          \
-            k_classify<TC, CH, S><<<n, 64, 0, s>>>(a);          \
-        else if (x->nt_loads && move)                           \
-            k_step<TC, CH, true, S, true><<<n, 64, 0, s>>>(a);  \
-        else if (x->nt_loads)                                   \
-            k_step<TC, CH, false, S, true><<<n, 64, 0, s>>>(a); \
-        else if (move)                                          \
-            k_step<TC, CH, true, S, false><<<n, 64, 0, s>>>(a); \
-        else                                                    \
-            k_step<TC, CH, false, S, false><<<n, 64, 0, s>>>(a); \
+#define DSMC_LAUNCH(TC, CH, S)                                   \
+    do {                                                         \
+        if (kind == 0)                                           \
+            k_classify<TC, CH, S><<<n, 64, 0, gs>>>(a);          \
+        else if (x->nt_loads && move)                            \
+            k_step<TC, CH, true, S, true><<<n, 64, 0, gs>>>(a);  \
+        else if (x->nt_loads)                                    \
+            k_step<TC, CH, false, S, true><<<n, 64, 0, gs>>>(a); \
+        else if (move)                                           \
+            k_step<TC, CH, true, S, false><<<n, 64, 0, gs>>>(a); \
+        else                                                     \
+            k_step<TC, CH, false, S, false><<<n, 64, 0, gs>>>(a); \
     } while (0)
         if (state32(x->cfg)) {
             if (g.tc == 4 && g.ch == 8)
@@ -564,7 +580,36 @@ void launch_tiles(const dsmc_ctx *x, int kind, bool move, hipStream_t s, const S
                 DSMC_LAUNCH(1, 8, double);
         }
 #undef DSMC_LAUNCH
+        if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
+        if (gs != s) {  // join the side stream back into the caller's
+            if (hipEventRecord(x->ev_join[gi - 1], gs) != hipSuccess) return DSMC_EHIP;
+            if (hipStreamWaitEvent(s, x->ev_join[gi - 1], 0) != hipSuccess) return DSMC_EHIP;
+        }
     }
+    return DSMC_OK;
+}
+
+// side streams and their events for a batch's tile groups (see dsmc_ctx)
+int make_side_streams(dsmc_ctx *x)
+{
+    for (int k = 0; k < 3; ++k) {
+        if (hipStreamCreateWithFlags(&x->side[k], hipStreamNonBlocking) != hipSuccess) return DSMC_EHIP;
+        if (hipEventCreateWithFlags(&x->ev_join[k], hipEventDisableTiming) != hipSuccess) return DSMC_EHIP;
+    }
+    if (hipEventCreateWithFlags(&x->ev_fork, hipEventDisableTiming) != hipSuccess) return DSMC_EHIP;
+    x->forked = true;
+    return DSMC_OK;
+}
+
+// releases what a context owns on the device side and the context itself
+void release_ctx(dsmc_ctx *x)
+{
+    for (int k = 0; k < 3; ++k) {
+        if (x->side[k]) (void)hipStreamDestroy(x->side[k]);
+        if (x->ev_join[k]) (void)hipEventDestroy(x->ev_join[k]);
+    }
+    if (x->ev_fork) (void)hipEventDestroy(x->ev_fork);
+    delete x;
 }
 
 int fill_f64(double *p, size_t n, double v, hipStream_t s)
@@ -892,6 +937,7 @@ int init_ctx(const dsmc_config *cfg, const dsmc_replica *reps, int32_t nrep, con
         hipStreamSynchronize(s) != hipSuccess)
         rc = DSMC_EHIP;
     if (rc == DSMC_OK) rc = set_tiling(x, 0, s);
+    if (rc == DSMC_OK && nrep > 1) rc = make_side_streams(x);
     if (rc == DSMC_OK) {
         k_zero_counters<<<1, 64, 0, s>>>(x->ctr);
         if (hipGetLastError() != hipSuccess) rc = DSMC_EHIP;
@@ -969,7 +1015,7 @@ int init_ctx(const dsmc_config *cfg, const dsmc_replica *reps, int32_t nrep, con
         }
     }
     if (rc != DSMC_OK) {
-        delete x;
+        release_ctx(x);
         return rc;
     }
     *out = x;
@@ -1127,6 +1173,7 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
     hipStream_t s = S(stream);
     x->last = s;
     const int nc = x->ncells;
+    int rc_tiles = DSMC_OK;
     if (nsteps > 0 && !x->classified) {
         // moves of the coming step for a state set or changed from outside
         const int p = (int)(x->step & 1);
@@ -1136,15 +1183,16 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
             StepArgs a = step_args(x, 1 - x->cur, x->step, false, true);
             a.reseed = 1;
             TRY(launch(x, DSMC_K_CLASSIFY, s, [&] {
-                launch_tiles(x, 0, true, s, a);
+                rc_tiles = launch_tiles(x, 0, true, s, a);
                 k_reseed_done<<<1, 64, 0, s>>>(x->ctr);
             }));
             x->cur = 1 - x->cur;
             x->pending = false;
         } else {
             const StepArgs a = step_args(x, x->cur, x->step, false, true);
-            TRY(launch(x, DSMC_K_CLASSIFY, s, [&] { launch_tiles(x, 0, true, s, a); }));
+            TRY(launch(x, DSMC_K_CLASSIFY, s, [&] { rc_tiles = launch_tiles(x, 0, true, s, a); }));
         }
+        TRY(rc_tiles);
         x->classified = true;
     }
     for (int32_t it = 0; it < nsteps; ++it) {
@@ -1166,7 +1214,8 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
         const bool sample = sample_every > 0 && ((x->step + 1) % sample_every) == 0;
         const bool move = it + 1 < nsteps;  // the call's last step leaves the state settled
         const StepArgs a = step_args(x, cur, x->step, sample, false);
-        TRY(launch(x, DSMC_K_STEP, s, [&] { launch_tiles(x, 1, move, s, a); }));
+        TRY(launch(x, DSMC_K_STEP, s, [&] { rc_tiles = launch_tiles(x, 1, move, s, a); }));
+        TRY(rc_tiles);
         x->cur = nxt;
         if (sample) x->nsamples += 1;
         x->step += 1;
@@ -1633,7 +1682,7 @@ void dsmc_destroy(dsmc_ctx *x)
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : x->pool) (void)hipEventDestroy(e);
-    delete x;
+    release_ctx(x);
 }
 
 }  // extern "C"

@@ -151,6 +151,13 @@ def test_long_jump_overflow_is_reported():
     ch, _, _ = _pair(nx, ny, 20, 0.5, dt=2.0, particles=p, capacity=2000, far_capacity=4)
     ch.step(1)
     assert ch.status()["bits"] & 0x2
+    # the long jumps that did not fit the list leave zeros in their slots, and
+    # the state stays inside the channel (so further steps stay in bounds)
+    for _ in range(2):
+        x, y = (t.cpu().numpy() for t in ch.particles()[:2])
+        assert np.isfinite(x).all() and np.isfinite(y).all()
+        assert (x >= 0).all() and (x <= nx).all() and (y >= 0).all() and (y <= ny).all()
+        ch.step(1)
 
 
 @pytest.mark.parametrize("q,order", [(9, 2), (9, 3), (37, 3), (37, 0), (37, 1)])
