@@ -1656,12 +1656,15 @@ int dsmc_graph_launch(dsmc_ctx *x, void *stream)
 {
     if (!x) return DSMC_EINVAL;
     if (!x->gexec) return DSMC_ESTATE;
-    TRY(settle(x, S(stream)));
-    // the captured parities and sampling pattern must hold from this step
-    if ((x->step & 1) || x->cur != x->g_cur) return DSMC_ESTATE;
+    // the captured parities and sampling pattern must hold from this step (a
+    // pending reseed, completed first, moves the state to the other buffer);
+    // checked before anything is enqueued
+    const int cur = x->pending ? 1 - x->cur : x->cur;
+    if ((x->step & 1) || cur != x->g_cur) return DSMC_ESTATE;
     if (x->g_sample_every > 0 && x->step % x->g_sample_every != 0) return DSMC_ESTATE;
     if (x->step + x->g_nsteps > (int64_t)0xFFFFFFFF) return DSMC_ESTATE;
     hipStream_t s = S(stream);
+    TRY(settle(x, s));
     x->last = s;
     k_set_step_base<<<1, 64, 0, s>>>(x->ctr, (uint32_t)x->step);
     if (hipGetLastError() != hipSuccess) return DSMC_EHIP;

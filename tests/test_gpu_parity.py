@@ -263,6 +263,39 @@ def test_reseed_followed_by_other_calls(between):
     _assert_counters(ch, ref)
 
 
+def test_reseed_then_step_graph():
+    # a graph captured right after a reseed starts from the completed state;
+    # a replay whose buffer parity would not match is refused before it
+    # changes anything, and an eager step then completes the second reseed
+    nx, ny, ppc = 8, 6, 30
+    ch, ref, _ = _pair(nx, ny, ppc, 0.1, seed=6, capacity=nx * ny * ppc * 3)
+    ch.step(2, sample_every=1)
+    ref.step(2, sample_every=1)
+    lat = O.lattice(9)
+    cells = inputs.strip_cells(nx, ny, 2)
+    s = torch.cuda.Stream()
+    f = torch.as_tensor(inputs.populations(11, lat["w"], nx * ny, 0.03), device="cuda")
+    ch.map_from_lbm(f, torch.as_tensor(cells, device="cuda"), 9, 2, stream=s)
+    assert ref.lb2dsmc(lat, 2, f.cpu().numpy(), cells) == 0
+    ch.graph_create(4, sample_every=1, stream=s)
+    for _ in range(2):
+        ch.graph_launch(stream=s)
+        ref.step(4, sample_every=1)
+    s.synchronize()
+    _assert_state(ch, ref, what="two replays after a reseed")
+    _assert_counters(ch, ref)
+    f2 = torch.as_tensor(inputs.populations(12, lat["w"] * 1.1, nx * ny, 0.03), device="cuda")
+    ch.map_from_lbm(f2, torch.as_tensor(cells, device="cuda"), 9, 2, stream=s)
+    assert ref.lb2dsmc(lat, 2, f2.cpu().numpy(), cells) == 0
+    with pytest.raises(RuntimeError):
+        ch.graph_launch(stream=s)  # the completed reseed would leave the other buffer current
+    ch.step(2, sample_every=1, stream=s)
+    ref.step(2, sample_every=1)
+    s.synchronize()
+    _assert_state(ch, ref, what="an eager step after the refused replay")
+    _assert_counters(ch, ref)
+
+
 def test_rejected_reseed_then_step():
     # a reseed over capacity is rejected on the device: the step that
     # completes it keeps every particle and the cell starts as they were
