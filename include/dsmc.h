@@ -380,13 +380,17 @@ int dsmc_replica_counters(dsmc_ctx *ctx, uint64_t *out, void *stream);
 /* Step graphs: dsmc_graph_create captures one dsmc_step(ctx, nsteps,
  * sample_every) call (nsteps even, a multiple of sample_every when that is
  * > 0) into a HIP graph on `stream`, which must be a created stream (not
- * the null stream); nothing runs and the context is unchanged.  Each
- * dsmc_graph_launch replays it on `stream` exactly as that dsmc_step call
- * would run from the current step: the step index comes from device memory,
- * set by one small kernel before the replay.  A replay needs the current
- * step even, aligned with sample_every, and the same current buffer as at
- * capture (DSMC_ESTATE otherwise).  Creating a graph replaces the previous
+ * the null stream); nothing of the step runs and the context is unchanged
+ * (a pending reseed is completed first).  Each dsmc_graph_launch replays it
+ * on `stream` exactly as that dsmc_step call would run from the current
+ * step: the step index comes from device memory, set by one small kernel
+ * before the replay.  A replay needs the current step even, aligned with
+ * sample_every, and the same current buffer as at capture, counting the
+ * buffer switch of completing a pending reseed (DSMC_ESTATE otherwise,
+ * before anything is enqueued).  Creating a graph replaces the previous
  * one; dsmc_destroy releases it.  Kernel profiling does not time replays.
+ * Batches run their tile groups on side streams forked from `stream`; the
+ * fork and join are captured with them.
  * Errors: DSMC_EINVAL, DSMC_ESTATE, DSMC_EHIP. */
 int dsmc_graph_create(dsmc_ctx *ctx, int32_t nsteps, int32_t sample_every, void *stream);
 int dsmc_graph_launch(dsmc_ctx *ctx, void *stream);
