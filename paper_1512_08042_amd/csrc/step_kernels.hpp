@@ -356,7 +356,7 @@ template <class S>
 __global__ void k_reseed_copy(ReseedArgs a);
 template <class S>
 __global__ void k_reseed_gen(ReseedArgs a);
-__global__ void k_reseed_unmark(ReseedArgs a);
+__global__ void k_reseed_done(Counters *ctr);
 // lattice step (YM: y_mode 0 periodic, 1 buffer rows, 2 diffuse walls) and
 // its adjoint (YB: y_mode 1) for Q velocities;
 // NARROW: the grid is narrower than the largest velocity component
