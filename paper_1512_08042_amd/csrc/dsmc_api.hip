@@ -1206,6 +1206,8 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
         c.rep = x->rep;
         c.cell_rep = x->cell_rep;
         c.ncells = nc;
+        c.nx1 = x->nrep == 1 ? x->reps[0].G.nx : 0;
+        c.ny1 = x->nrep == 1 ? x->reps[0].G.ny : 0;
         TRY(launch(x, DSMC_K_CELL_COUNT, s, [&] { k_cell_count<<<x->nblk, 256, 0, s>>>(c); }));
         TRY(launch(x, DSMC_K_CELL_FINAL, s, [&] {
             k_cell_final<<<x->nblk, 256, 0, s>>>(x->countnew, nc, x->blocksum, x->cs[nxt], x->ctr, p ^ 1);

@@ -949,8 +949,13 @@ __global__ __launch_bounds__(256) void k_cell_count(CellArgs a)
     const int c = blockIdx.x * 256 + threadIdx.x;
     int total = 0;
     if (c < a.ncells) {
-        const RepConst &R = a.rep[a.cell_rep[c]];
-        const int nx = R.G.nx, ny = R.G.ny, cb = R.cbase;
+        int nx = a.nx1, ny = a.ny1, cb = 0;
+        if (nx <= 0) {  // a batch: the cell's channel
+            const RepConst &R = a.rep[a.cell_rep[c]];
+            nx = R.G.nx;
+            ny = R.G.ny;
+            cb = R.cbase;
+        }
         const int cix = (c - cb) % nx, ciy = (c - cb) / nx;
 #pragma unroll
         for (int d = 0; d < NDIR; ++d) {

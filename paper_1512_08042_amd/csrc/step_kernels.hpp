@@ -153,6 +153,7 @@ struct CellArgs {
     const RepConst *rep;     // the channels
     const int32_t *cell_rep; // [ncells] channel of every cell
     int ncells;
+    int nx1, ny1;            // > 0: one channel of nx1 x ny1 cells (rep and cell_rep are not read)
 };
 
 // the initial Maxwellian of one channel: its cells start at cs, nbar, ...
