@@ -167,7 +167,7 @@ __device__ __forceinline__ void lbm_adj_node(const LbmAdjArgs &a, int node, doub
 // (added when a.accumulate, else written): one writer per slot, so the sums
 // do not depend on scheduling.
 template <int Q, bool YB, bool NARROW>
-__global__ __launch_bounds__(256) void k_lbm_adjoint(LbmAdjArgs a)
+__global__ __launch_bounds__(256, 4) void k_lbm_adjoint(LbmAdjArgs a)
 {
     __shared__ double sh[4];
     const int node = blockIdx.x * 256 + threadIdx.x;

@@ -516,7 +516,7 @@ __device__ __forceinline__ void lbm_node(const LbmArgs &a, int node)
 }
 
 template <int Q, int YM, bool NARROW>
-__global__ __launch_bounds__(256) void k_lbm(LbmArgs a)
+__global__ __launch_bounds__(256, 4) void k_lbm(LbmArgs a)
 {
     const int node = blockIdx.x * 256 + threadIdx.x;
     if (node >= a.nx * a.ny) return;
