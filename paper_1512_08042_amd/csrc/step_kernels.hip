@@ -904,11 +904,12 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     if (MOVE && ballot64(limit) != 0 && lane == 0) atomicOr(&a.K().ctr->status, ST_WALL_LIMIT);
 }
 
-// five waves per SIMD: without the collisions and the sampling the tile fits
-// 96 VGPRs (a few spills in the cold wall path), and the FP64 2 x 4 tile
-// takes exactly 8 KB of LDS, so 20 tiles share a CU
+// tiles of four chunks at five waves per SIMD: without the collisions and
+// the sampling they fit 96 VGPRs (a few spills in the cold wall path), and
+// the FP64 2 x 4 tile takes exactly 8 KB of LDS, so 20 tiles share a CU;
+// eight-chunk tiles would spill in the move and stay at four
 template <int TC, int CH, class S>
-__global__ __launch_bounds__(64, 5) void k_classify(StepArgs a)
+__global__ __launch_bounds__(64, CH == 4 ? 5 : 4) void k_classify(StepArgs a)
 {
     tile_kernel<TC, CH, S, false, true, true>(a);  // whole cells, read once: non-temporal
 }
