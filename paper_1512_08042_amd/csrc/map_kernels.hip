@@ -162,41 +162,52 @@ __device__ __forceinline__ double grad_G(const double *p, double x, double y)
 __global__ __launch_bounds__(256) void k_reseed_prep(ReseedArgs a)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= a.nsel) return;
-    const int c = a.cells[i];
-    a.nnew[i] = 0;
-    if (c < 0 || c >= a.ncells) {
-        atomicOr(&a.ctr->reseed_err, ST_BAD_CELL);
-        return;
+    unsigned long long add_new = 0, add_removed = 0;
+    if (i < a.nsel) {
+        const int c = a.cells[i];
+        a.nnew[i] = 0;
+        bool ok = true;
+        if (c < 0 || c >= a.ncells) {
+            atomicOr(&a.ctr->reseed_err, ST_BAD_CELL);
+            ok = false;
+        } else if (atomicCAS(&a.mark[c], 0, i + 1) != 0) {
+            atomicOr(&a.ctr->reseed_err, ST_BAD_CELL);
+            ok = false;
+        }
+        if (ok) {
+            double *pr = a.prm + (size_t)i * 12;
+            if (a.L.Q == 9)
+                grad_params<9>(a.f + c, (size_t)a.ncells, a.L, a.order, pr);
+            else
+                grad_params<37>(a.f + c, (size_t)a.ncells, a.L, a.order, pr);
+            const U4 r = draw(a.k0, a.k1, 0u, (uint32_t)c, a.event, TAG_RESEED_N, 0u);
+            const double target = pr[0] * (double)a.ppc + u53(r.x, r.y);
+            bool finite = true;
+            for (int k = 0; k < 12; ++k)
+                if (!isfinite(pr[k])) finite = false;
+            int nn = 0;
+            if (!finite) {
+                atomicOr(&a.ctr->status, ST_NONFINITE);
+                nn = 0;
+            } else if (target >= 16777215.0) {
+                atomicOr(&a.ctr->status, ST_NNEW_LIMIT);
+                nn = 16777215;
+            } else if (target >= 1.0) {
+                nn = (int)floor(target);
+            }
+            if (!(pr[0] > 0.0)) nn = 0;
+            a.nnew[i] = nn;
+            add_new = (unsigned long long)nn;
+            add_removed = (unsigned long long)(a.cs_old[c + 1] - a.cs_old[c]);
+        }
     }
-    if (atomicCAS(&a.mark[c], 0, i + 1) != 0) {
-        atomicOr(&a.ctr->reseed_err, ST_BAD_CELL);
-        return;
+    // the reseed's totals: one add per wave (adds to one address serialise)
+    add_new = wave_sum_u64(add_new);
+    add_removed = wave_sum_u64(add_removed);
+    if ((threadIdx.x & 63) == 0) {
+        if (add_new) atomicAdd(&a.ctr->reseed_new, add_new);
+        if (add_removed) atomicAdd(&a.ctr->reseed_removed, add_removed);
     }
-    double *pr = a.prm + (size_t)i * 12;
-    if (a.L.Q == 9)
-        grad_params<9>(a.f + c, (size_t)a.ncells, a.L, a.order, pr);
-    else
-        grad_params<37>(a.f + c, (size_t)a.ncells, a.L, a.order, pr);
-    const U4 r = draw(a.k0, a.k1, 0u, (uint32_t)c, a.event, TAG_RESEED_N, 0u);
-    const double target = pr[0] * (double)a.ppc + u53(r.x, r.y);
-    bool finite = true;
-    for (int k = 0; k < 12; ++k)
-        if (!isfinite(pr[k])) finite = false;
-    int nn = 0;
-    if (!finite) {
-        atomicOr(&a.ctr->status, ST_NONFINITE);
-        nn = 0;
-    } else if (target >= 16777215.0) {
-        atomicOr(&a.ctr->status, ST_NNEW_LIMIT);
-        nn = 16777215;
-    } else if (target >= 1.0) {
-        nn = (int)floor(target);
-    }
-    if (!(pr[0] > 0.0)) nn = 0;
-    a.nnew[i] = nn;
-    atomicAdd(&a.ctr->reseed_new, (unsigned long long)nn);
-    atomicAdd(&a.ctr->reseed_removed, (unsigned long long)(a.cs_old[c + 1] - a.cs_old[c]));
 }
 
 // per-cell particle counts after the reseed, and their block sums
