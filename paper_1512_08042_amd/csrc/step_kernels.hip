@@ -614,6 +614,7 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
                     g[b][k] = src >= 0 ? *p : (S)0;
             }
         }
+        __builtin_amdgcn_s_setprio(0);  // the gather is issued
         // every slot of the tile is staged: a slot that no near group fills
         // holds zeros until a long jump fills it (or stays so when the long
         // jumps overflowed their list, which the status reports), and its
@@ -838,6 +839,10 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     const bool rerr = rs && ((const __attribute__((address_space(4))) Counters *)a.K().ctr)->reseed_err != 0u;
     const int32_t *const cs_old = a.K().cs[1 - a.cur];
 
+    // The waves of a SIMD take turns by priority: a tile up to the issue of
+    // its gather runs at a raised one, so that the two load rounds the tile
+    // waits on leave as early as possible.
+    __builtin_amdgcn_s_setprio(2);
     // set-up: every per-cell quantity of the tile is loaded in one round
     if (lane <= TC) L.csn[lane] = (rerr ? cs_old : a.cs_new())[min(c0 + lane, ce)];
     if (rs && lane < TC) {
