@@ -1370,9 +1370,7 @@ int map_lbm_to_dsmc(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f
     TRY(launch(x, DSMC_K_RESEED, s, [&] {
         if (nsel > 0) k_reseed_prep<<<gsel, 256, 0, s>>>(a);
         k_reseed_count<<<x->nblk, 256, 0, s>>>(a);
-        k_scan_blocks<<<1, 1024, 0, s>>>(x->blocksum, x->nblk, x->cs[nxt], x->ncells, x->ctr, -1);
-        k_block_scan<<<x->nblk, 256, 0, s>>>(x->countnew, x->ncells, x->blocksum, x->cs[nxt]);
-        k_reseed_check<<<1, 64, 0, s>>>(a);
+        k_reseed_starts<<<x->nblk, 256, 0, s>>>(a);
         // the new particles go to buffer nxt; the kept ones follow when the
         // state settles (the next step's classify pass, or settle())
         if (nsel > 0) {

@@ -230,16 +230,32 @@ __global__ __launch_bounds__(256) void k_reseed_count(ReseedArgs a)
     if (threadIdx.x == 0) a.blocksum[blockIdx.x] = lds[0] + lds[1] + lds[2] + lds[3];
 }
 
-// decide whether the reseed goes ahead (single thread)
-__global__ void k_reseed_check(ReseedArgs a)
+// The reseed's new cell starts in one pass: block b adds up the block sums
+// of blocks 0 .. b-1 itself (at most a few hundred integers, exact in any
+// order) and scans its own 256 counts.  The last thread also decides whether
+// the reseed goes ahead, from the 64-bit totals of the listed cells (the
+// 32-bit starts are meaningless when that total is above capacity).
+__global__ __launch_bounds__(256) void k_reseed_starts(ReseedArgs a)
 {
-    if (threadIdx.x != 0) return;
-    Counters *ct = a.ctr;
-    if (ct->reseed_err & ST_BAD_CELL) ct->status |= ST_BAD_CELL;
-    const long long total = (long long)a.cs_old[a.ncells] + (long long)ct->reseed_new - (long long)ct->reseed_removed;
-    if (total > a.capacity) {
-        ct->reseed_err |= ST_CAPACITY;
-        ct->status |= ST_CAPACITY;
+    __shared__ int lds[4];
+    const int b = blockIdx.x;
+    int part = 0;
+    for (int i = threadIdx.x; i < b; i += 256) part += a.blocksum[i];
+    const int off = block_reduce_256(part, lds);
+    const int c = b * 256 + threadIdx.x;
+    const int v = c < a.ncells ? a.countnew[c] : 0;
+    const int ex = block_exscan_256(v, lds);
+    if (c < a.ncells) a.cs_new[c] = off + ex;
+    if (b == (int)gridDim.x - 1 && threadIdx.x == 255) {
+        a.cs_new[a.ncells] = off + ex + v;
+        Counters *ct = a.ctr;
+        if (ct->reseed_err & ST_BAD_CELL) ct->status |= ST_BAD_CELL;
+        const long long total =
+            (long long)a.cs_old[a.ncells] + (long long)ct->reseed_new - (long long)ct->reseed_removed;
+        if (total > a.capacity) {
+            ct->reseed_err |= ST_CAPACITY;
+            ct->status |= ST_CAPACITY;
+        }
     }
 }
 

@@ -352,7 +352,7 @@ __global__ void k_far_reset(Counters *c, int slot);
 __global__ void k_project(ProjectArgs a);
 __global__ void k_reseed_prep(ReseedArgs a);
 __global__ void k_reseed_count(ReseedArgs a);
-__global__ void k_reseed_check(ReseedArgs a);
+__global__ void k_reseed_starts(ReseedArgs a);
 template <class S>
 __global__ void k_reseed_copy(ReseedArgs a);
 template <class S>
