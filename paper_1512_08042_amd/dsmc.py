@@ -106,6 +106,11 @@ class Channel:
         return out
 
     def map_from_lbm(self, f: torch.Tensor, cell_ids: torch.Tensor, lattice_q: int, order: int, stream=None):
+        """LB2DSMC reseed of the listed cells from populations f [Q][ncells]
+        (Table 1).  Only the new particles are written here; the other
+        cells' particles move to their new slots in the next step's first
+        pass, or when the state is read first (views(), particles(),
+        status()), so cell_ids may be freed once this call's work is done."""
         assert f.dtype == torch.float64 and f.is_contiguous() and f.shape == (lattice_q, self.ncells)
         assert cell_ids.dtype == torch.int32 and cell_ids.is_contiguous()
         check(lib().map_lbm_to_dsmc(self._h, int(lattice_q), int(order), _ptr(f), _ptr(cell_ids),
@@ -113,6 +118,8 @@ class Channel:
 
     # ---- inspection ---------------------------------------------------------------
     def views(self) -> _lib.Views:
+        """Current buffer, cell starts and bookkeeping (completes a pending
+        reseed first, on the stream of the last call)."""
         v = _lib.Views()
         check(lib().dsmc_get_views(self._h, ctypes.byref(v)), "dsmc_get_views")
         return v
