@@ -5,6 +5,7 @@ import os
 
 import numpy as np
 import pytest
+from numpy.polynomial import hermite_e
 from scipy import stats
 
 import inputs
@@ -104,18 +105,132 @@ def test_grad_params_at_equilibrium_accept_everything():
     assert stats.kstest(xi[:, 1], "norm").pvalue > 1e-4
 
 
+def _grad_state_sums(rho, u, a2, a3, ppc):
+    """Raw velocity moments (the 11 sampled sums of a cell holding rho ppc
+    particles) of the Grad distribution rho omega(c) G(c), c = xi - u, whose
+    comoving, density-normalised coefficients are a2 = (xx, xy, yy) and
+    a3 = (xxx, xxy, xyy, yyy).  Under omega G the comoving moments are
+    <c_i> = 0, <c_i c_j> = d_ij + a2_ij, <c_i c_j c_k> = a3_ijk (Hermite
+    orthogonality); the raw ones follow from xi = u + c."""
+    ux, uy = u
+    A2 = np.array([[a2[0], a2[1]], [a2[1], a2[2]]])
+    A3 = np.zeros((2, 2, 2))
+    for (i, j, k), v in {(0, 0, 0): a3[0], (0, 0, 1): a3[1], (0, 1, 1): a3[2], (1, 1, 1): a3[3]}.items():
+        for p in {(i, j, k), (i, k, j), (j, i, k), (j, k, i), (k, i, j), (k, j, i)}:
+            A3[p] = v
+    U = np.array([ux, uy])
+    C2 = np.eye(2) + A2                       # <c_i c_j>
+    E2 = C2 + np.outer(U, U)                  # <xi_i xi_j>
+    E3 = np.zeros((2, 2, 2))                  # <xi_i xi_j xi_k>
+    for i in range(2):
+        for j in range(2):
+            for k in range(2):
+                E3[i, j, k] = (A3[i, j, k] + U[i] * C2[j, k] + U[j] * C2[i, k] + U[k] * C2[i, j]
+                               + U[i] * U[j] * U[k])
+    n = rho * ppc
+    return np.array([n, n * ux, n * uy, n * E2[0, 0], n * E2[0, 1], n * E2[1, 1], n * E3[0, 0, 0],
+                     n * E3[0, 0, 1], n * E3[0, 1, 1], n * E3[1, 1, 1], n])
+
+
+def test_grad_params_of_a_shifted_grad_state():
+    # Table 1 step 1 under reading O4: populations of a Grad state of density
+    # 1.7 moving at u = (0.3, -0.2) with known comoving, density-normalised
+    # a2, a3 (projected onto D2Q37, which carries every moment to third
+    # order) give back exactly those a2, a3, u and rho, and M, C of steps 2-3.
+    # An absolute-frame or un-normalised reading fails here.
+    lat = O.lattice(37)
+    rho, u = 1.7, (0.3, -0.2)
+    a2 = (0.05, -0.03, 0.02)
+    a3 = (0.04, -0.015, 0.025, -0.01)
+    sums = _grad_state_sums(rho, u, a2, a3, 100)
+    f = O.dsmc2lb(sums[:, None], 100, lat, 3)[:, 0]
+    prm = O.grad_params(f, lat, 3)
+    assert prm[0] == pytest.approx(rho, rel=1e-13)
+    assert prm[1:3] == pytest.approx(u, rel=1e-12, abs=1e-13)
+    assert prm[3:6] == pytest.approx(a2, rel=1e-11, abs=1e-13)
+    assert prm[6:10] == pytest.approx(a3, rel=1e-11, abs=1e-13)
+    assert prm[10] == pytest.approx(0.05, rel=1e-11)
+    assert prm[11] == pytest.approx(1.0 + 30.0 * 0.05, rel=1e-12)
+    # order 2 keeps a2 and zeroes a3 (so M comes from a2 alone)
+    prm2 = O.grad_params(O.dsmc2lb(sums[:, None], 100, lat, 2)[:, 0], lat, 2)
+    assert prm2[3:6] == pytest.approx(a2, rel=1e-11, abs=1e-13)
+    assert np.all(prm2[6:10] == 0.0)
+
+
+def test_grad_params_shifted_maxwellian_at_density_above_one_is_zero():
+    # a Maxwellian of density 1.7 moving at (0.3, -0.2): in its own frame it
+    # is the equilibrium, so every a2, a3 vanishes and C = 1 (no rejection)
+    lat = O.lattice(37)
+    for rho, ux, uy in ((1.7, 0.3, -0.2), (0.6, -0.25, 0.15)):
+        f = O.dsmc2lb(_maxwellian_averages(np.array([rho]), np.array([ux]), np.array([uy]), 100), 100, lat, 3)
+        prm = O.grad_params(f[:, 0], lat, 3)
+        assert prm[0] == pytest.approx(rho, rel=1e-13)
+        assert prm[1:3] == pytest.approx((ux, uy), rel=1e-12)
+        assert np.allclose(prm[3:10], 0.0, atol=1e-13)
+        assert prm[11] == pytest.approx(1.0, abs=1e-12)
+
+
+def test_grad_params_match_particle_comoving_coefficients():
+    # From a particle set of a non-equilibrium state (density 1.7, mean
+    # velocity (0.3, -0.2), skewed and anisotropic), evaluate the comoving,
+    # density-normalised coefficients on the particles themselves:
+    # a(n) = < H(n)(v - <v>) >, a mean over particles.  Project the particles'
+    # sums onto D2Q37 with the DSMC2LB map and reconstruct: Table 1 step 1
+    # must return the particle values.
+    lat = O.lattice(37)
+    ppc = 100
+    rng = np.random.default_rng(21)
+    n = 170
+    vx = 0.3 + rng.normal(0.0, 1.15, n) + 0.35 * (rng.uniform(-1, 1, n) ** 3)
+    vy = -0.2 + rng.normal(0.0, 0.9, n) + 0.2 * rng.exponential(1.0, n)
+    vz = rng.normal(0.0, 1.0, n)
+    sums = np.array([n, vx.sum(), vy.sum(), (vx * vx).sum(), (vx * vy).sum(), (vy * vy).sum(), (vx ** 3).sum(),
+                     (vx * vx * vy).sum(), (vx * vy * vy).sum(), (vy ** 3).sum(), (vz * vz).sum()])
+    f = O.dsmc2lb(sums[:, None], ppc, lat, 3)[:, 0]
+    prm = O.grad_params(f, lat, 3)
+    cx, cy = vx - vx.mean(), vy - vy.mean()
+    want = {k: np.mean(_he(p, cx) * _he(q, cy)) for k, (p, q) in _TENSOR_PQ.items()}
+    assert prm[0] == pytest.approx(n / ppc, rel=1e-13)
+    assert prm[1] == pytest.approx(vx.mean(), rel=1e-12) and prm[2] == pytest.approx(vy.mean(), rel=1e-12)
+    for k, i in _PRM_INDEX.items():
+        assert prm[i] == pytest.approx(want[k], rel=1e-10, abs=1e-12), k
+    M = max(abs(want[k]) for k in _PRM_INDEX)
+    assert prm[10] == pytest.approx(M, rel=1e-10)
+    assert prm[11] == pytest.approx(1.0 + 30.0 * M, rel=1e-10)
+    # the state really is away from rest, at density != 1 and out of equilibrium
+    assert abs(prm[0] - 1.0) > 0.5 and abs(prm[1]) > 0.1 and M > 0.05
+
+
+def _he(n, x):
+    """Probabilists' Hermite polynomial He_n(x) from numpy's own series
+    evaluation (numpy.polynomial.hermite_e), not a retyped formula."""
+    c = np.zeros(n + 1)
+    c[n] = 1.0
+    return hermite_e.hermeval(x, c)
+
+
+# the 2-D Hermite tensors as products of 1-D He_n: H_{i..} with p x-indices
+# and q y-indices is He_p(x) He_q(y) (the weight factorises)
+_TENSOR_PQ = {"x": (1, 0), "y": (0, 1), "xx": (2, 0), "xy": (1, 1), "yy": (0, 2),
+              "xxx": (3, 0), "xxy": (2, 1), "xyy": (1, 2), "yyy": (0, 3)}
+# multiplicity of each unique component in the full contraction a:H
+_MULT = {"xx": 1, "xy": 2, "yy": 1, "xxx": 1, "xxy": 3, "xyy": 3, "yyy": 1}
+_PRM_INDEX = {"xx": 3, "xy": 4, "yy": 5, "xxx": 6, "xxy": 7, "xyy": 8, "yyy": 9}
+
+
 def _target_moments(prm, lim=9.0, n=1201):
-    """Moments of omega(xi) clip(G, 0, C) by 2-D trapezoid quadrature."""
+    """Moments of omega(xi) clip(G, 0, C) by 2-D trapezoid quadrature, with
+    G = 1 + a2:H2/2! + a3:H3/3! (Eq. (distr_outeq)) assembled from the
+    library Hermite polynomials."""
     g1 = np.linspace(-lim, lim, n)
     X, Y = np.meshgrid(g1, g1, indexing="ij")
-    hxx, hxy, hyy = X * X - 1, X * Y, Y * Y - 1
-    hxxx, hxxy, hxyy, hyyy = X ** 3 - 3 * X, X * X * Y - Y, X * Y * Y - X, Y ** 3 - 3 * Y
-    G = 1 + (prm[3] * hxx + 2 * prm[4] * hxy + prm[5] * hyy) / 2 + \
-        (prm[6] * hxxx + 3 * prm[7] * hxxy + 3 * prm[8] * hxyy + prm[9] * hyyy) / 6
+    H = {k: _he(p, X) * _he(q, Y) for k, (p, q) in _TENSOR_PQ.items()}
+    G = np.ones_like(X)
+    for k, i in _PRM_INDEX.items():
+        G = G + _MULT[k] * prm[i] * H[k] / math.factorial(len(k))
     dens = np.exp(-0.5 * (X * X + Y * Y)) / (2 * np.pi) * np.clip(G, 0.0, prm[11])
     h = g1[1] - g1[0]
     Z = dens.sum() * h * h
-    H = {"xx": hxx, "xy": hxy, "yy": hyy, "xxx": hxxx, "xxy": hxxy, "xyy": hxyy, "yyy": hyyy, "x": X, "y": Y}
     return Z, {k: (dens * v).sum() * h * h / Z for k, v in H.items()}
 
 
@@ -147,8 +262,17 @@ def test_ar_sampler_reproduces_grad_distribution(order):
     se_t = math.sqrt(n * (1 - p)) / p
     assert abs(tries - n / p) < 4.5 * se_t
     # without clipping the moments are the Hermite coefficients themselves
-    assert mom["xx"] == pytest.approx(prm[3], abs=1e-6)
-    assert mom["xxy"] == pytest.approx(prm[7], abs=1e-6)
+    # (orthogonality of the Hermite tensors under omega): every component,
+    # and a zero first moment (a1 = 0 in the comoving frame)
+    assert mom["x"] == pytest.approx(0.0, abs=1e-6) and mom["y"] == pytest.approx(0.0, abs=1e-6)
+    for k, i in _PRM_INDEX.items():
+        assert mom[k] == pytest.approx(prm[i], abs=1e-6), k
+    # the oracle's G agrees with the Hermite-polynomial assembly pointwise
+    pts = np.random.default_rng(11).normal(0.0, 1.5, (50, 2))
+    for x, y in pts:
+        want = 1.0 + sum(_MULT[k] * prm[i] * _he(_TENSOR_PQ[k][0], x) * _he(_TENSOR_PQ[k][1], y)
+                         / math.factorial(len(k)) for k, i in _PRM_INDEX.items())
+        assert O.grad_G(prm, x, y) == pytest.approx(want, rel=1e-13, abs=1e-14)
 
 
 def test_table3_velocity_scale():
