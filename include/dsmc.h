@@ -49,7 +49,9 @@ extern "C" {
 
 /* device status bits (sticky until dsmc_read_status with clear = 1) */
 #define DSMC_ST_WALL_LIMIT 0x1u   /* a particle hit the walls 16 times in one step and was stopped on the wall */
-#define DSMC_ST_FAR_OVERFLOW 0x2u /* more long jumps (> 1 cell) in one step than far_capacity: that step's sort is invalid */
+#define DSMC_ST_FAR_OVERFLOW 0x2u /* more long jumps (> 1 cell) in one step than far_capacity: the next step found
+                                     them by scanning every cell's long-jump group instead of the list (slower;
+                                     results are unchanged) */
 #define DSMC_ST_CAPACITY 0x4u     /* a reseed would exceed capacity: it was skipped, state unchanged */
 #define DSMC_ST_AR_LIMIT 0x8u     /* acceptance-rejection reached ar_max_tries: the last try was kept */
 #define DSMC_ST_NONFINITE 0x10u   /* non-finite populations in a reseeded cell: it received no particles */
@@ -156,7 +158,10 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
  * cumulative averages that feed DSMC2LB, Section 2.1).  Errors: DSMC_EINVAL. */
 int dsmc_step(dsmc_ctx *ctx, int32_t nsteps, int32_t sample_every, void *stream);
 
-/* Write the time averages of the 11 sampled sums per cell to out (device,
+/* The cumulative averages of the DSMC moments that DSMC2LB projects
+ * (Section 2.1: the coupling cells' averaged hydrodynamic variables, scaled
+ * as in the appendix, give the coefficients of the truncated expansion).
+ * Writes the time averages of the 11 sampled sums per cell to out (device,
  * [11][ncells] doubles; may be NULL to only reset): the mean over samples of
  * N, sum vx, sum vy, sum vx^2, sum vx vy, sum vy^2, sum vx^3, sum vx^2 vy,
  * sum vx vy^2, sum vy^3, sum vz^2 (raw velocities).  reset != 0 zeroes the
@@ -388,7 +393,9 @@ int dsmc_replica_counters(dsmc_ctx *ctx, uint64_t *out, void *stream);
  * sample_every, and the same current buffer as at capture, counting the
  * buffer switch of completing a pending reseed (DSMC_ESTATE otherwise,
  * before anything is enqueued).  Creating a graph replaces the previous
- * one; dsmc_destroy releases it.  Kernel profiling does not time replays.
+ * one; dsmc_destroy releases it, and so does a re-tiling (dsmc_set_tiling,
+ * dsmc_autotune: the graph holds the old tile shapes), after which
+ * dsmc_graph_launch returns DSMC_ESTATE until a graph is created again.  Kernel profiling does not time replays.
  * Batches run their tile groups on side streams forked from `stream`; the
  * fork and join are captured with them.
  * Errors: DSMC_EINVAL, DSMC_ESTATE, DSMC_EHIP. */
@@ -421,7 +428,18 @@ int dsmc_profile_enable(dsmc_ctx *ctx, int32_t enable);
 int dsmc_profile_read(dsmc_ctx *ctx, int32_t kernel, double *ms_total, int64_t *launches);
 
 void dsmc_destroy(dsmc_ctx *ctx);
+
+/* Text of a return code (static storage). */
 const char *dsmc_strerror(int code);
+
+/* What the most recent failing call on ctx reported: the call's name, the
+ * reason (the argument or state it rejected, or the HIP runtime's message)
+ * and the code's text.  An empty string when no call on ctx has failed; a
+ * successful call leaves it unchanged.  The text is owned by ctx and valid
+ * until its next failing call or dsmc_destroy.  ctx = NULL gives a static
+ * message.  Errors found on the device are status bits, not messages (see
+ * dsmc_read_status). */
+const char *dsmc_last_error(const dsmc_ctx *ctx);
 
 #ifdef __cplusplus
 }

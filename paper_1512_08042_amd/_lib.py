@@ -24,7 +24,8 @@ EXPORTS = ("dsmc_query_sizes", "dsmc_init", "dsmc_step", "dsmc_sample_moments", 
            "lbm_step_checkpointed", "lbm_adjoint_workspace", "lbm_adjoint_step", "lbm_adjoint",
            "lbm_hermite_moments", "lbm_hermite_moments_adjoint", "dsmc_project_moments_adjoint",
            "dsmc_batch_query_sizes", "dsmc_batch_init", "dsmc_set_tiling", "dsmc_autotune", "dsmc_replica_counters",
-           "dsmc_graph_create", "dsmc_graph_launch", "dsmc_project_equilibrium", "dsmc_hybrid_cycle")
+           "dsmc_graph_create", "dsmc_graph_launch", "dsmc_project_equilibrium", "dsmc_hybrid_cycle",
+           "dsmc_last_error")
 
 
 class Config(ctypes.Structure):
@@ -120,20 +121,26 @@ def lib():
         L.dsmc_destroy.restype = None
         L.dsmc_strerror.argtypes = [ctypes.c_int]
         L.dsmc_strerror.restype = ctypes.c_char_p
+        L.dsmc_last_error.argtypes = [c_p]
+        L.dsmc_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name not in ("dsmc_destroy", "dsmc_strerror"):
+            if name not in ("dsmc_destroy", "dsmc_strerror", "dsmc_last_error"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
 
 
 class DsmcError(RuntimeError):
-    def __init__(self, code, where):
+    def __init__(self, code, where, detail=""):
         self.code = code
+        self.detail = detail
         msg = lib().dsmc_strerror(code).decode()
-        super().__init__("%s failed: %s (%d)" % (where, msg, code))
+        super().__init__("%s failed: %s (%d)%s" % (where, msg, code, ("; " + detail) if detail else ""))
 
 
-def check(rc, where):
+def check(rc, where, ctx=None):
+    """Raise DsmcError for a failing return code; with the call's context,
+    the library's message for it (dsmc_last_error) is attached."""
     if rc != OK:
-        raise DsmcError(rc, where)
+        detail = lib().dsmc_last_error(ctx).decode() if ctx else ""
+        raise DsmcError(rc, where, detail)

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -309,6 +310,16 @@ struct ProfRec {
     hipEvent_t a, b;
 };
 
+// Why the current call failed, set where the failure is found: a static
+// string, or null for a HIP runtime error (whose own message is taken).
+thread_local const char *t_reason = nullptr;
+
+inline int fail(int code, const char *why)
+{
+    t_reason = why;
+    return code;
+}
+
 }  // namespace
 
 struct dsmc_ctx {
@@ -374,11 +385,24 @@ struct dsmc_ctx {
     bool prof;
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
+    char err[320];  // what the last failing call reported (dsmc_last_error)
 };
 
 namespace {
 
 inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+// records a failing call's message in the context (dsmc_last_error)
+int noted(dsmc_ctx *x, const char *call, int rc)
+{
+    if (rc != DSMC_OK && x) {
+        const char *why = t_reason;
+        if (!why) why = rc == DSMC_EHIP ? hipGetErrorString(hipPeekAtLastError()) : "rejected";
+        std::snprintf(x->err, sizeof(x->err), "%s: %s (%s)", call, why, dsmc_strerror(rc));
+    }
+    t_reason = nullptr;
+    return rc;
+}
 
 template <class F>
 int launch(dsmc_ctx *x, int kid, hipStream_t s, F &&f)
@@ -397,7 +421,8 @@ int launch(dsmc_ctx *x, int kid, hipStream_t s, F &&f)
         if (hipEventRecord(e0, s) != hipSuccess) return DSMC_EHIP;
     }
     f();
-    if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DSMC_EHIP, hipGetErrorString(e));
     if (timed) {
         if (hipEventRecord(e1, s) != hipSuccess) return DSMC_EHIP;
         x->recs.push_back(ProfRec{kid, e0, e1});
@@ -476,12 +501,29 @@ void tile_shape(bool f32, int ppc, int ppt, int &tc, int &ch)
     }
 }
 
+// releases a captured step graph, after the work enqueued on the context's
+// last stream (where a replay runs) has finished
+int release_graph(dsmc_ctx *x)
+{
+    if (!x->gexec && !x->graph) return DSMC_OK;
+    if (hipStreamSynchronize(x->last) != hipSuccess) return DSMC_EHIP;
+    if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
+    if (x->graph) (void)hipGraphDestroy(x->graph);
+    x->gexec = nullptr;
+    x->graph = nullptr;
+    x->g_nsteps = 0;
+    return DSMC_OK;
+}
+
 // Builds the tile groups for a target of ppt particles per tile (0: the
 // default, about 200 for FP64 and 400 for FP32 state) and uploads the tile
 // table.  The trajectory does not depend on the tiling (the moment sums only
-// to rounding: their summation order follows the tile shape).
+// to rounding: their summation order follows the tile shape).  A captured
+// step graph bakes in the tile shapes, grids and table offsets, so it is
+// released: a replay would run the old shapes over the new table.
 int set_tiling(dsmc_ctx *x, int ppt, hipStream_t s)
 {
+    if (release_graph(x) != DSMC_OK) return DSMC_EHIP;
     const bool f32 = state32(x->cfg);
     if (ppt <= 0) ppt = f32 ? 400 : 200;
     static const int SHAPES[2][4][2] = {{{4, 4}, {2, 4}, {1, 4}, {1, 8}}, {{4, 8}, {4, 4}, {2, 8}, {1, 8}}};
@@ -844,6 +886,7 @@ int init_ctx(const dsmc_config *cfg, const dsmc_replica *reps, int32_t nrep, con
     dsmc_ctx *x = new (std::nothrow) dsmc_ctx();
     if (!x) return DSMC_EINVAL;
     x->cfg = *cfg;
+    x->err[0] = '\0';
     if (nrep == 1) {  // the channel's own parameters, for the single-channel calls
         x->cfg.nx = reps[0].nx;
         x->cfg.ny = reps[0].ny;
@@ -1063,17 +1106,22 @@ int dsmc_batch_init(const dsmc_config *common, const dsmc_replica *reps, int32_t
     return init_ctx(common, reps, nrep, buf, 0, 0, S(stream), out);
 }
 
-int dsmc_set_tiling(dsmc_ctx *x, int32_t particles_per_tile, void *stream)
+static int dsmc_set_tiling_impl(dsmc_ctx *x, int32_t particles_per_tile, void *stream)
 {
-    if (!x || particles_per_tile < 0 || particles_per_tile > (1 << 20)) return DSMC_EINVAL;
+    if (!x) return DSMC_EINVAL;
+    if (particles_per_tile < 0 || particles_per_tile > (1 << 20))
+        return fail(DSMC_EINVAL, "particles_per_tile must be in [0, 2^20]");
     hipStream_t s = S(stream);
     x->last = s;
     return set_tiling(x, particles_per_tile, s);
 }
 
-int dsmc_autotune(dsmc_ctx *x, int32_t steps_per_trial, int32_t sample_every, dsmc_tuning *out, void *stream)
+static int dsmc_autotune_impl(dsmc_ctx *x, int32_t steps_per_trial, int32_t sample_every, dsmc_tuning *out,
+                              void *stream)
 {
-    if (!x || steps_per_trial < 1 || sample_every < 0) return DSMC_EINVAL;
+    if (!x) return DSMC_EINVAL;
+    if (steps_per_trial < 1 || sample_every < 0)
+        return fail(DSMC_EINVAL, "steps_per_trial must be >= 1 and sample_every >= 0");
     hipStream_t s = S(stream);
     x->last = s;
     const bool f32 = state32(x->cfg);
@@ -1118,9 +1166,10 @@ int dsmc_autotune(dsmc_ctx *x, int32_t steps_per_trial, int32_t sample_every, ds
     return rc;
 }
 
-int dsmc_replica_counters(dsmc_ctx *x, uint64_t *out, void *stream)
+static int dsmc_replica_counters_impl(dsmc_ctx *x, uint64_t *out, void *stream)
 {
-    if (!x || !out) return DSMC_EINVAL;
+    if (!x) return DSMC_EINVAL;
+    if (!out) return fail(DSMC_EINVAL, "out is NULL");
     hipStream_t s = S(stream);
     x->last = s;
     k_replica_stats<<<(unsigned)x->nrep, 256, 0, s>>>(x->tstat, x->rep, x->rstat);
@@ -1167,9 +1216,10 @@ int settle(dsmc_ctx *x, hipStream_t s)
 
 extern "C" {
 
-int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
+static int dsmc_step_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
 {
-    if (!x || nsteps < 0 || sample_every < 0) return DSMC_EINVAL;
+    if (!x) return DSMC_EINVAL;
+    if (nsteps < 0 || sample_every < 0) return fail(DSMC_EINVAL, "nsteps and sample_every must be >= 0");
     hipStream_t s = S(stream);
     x->last = s;
     const int nc = x->ncells;
@@ -1226,13 +1276,13 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
     return DSMC_OK;
 }
 
-int dsmc_sample_moments(dsmc_ctx *x, double *out, int32_t reset, void *stream)
+static int dsmc_sample_moments_impl(dsmc_ctx *x, double *out, int32_t reset, void *stream)
 {
     if (!x) return DSMC_EINVAL;
     hipStream_t s = S(stream);
     x->last = s;
     if (out) {
-        if (x->nsamples <= 0) return DSMC_ESTATE;
+        if (x->nsamples <= 0) return fail(DSMC_ESTATE, "no sample has been taken since the last reset");
         const size_t n = (size_t)NMOM * x->ncells;
         const double Sd = (double)x->nsamples;
         TRY(launch(x, -1, s, [&] { k_average<<<grid_threads(n), 256, 0, s>>>(x->mom, out, n, Sd); }));
@@ -1251,8 +1301,10 @@ static int project(dsmc_ctx *x, const double *mom, double S_, int64_t ncells, in
                    int c_stride = 1, int n_off = 0, int n_stride = 1, int64_t nn_out = -1)
 {
     const Lattice *L = lattice_of(lattice);
-    if (!L || order < 0 || order > 3 || !f_out || !mom || ncells < 1 || ppc < 1 || !(kT > 0.0)) return DSMC_EINVAL;
-    if (equilibrium && order == 3 && lattice == 9) return DSMC_EINVAL;  // D2Q9 does not carry it
+    if (!L || order < 0 || order > 3 || !f_out || !mom || ncells < 1 || ppc < 1 || !(kT > 0.0))
+        return fail(DSMC_EINVAL, "lattice must be 9 or 37, order 0..3, buffers non-NULL, ncells, ppc and kT > 0");
+    if (equilibrium && order == 3 && lattice == 9)  // D2Q9 does not carry it
+        return fail(DSMC_EINVAL, "the third-order equilibrium needs D2Q37");
     ProjectArgs a;
     a.mom = mom;
     a.S = S_;
@@ -1273,14 +1325,15 @@ static int project(dsmc_ctx *x, const double *mom, double S_, int64_t ncells, in
     return launch(x, DSMC_K_PROJECT, s, [&] { k_project<<<grid_threads((size_t)a.n), 256, 0, s>>>(a); });
 }
 
-int map_dsmc_to_lbm(dsmc_ctx *x, int32_t lattice, int32_t order, double *f_out, void *stream)
+static int map_dsmc_to_lbm_impl(dsmc_ctx *x, int32_t lattice, int32_t order, double *f_out, void *stream)
 {
     if (!x) return DSMC_EINVAL;
-    if (x->nrep != 1) return DSMC_ESTATE;  // one channel only
-    if (!lattice_of(lattice) || order < 0 || order > 3 || !f_out) return DSMC_EINVAL;
+    if (x->nrep != 1) return fail(DSMC_ESTATE, "a batch context has no mapping (one channel only)");
+    if (!lattice_of(lattice) || order < 0 || order > 3 || !f_out)
+        return fail(DSMC_EINVAL, "lattice must be 9 or 37, order 0..3 and f_out non-NULL");
     hipStream_t s = S(stream);
     x->last = s;
-    if (x->nsamples <= 0) return DSMC_ESTATE;
+    if (x->nsamples <= 0) return fail(DSMC_ESTATE, "no sample has been taken since the last reset");
     return project(x, x->mom, (double)x->nsamples, x->ncells, x->cfg.ppc, x->cfg.kT_over_m, lattice, order, f_out, s);
 }
 
@@ -1298,17 +1351,21 @@ int dsmc_project_equilibrium(const double *avg, int64_t ncells, int32_t ppc, dou
     return project(nullptr, avg, 1.0, ncells, ppc, kT_over_m, lattice, order, f_out, S(stream), 1);
 }
 
-int dsmc_hybrid_cycle(dsmc_ctx *x, const dsmc_hybrid *h, double *f_lb, double *f_tmp, double *avg_out, void *stream)
+static int dsmc_hybrid_cycle_impl(dsmc_ctx *x, const dsmc_hybrid *h, double *f_lb, double *f_tmp, double *avg_out,
+                                  void *stream)
 {
-    if (!x || !h || !f_lb || !f_tmp) return DSMC_EINVAL;
-    if (x->nrep != 1) return DSMC_ESTATE;  // one channel only
+    if (!x) return DSMC_EINVAL;
+    if (!h || !f_lb || !f_tmp) return fail(DSMC_EINVAL, "h, f_lb and f_tmp must be non-NULL");
+    if (x->nrep != 1) return fail(DSMC_ESTATE, "a batch context has no hybrid cycle (one channel only)");
     LbmArgs la;
-    if (!lbm_args(&h->lbm, la)) return DSMC_EINVAL;
-    if (h->lbm.ny != x->cfg.ny || h->lbm.x_buffer < 1) return DSMC_EINVAL;
-    if (h->dsmc_steps < 1 || h->lbm_steps < 0 || (h->mapping != 0 && h->mapping != 1)) return DSMC_EINVAL;
+    if (!lbm_args(&h->lbm, la)) return fail(DSMC_EINVAL, "invalid lattice configuration");
+    if (h->lbm.ny != x->cfg.ny || h->lbm.x_buffer < 1)
+        return fail(DSMC_EINVAL, "the lattice needs the channel's ny and at least one buffer column");
+    if (h->dsmc_steps < 1 || h->lbm_steps < 0 || (h->mapping != 0 && h->mapping != 1))
+        return fail(DSMC_EINVAL, "dsmc_steps >= 1, lbm_steps >= 0 and mapping 0 or 1 are required");
     if (h->order < 1 || h->order > 3 || (h->mapping == 0 && h->order == 3 && h->lbm.lattice == 9))
-        return DSMC_EINVAL;
-    if (h->dsmc_column < 0 || h->dsmc_column >= x->cfg.nx) return DSMC_EINVAL;
+        return fail(DSMC_EINVAL, "order must be 1..3 (the third-order equilibrium needs D2Q37)");
+    if (h->dsmc_column < 0 || h->dsmc_column >= x->cfg.nx) return fail(DSMC_EINVAL, "dsmc_column outside [0, nx)");
     hipStream_t s = S(stream);
     x->last = s;
     // the DSMC subdomain, sampled every step over the cycle
@@ -1325,14 +1382,15 @@ int dsmc_hybrid_cycle(dsmc_ctx *x, const dsmc_hybrid *h, double *f_lb, double *f
     return lbm_step(&h->lbm, f_lb, f_tmp, h->lbm_steps, stream);
 }
 
-int map_lbm_to_dsmc(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f_in, const int32_t *cell_ids,
-                    int32_t nsel, void *stream)
+static int map_lbm_to_dsmc_impl(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f_in,
+                                const int32_t *cell_ids, int32_t nsel, void *stream)
 {
     if (!x) return DSMC_EINVAL;
-    if (x->nrep != 1) return DSMC_ESTATE;  // one channel only
+    if (x->nrep != 1) return fail(DSMC_ESTATE, "a batch context has no mapping (one channel only)");
     const Lattice *L = lattice_of(lattice);
-    if (!L || (order != 2 && order != 3) || !f_in || nsel < 0 || (nsel > 0 && !cell_ids)) return DSMC_EINVAL;
-    if (nsel > x->ncells) return DSMC_EINVAL;
+    if (!L || (order != 2 && order != 3) || !f_in || nsel < 0 || (nsel > 0 && !cell_ids))
+        return fail(DSMC_EINVAL, "lattice must be 9 or 37, order 2 or 3, f_in non-NULL, nsel >= 0 with cell_ids");
+    if (nsel > x->ncells) return fail(DSMC_EINVAL, "nsel exceeds the number of cells");
     hipStream_t s = S(stream);
     x->last = s;
     TRY(settle(x, s));
@@ -1532,9 +1590,10 @@ int dsmc_project_moments_adjoint(const double *f_bar, const double *avg, int64_t
     return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
 }
 
-int dsmc_read_status(dsmc_ctx *x, dsmc_status *out, int32_t clear, void *stream)
+static int dsmc_read_status_impl(dsmc_ctx *x, dsmc_status *out, int32_t clear, void *stream)
 {
-    if (!x || !out) return DSMC_EINVAL;
+    if (!x) return DSMC_EINVAL;
+    if (!out) return fail(DSMC_EINVAL, "out is NULL");
     hipStream_t s = S(stream);
     TRY(settle(x, s));
     Counters h;
@@ -1559,9 +1618,10 @@ int dsmc_read_status(dsmc_ctx *x, dsmc_status *out, int32_t clear, void *stream)
     return DSMC_OK;
 }
 
-int dsmc_get_views(dsmc_ctx *x, dsmc_views *out)
+static int dsmc_get_views_impl(dsmc_ctx *x, dsmc_views *out)
 {
-    if (!x || !out) return DSMC_EINVAL;
+    if (!x) return DSMC_EINVAL;
+    if (!out) return fail(DSMC_EINVAL, "out is NULL");
     TRY(settle(x, x->last));  // a pending reseed, on the stream of the last call
     out->current = x->cur;
     out->cell_start = x->cs[x->cur];
@@ -1575,16 +1635,17 @@ int dsmc_get_views(dsmc_ctx *x, dsmc_views *out)
     return DSMC_OK;
 }
 
-int dsmc_profile_enable(dsmc_ctx *x, int32_t enable)
+static int dsmc_profile_enable_impl(dsmc_ctx *x, int32_t enable)
 {
     if (!x) return DSMC_EINVAL;
     x->prof = enable != 0;
     return DSMC_OK;
 }
 
-int dsmc_profile_read(dsmc_ctx *x, int32_t kernel, double *ms_total, int64_t *launches)
+static int dsmc_profile_read_impl(dsmc_ctx *x, int32_t kernel, double *ms_total, int64_t *launches)
 {
-    if (!x || kernel < 0 || kernel >= DSMC_K_COUNT) return DSMC_EINVAL;
+    if (!x) return DSMC_EINVAL;
+    if (kernel < 0 || kernel >= DSMC_K_COUNT) return fail(DSMC_EINVAL, "unknown kernel id");
     double tot = 0.0;
     int64_t cnt = 0;
     std::vector<ProfRec> keep;
@@ -1607,18 +1668,17 @@ int dsmc_profile_read(dsmc_ctx *x, int32_t kernel, double *ms_total, int64_t *la
     return DSMC_OK;
 }
 
-int dsmc_graph_create(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
+static int dsmc_graph_create_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
 {
-    if (!x || nsteps < 2 || (nsteps & 1) || sample_every < 0) return DSMC_EINVAL;
-    if (sample_every > 0 && nsteps % sample_every != 0) return DSMC_EINVAL;
+    if (!x) return DSMC_EINVAL;
+    if (nsteps < 2 || (nsteps & 1) || sample_every < 0)
+        return fail(DSMC_EINVAL, "nsteps must be even and >= 2, sample_every >= 0");
+    if (sample_every > 0 && nsteps % sample_every != 0)
+        return fail(DSMC_EINVAL, "nsteps must be a multiple of sample_every");
     hipStream_t s = S(stream);
-    if (s == nullptr) return DSMC_EINVAL;  // capture needs a created stream
+    if (s == nullptr) return fail(DSMC_EINVAL, "capture needs a created stream, not the null stream");
     TRY(settle(x, s));                     // (the graph starts from a settled state)
-    if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
-    if (x->graph) (void)hipGraphDestroy(x->graph);
-    x->gexec = nullptr;
-    x->graph = nullptr;
-    x->g_nsteps = 0;
+    TRY(release_graph(x));
     // capture one dsmc_step call with steps counted from 0; the host-side
     // bookkeeping of the capture is undone afterwards (nothing ran)
     const int64_t step = x->step, nsamples = x->nsamples;
@@ -1652,17 +1712,19 @@ int dsmc_graph_create(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *s
     return DSMC_OK;
 }
 
-int dsmc_graph_launch(dsmc_ctx *x, void *stream)
+static int dsmc_graph_launch_impl(dsmc_ctx *x, void *stream)
 {
     if (!x) return DSMC_EINVAL;
-    if (!x->gexec) return DSMC_ESTATE;
+    if (!x->gexec) return fail(DSMC_ESTATE, "no step graph (none created, or released by a re-tiling)");
     // the captured parities and sampling pattern must hold from this step (a
     // pending reseed, completed first, moves the state to the other buffer);
     // checked before anything is enqueued
     const int cur = x->pending ? 1 - x->cur : x->cur;
-    if ((x->step & 1) || cur != x->g_cur) return DSMC_ESTATE;
-    if (x->g_sample_every > 0 && x->step % x->g_sample_every != 0) return DSMC_ESTATE;
-    if (x->step + x->g_nsteps > (int64_t)0xFFFFFFFF) return DSMC_ESTATE;
+    if ((x->step & 1) || cur != x->g_cur)
+        return fail(DSMC_ESTATE, "the current step must be even, on the state buffer the graph was captured with");
+    if (x->g_sample_every > 0 && x->step % x->g_sample_every != 0)
+        return fail(DSMC_ESTATE, "the current step is not aligned with the graph's sampling period");
+    if (x->step + x->g_nsteps > (int64_t)0xFFFFFFFF) return fail(DSMC_ESTATE, "step counter beyond 2^32");
     hipStream_t s = S(stream);
     TRY(settle(x, s));
     x->last = s;
@@ -1672,6 +1734,97 @@ int dsmc_graph_launch(dsmc_ctx *x, void *stream)
     x->step += x->g_nsteps;
     if (x->g_sample_every > 0) x->nsamples += x->g_nsteps / x->g_sample_every;
     return DSMC_OK;
+}
+
+int dsmc_set_tiling(dsmc_ctx *x, int32_t particles_per_tile, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_set_tiling", dsmc_set_tiling_impl(x, particles_per_tile, stream));
+}
+
+int dsmc_autotune(dsmc_ctx *x, int32_t steps_per_trial, int32_t sample_every, dsmc_tuning *out, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_autotune", dsmc_autotune_impl(x, steps_per_trial, sample_every, out, stream));
+}
+
+int dsmc_replica_counters(dsmc_ctx *x, uint64_t *out, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_replica_counters", dsmc_replica_counters_impl(x, out, stream));
+}
+
+int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_step", dsmc_step_impl(x, nsteps, sample_every, stream));
+}
+
+int dsmc_sample_moments(dsmc_ctx *x, double *out, int32_t reset, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_sample_moments", dsmc_sample_moments_impl(x, out, reset, stream));
+}
+
+int map_dsmc_to_lbm(dsmc_ctx *x, int32_t lattice, int32_t order, double *f_out, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "map_dsmc_to_lbm", map_dsmc_to_lbm_impl(x, lattice, order, f_out, stream));
+}
+
+int dsmc_hybrid_cycle(dsmc_ctx *x, const dsmc_hybrid *h, double *f_lb, double *f_tmp, double *avg_out, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_hybrid_cycle", dsmc_hybrid_cycle_impl(x, h, f_lb, f_tmp, avg_out, stream));
+}
+
+int map_lbm_to_dsmc(dsmc_ctx *x, int32_t lattice, int32_t order, const double *f_in, const int32_t *cell_ids,
+                    int32_t nsel, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "map_lbm_to_dsmc", map_lbm_to_dsmc_impl(x, lattice, order, f_in, cell_ids, nsel, stream));
+}
+
+int dsmc_read_status(dsmc_ctx *x, dsmc_status *out, int32_t clear, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_read_status", dsmc_read_status_impl(x, out, clear, stream));
+}
+
+int dsmc_get_views(dsmc_ctx *x, dsmc_views *out)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_get_views", dsmc_get_views_impl(x, out));
+}
+
+int dsmc_profile_enable(dsmc_ctx *x, int32_t enable)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_profile_enable", dsmc_profile_enable_impl(x, enable));
+}
+
+int dsmc_profile_read(dsmc_ctx *x, int32_t kernel, double *ms_total, int64_t *launches)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_profile_read", dsmc_profile_read_impl(x, kernel, ms_total, launches));
+}
+
+int dsmc_graph_create(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_graph_create", dsmc_graph_create_impl(x, nsteps, sample_every, stream));
+}
+
+int dsmc_graph_launch(dsmc_ctx *x, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_graph_launch", dsmc_graph_launch_impl(x, stream));
+}
+
+const char *dsmc_last_error(const dsmc_ctx *x)
+{
+    if (!x) return "no context";
+    return x->err;
 }
 
 void dsmc_destroy(dsmc_ctx *x)

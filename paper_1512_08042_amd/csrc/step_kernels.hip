@@ -142,13 +142,34 @@ __device__ __forceinline__ int tile_source(const TileLds<TC, CH, S> &L, int t, i
     return (off >= 0 && off < L.gn[t][k]) ? L.gsrc[t][k] + off : -1;
 }
 
-// Long jumps arriving in tile cell t (rare): every near group is preceded
-// in the sort by the long jumps from smaller source cells; counts them and
-// shifts the group starts.
+// ---- long jumps (moves of more than one cell; rare) ---------------------------
+// The pass that moved the particles recorded each long jump (slot, old cell,
+// new cell) in a list of far_cap entries and counted all of them.  When more
+// were counted than the list holds, the list is incomplete and the long jumps
+// are found in the partitioned state itself instead: they are the DIR_FAR
+// group of every cell of the channel, and each one's new cell follows from
+// its stored position exactly as the recording pass found it.
+__device__ __forceinline__ bool far_listed(const StepArgs &a)
+{
+    return a.K().ctr->nfar[a.far_in_slot()] <= (uint32_t)a.K().far_cap;
+}
+
+// new cell (index in the context) of the long jump in input slot q
+template <class S>
+__device__ __forceinline__ int far_new_cell(const StepArgs &a, int q)
+{
+    int nix, niy;
+    cell_xy(a.geo(), (double)a.template in<S>(0)[q], (double)a.template in<S>(1)[q], nix, niy);
+    return a.R().cbase + niy * a.geo().nx + nix;
+}
+
+// Long jumps arriving in tile cell t, from the list (one lane per cell):
+// every near group is preceded in the sort by the long jumps from smaller
+// source cells; counts them and shifts the group starts.
 template <int TC, int CH, class S>
 __device__ void tile_far_shift(const StepArgs &a, TileLds<TC, CH, S> &L, int t, int c, int nfin)
 {
-    const uint32_t nf = min(a.K().ctr->nfar[a.far_in_slot()], (uint32_t)a.K().far_cap);
+    const uint32_t nf = a.K().ctr->nfar[a.far_in_slot()];
     const int ng = L.ng[t];
     int shift[NDIR];
 #pragma unroll
@@ -169,43 +190,158 @@ __device__ void tile_far_shift(const StepArgs &a, TileLds<TC, CH, S> &L, int t, 
     a.farcnt_in()[c] = 0;
 }
 
+// The same after an overflow, by the whole wave: lane l scans the DIR_FAR
+// groups of the channel's cells l, l + 64, ...; the per-lane shifts and
+// counts are summed over the wave (integers: exact in any order).  c0 is the
+// tile's first cell; lane t < ntc holds nfin of tile cell t.
+template <int TC, int CH, class S>
+__device__ void tile_far_shift_scan(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int ntc, int nfin)
+{
+    const int lane = threadIdx.x;
+    const int cb = a.R().cbase, ce = a.R().cend;
+    int shift[TC][NDIR], found[TC];
+#pragma unroll
+    for (int t = 0; t < TC; ++t) {
+        found[t] = 0;
+#pragma unroll
+        for (int k = 0; k < NDIR; ++k) shift[t][k] = 0;
+    }
+    for (int o = cb + lane; o < ce; o += 64) {
+        const int32_t *g = a.grp_in() + (size_t)o * GSTRIDE + DIR_FAR;
+        for (int q = g[0]; q < g[1]; ++q) {
+            const int t = far_new_cell<S>(a, q) - c0;
+#pragma unroll
+            for (int u = 0; u < TC; ++u) {
+                if (u != t || u >= ntc) continue;
+                found[u] += 1;
+#pragma unroll
+                for (int k = 0; k < NDIR; ++k)
+                    if (k < L.ng[u] && o < L.gkey[u][k]) shift[u][k] += 1;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < TC; ++t) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) found[t] += __shfl_xor(found[t], off, 64);
+#pragma unroll
+        for (int k = 0; k < NDIR; ++k) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) shift[t][k] += __shfl_xor(shift[t][k], off, 64);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < TC; ++t) {
+        if (t != lane || t >= ntc) continue;
+#pragma unroll
+        for (int k = 0; k < NDIR; ++k)
+            if (k < L.ng[t]) L.gstart[t][k] += shift[t][k];
+        if (found[t] != nfin) atomicOr(&a.K().ctr->status, ST_INTERNAL);
+        if (nfin > 0) a.farcnt_in()[c0 + t] = 0;
+    }
+}
+
+// total size of tile cell t's near groups from source cells before o
+template <int TC, int CH, class S>
+__device__ __forceinline__ int near_before(const TileLds<TC, CH, S> &L, int t, int o)
+{
+    int r = 0;
+    for (int k = 0; k < L.ng[t]; ++k)
+        if (L.gkey[t][k] < o) r += L.gn[t][k];
+    return r;
+}
+
+// stages the long jump from input slot q at offset r of tile cell t (see
+// tile_far_gather)
+template <int TC, int CH, class S>
+__device__ __forceinline__ void far_put(const StepArgs &a, const TileLds<TC, CH, S> &L, S *const *s, int n_old,
+                                        int32_t *pick, int t, int q, int r)
+{
+    const int D0 = L.csn[0];
+    const int slot = L.csn[t] - D0 + r;
+    if (q < 0 || q >= n_old || slot >= L.csn[t + 1] - D0) {
+        atomicOr(&a.K().ctr->status, ST_INTERNAL);
+        return;
+    }
+#pragma unroll
+    for (int k = 2; k < 5; ++k) s[k][slot] = a.template in<S>(k)[q];
+    if (pick) {
+        pick[slot] = q;
+    } else {
+        s[0][slot] = a.template in<S>(0)[q];
+        s[1][slot] = a.template in<S>(1)[q];
+    }
+}
+
 // Stages the long jumps arriving in the tile at their sorted slots: after
 // the near groups of smaller source cells and the long jumps of smaller
 // (source cell, source slot).  s[2..4] address the tile's velocity stage;
 // positions go to s[0], s[1] too, or, when `pick` is given (positions kept in
 // the owner lanes' registers), the source slot goes to pick[slot] for the
-// owner lane to fetch.
+// owner lane to fetch.  From the list, lanes take entries in turn.  After an
+// overflow, lane l scans the DIR_FAR groups of a contiguous block of the
+// channel's cells twice: it counts the tile's arrivals in its block, adds the
+// counts of the lanes before it (the earlier source cells), then stages its
+// arrivals in (source cell, slot) order.
 template <int TC, int CH, class S>
 __device__ void tile_far_gather(const StepArgs &a, const TileLds<TC, CH, S> &L, S *const *s, int c0, int ntc,
                                 int n_old, int32_t *pick)
 {
-    const uint32_t nf = min(a.K().ctr->nfar[a.far_in_slot()], (uint32_t)a.K().far_cap);
-    const int D0 = L.csn[0];
-    for (uint32_t e = threadIdx.x; e < nf; e += 64) {
-        const int nc = a.far_in()[4 * (size_t)e + 2];
-        if (nc < c0 || nc >= c0 + ntc) continue;
-        const int t = nc - c0;
-        const int q = a.far_in()[4 * (size_t)e], o = a.far_in()[4 * (size_t)e + 1];
-        int r = 0;
-        for (int k = 0; k < L.ng[t]; ++k)
-            if (L.gkey[t][k] < o) r += L.gn[t][k];
-        for (uint32_t f = 0; f < nf; ++f) {
-            if (a.far_in()[4 * (size_t)f + 2] != nc) continue;
-            const int o2 = a.far_in()[4 * (size_t)f + 1], q2 = a.far_in()[4 * (size_t)f];
-            if (o2 < o || (o2 == o && q2 < q)) ++r;
+    const int lane = threadIdx.x;
+    if (far_listed(a)) {
+        const uint32_t nf = a.K().ctr->nfar[a.far_in_slot()];
+        for (uint32_t e = lane; e < nf; e += 64) {
+            const int nc = a.far_in()[4 * (size_t)e + 2];
+            if (nc < c0 || nc >= c0 + ntc) continue;
+            const int t = nc - c0;
+            const int q = a.far_in()[4 * (size_t)e], o = a.far_in()[4 * (size_t)e + 1];
+            int r = near_before<TC, CH, S>(L, t, o);
+            for (uint32_t f = 0; f < nf; ++f) {
+                if (a.far_in()[4 * (size_t)f + 2] != nc) continue;
+                const int o2 = a.far_in()[4 * (size_t)f + 1], q2 = a.far_in()[4 * (size_t)f];
+                if (o2 < o || (o2 == o && q2 < q)) ++r;
+            }
+            far_put<TC, CH, S>(a, L, s, n_old, pick, t, q, r);
         }
-        const int slot = L.csn[t] - D0 + r;
-        if (q < 0 || q >= n_old || slot >= L.csn[t + 1] - D0) {
-            atomicOr(&a.K().ctr->status, ST_INTERNAL);
-            continue;
-        }
+        return;
+    }
+    const int cb = a.R().cbase, ce = a.R().cend;
+    const int blk = (ce - cb + 63) / 64;
+    const int o0 = min(cb + lane * blk, ce), o1 = min(o0 + blk, ce);
+    int cnt[TC];
 #pragma unroll
-        for (int k = 2; k < 5; ++k) s[k][slot] = a.template in<S>(k)[q];
-        if (pick) {
-            pick[slot] = q;
-        } else {
-            s[0][slot] = a.template in<S>(0)[q];
-            s[1][slot] = a.template in<S>(1)[q];
+    for (int t = 0; t < TC; ++t) cnt[t] = 0;
+    for (int o = o0; o < o1; ++o) {
+        const int32_t *g = a.grp_in() + (size_t)o * GSTRIDE + DIR_FAR;
+        for (int q = g[0]; q < g[1]; ++q) {
+            const int t = far_new_cell<S>(a, q) - c0;
+#pragma unroll
+            for (int u = 0; u < TC; ++u)
+                if (u == t && u < ntc) cnt[u] += 1;
+        }
+    }
+    // exclusive prefix over the lanes: the arrivals from the earlier blocks
+#pragma unroll
+    for (int t = 0; t < TC; ++t) {
+        int inc = cnt[t];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += v;
+        }
+        cnt[t] = inc - cnt[t];
+    }
+    for (int o = o0; o < o1; ++o) {
+        const int32_t *g = a.grp_in() + (size_t)o * GSTRIDE + DIR_FAR;
+        for (int q = g[0]; q < g[1]; ++q) {
+            const int t = far_new_cell<S>(a, q) - c0;
+#pragma unroll
+            for (int u = 0; u < TC; ++u) {
+                if (u != t || u >= ntc) continue;
+                far_put<TC, CH, S>(a, L, s, n_old, pick, u, q, near_before<TC, CH, S>(L, u, o) + cnt[u]);
+                cnt[u] += 1;
+            }
         }
     }
 }
@@ -280,9 +416,14 @@ __device__ void tile_groups(const StepArgs &a, TileLds<TC, CH, S> &L, int ntc, i
     }
     if (lane == 0) L.anyfar = 0;
     __syncthreads();
-    if (lane < ntc && nfin > 0) {
-        L.anyfar = 1;
-        tile_far_shift<TC, CH, S>(a, L, lane, a.R().cbase + L.tiy[lane] * nx + L.tix[lane], nfin);
+    if (ballot64(lane < ntc && nfin > 0) != 0) {  // long jumps arrive in the tile (rare)
+        if (far_listed(a)) {
+            if (lane < ntc && nfin > 0)
+                tile_far_shift<TC, CH, S>(a, L, lane, a.R().cbase + L.tiy[lane] * nx + L.tix[lane], nfin);
+        } else {
+            tile_far_shift_scan<TC, CH, S>(a, L, a.R().cbase + L.tiy[0] * nx + L.tix[0], ntc, nfin);
+        }
+        if (lane == 0) L.anyfar = 1;
     }
     __syncthreads();
 }
@@ -616,9 +757,8 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
         }
         __builtin_amdgcn_s_setprio(0);  // the gather is issued
         // every slot of the tile is staged: a slot that no near group fills
-        // holds zeros until a long jump fills it (or stays so when the long
-        // jumps overflowed their list, which the status reports), and its
-        // long-jump source slot is marked absent
+        // holds zeros until the long jump that the sort puts there fills it,
+        // and its long-jump source slot is marked absent until then
 #pragma unroll
         for (int b = 0; b < CH; ++b) {
             const int i = 64 * b + lane;

@@ -88,21 +88,22 @@ class Channel:
 
     # ---- the hot path -------------------------------------------------------------
     def step(self, nsteps: int = 1, sample_every: int = 0, stream=None):
-        check(lib().dsmc_step(self._h, int(nsteps), int(sample_every), _stream(stream)), "dsmc_step")
+        check(lib().dsmc_step(self._h, int(nsteps), int(sample_every), _stream(stream)), "dsmc_step", self._h)
 
     def sample_moments(self, reset: bool = False, stream=None) -> torch.Tensor:
         out = torch.empty((NMOM, self.ncells), dtype=torch.float64, device=self.device)
-        check(lib().dsmc_sample_moments(self._h, _ptr(out), int(reset), _stream(stream)), "dsmc_sample_moments")
+        check(lib().dsmc_sample_moments(self._h, _ptr(out), int(reset), _stream(stream)), "dsmc_sample_moments",
+              self._h)
         return out
 
     def reset_moments(self, stream=None):
-        check(lib().dsmc_sample_moments(self._h, None, 1, _stream(stream)), "dsmc_sample_moments")
+        check(lib().dsmc_sample_moments(self._h, None, 1, _stream(stream)), "dsmc_sample_moments", self._h)
 
     def map_to_lbm(self, lattice_q: int, order: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         if out is None:
             out = torch.empty((lattice_q, self.ncells), dtype=torch.float64, device=self.device)
         check(lib().map_dsmc_to_lbm(self._h, int(lattice_q), int(order), _ptr(out), _stream(stream)),
-              "map_dsmc_to_lbm")
+              "map_dsmc_to_lbm", self._h)
         return out
 
     def map_from_lbm(self, f: torch.Tensor, cell_ids: torch.Tensor, lattice_q: int, order: int, stream=None):
@@ -114,14 +115,14 @@ class Channel:
         assert f.dtype == torch.float64 and f.is_contiguous() and f.shape == (lattice_q, self.ncells)
         assert cell_ids.dtype == torch.int32 and cell_ids.is_contiguous()
         check(lib().map_lbm_to_dsmc(self._h, int(lattice_q), int(order), _ptr(f), _ptr(cell_ids),
-                                    int(cell_ids.numel()), _stream(stream)), "map_lbm_to_dsmc")
+                                    int(cell_ids.numel()), _stream(stream)), "map_lbm_to_dsmc", self._h)
 
     # ---- inspection ---------------------------------------------------------------
     def views(self) -> _lib.Views:
         """Current buffer, cell starts and bookkeeping (completes a pending
         reseed first, on the stream of the last call)."""
         v = _lib.Views()
-        check(lib().dsmc_get_views(self._h, ctypes.byref(v)), "dsmc_get_views")
+        check(lib().dsmc_get_views(self._h, ctypes.byref(v)), "dsmc_get_views", self._h)
         return v
 
     def _ws_view(self, addr: int, n: int, dtype) -> torch.Tensor:
@@ -139,7 +140,8 @@ class Channel:
 
     def status(self, clear: bool = False, stream=None) -> dict:
         s = _lib.Status()
-        check(lib().dsmc_read_status(self._h, ctypes.byref(s), int(clear), _stream(stream)), "dsmc_read_status")
+        check(lib().dsmc_read_status(self._h, ctypes.byref(s), int(clear), _stream(stream)), "dsmc_read_status",
+              self._h)
         return {"bits": int(s.bits), "n": int(s.n_particles), "ncoll": int(s.ncoll), "ncand": int(s.ncand),
                 "nwall": int(s.nwall), "nfar": int(s.nfar)}
 
@@ -152,7 +154,7 @@ class Channel:
     def set_tiling(self, particles_per_tile: int = 0, stream=None):
         """Tiles of about particles_per_tile particles (0: the default); the
         particles do not depend on it, the moment sums only to rounding."""
-        check(lib().dsmc_set_tiling(self._h, int(particles_per_tile), _stream(stream)), "dsmc_set_tiling")
+        check(lib().dsmc_set_tiling(self._h, int(particles_per_tile), _stream(stream)), "dsmc_set_tiling", self._h)
 
     def hybrid_cycle(self, f_lb: torch.Tensor, f_tmp: torch.Tensor, lbm_nx: int, tau: float, body_force_x: float,
                      dsmc_steps: int, lbm_steps: int, mapping: int = 0, order: int = 2, dsmc_column: int | None = None,
@@ -173,25 +175,26 @@ class Channel:
             assert avg_out.dtype == torch.float64 and avg_out.is_contiguous() and avg_out.shape == (NMOM, self.ncells)
         check(lib().dsmc_hybrid_cycle(self._h, ctypes.byref(h), _ptr(f_lb), _ptr(f_tmp),
                                       _ptr(avg_out) if avg_out is not None else None, _stream(stream)),
-              "dsmc_hybrid_cycle")
+              "dsmc_hybrid_cycle", self._h)
 
     def graph_create(self, nsteps: int, sample_every: int = 0, stream=None):
         """Capture one step(nsteps, sample_every) call into a HIP graph on
         `stream` (a torch.cuda.Stream; capture cannot use the null stream)."""
         check(lib().dsmc_graph_create(self._h, int(nsteps), int(sample_every), _stream(stream)),
-              "dsmc_graph_create")
+              "dsmc_graph_create", self._h)
 
     def graph_launch(self, stream=None):
         """Replay the captured steps from the current step."""
-        check(lib().dsmc_graph_launch(self._h, _stream(stream)), "dsmc_graph_launch")
+        check(lib().dsmc_graph_launch(self._h, _stream(stream)), "dsmc_graph_launch", self._h)
 
     def profile(self, enable: bool = True):
-        check(lib().dsmc_profile_enable(self._h, int(enable)), "dsmc_profile_enable")
+        check(lib().dsmc_profile_enable(self._h, int(enable)), "dsmc_profile_enable", self._h)
 
     def profile_read(self, kernel: int):
         ms = ctypes.c_double()
         n = ctypes.c_int64()
-        check(lib().dsmc_profile_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n)), "dsmc_profile_read")
+        check(lib().dsmc_profile_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n)), "dsmc_profile_read",
+              self._h)
         return ms.value, n.value
 
 
@@ -281,13 +284,13 @@ class Batch(Channel):
 
         out = np.zeros((self.nrep, 3), dtype=np.uint64)
         check(lib().dsmc_replica_counters(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
-                                          _stream(stream)), "dsmc_replica_counters")
+                                          _stream(stream)), "dsmc_replica_counters", self._h)
         return out
 
     def autotune(self, steps_per_trial: int = 2, sample_every: int = 0, stream=None) -> dict:
         t = _lib.Tuning()
         check(lib().dsmc_autotune(self._h, int(steps_per_trial), int(sample_every), ctypes.byref(t),
-                                  _stream(stream)), "dsmc_autotune")
+                                  _stream(stream)), "dsmc_autotune", self._h)
         return {"particles_per_tile": [t.particles_per_tile[i] for i in range(t.ncand)],
                 "ms_per_step": [t.ms_per_step[i] for i in range(t.ncand)],
                 "chosen": t.particles_per_tile[t.chosen]}

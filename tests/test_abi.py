@@ -49,6 +49,7 @@ def test_null_arguments_rejected_without_gpu():
     assert L.lbm_step(ctypes.byref(cfg), None, None, 1, None) == _lib.EINVAL
     assert L.dsmc_project_moments(None, 4, 10, 1.0, 9, 2, None, None) == _lib.EINVAL
     assert L.dsmc_strerror(_lib.ECAPACITY) == b"capacity exceeded"
+    assert L.dsmc_last_error(None) == b"no context"
 
 
 @pytest.mark.parametrize("q", [9, 37])

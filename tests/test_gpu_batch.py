@@ -194,3 +194,56 @@ def test_step_graph_replays_match_eager_steps():
     torch.cuda.synchronize()
     eager.close()
     graphed.close()
+
+
+def test_retiling_releases_the_step_graph():
+    # a graph holds the tile shapes it was captured with: a re-tiling
+    # releases it (a replay is refused, with the reason in the context's
+    # message), and a graph captured after the re-tiling replays like eager
+    # steps under the new tiling
+    D, _ = _gpu()
+    from paper_1512_08042_amd._lib import ESTATE, DsmcError
+
+    s = torch.cuda.Stream()
+    eager = D.Batch(REPS)
+    graphed = D.Batch(REPS)
+    torch.cuda.synchronize()
+    graphed.graph_create(2, sample_every=1, stream=s)
+    graphed.graph_launch(stream=s)
+    eager.step(2, sample_every=1)
+    graphed.set_tiling(100, stream=s)  # smaller tiles: two replicas change shape
+    with pytest.raises(DsmcError) as e:
+        graphed.graph_launch(stream=s)
+    assert e.value.code == ESTATE
+    assert "graph" in e.value.detail and "dsmc_graph_launch" in e.value.detail
+    graphed.graph_create(2, sample_every=1, stream=s)
+    for rep in range(2):
+        graphed.graph_launch(stream=s)
+        eager.step(2, sample_every=1)
+        s.synchronize()
+        for g, w in zip(graphed.particles(), eager.particles()):
+            assert np.array_equal(g.cpu().numpy(), w.cpu().numpy()), "replay %d after re-tiling" % rep
+        assert np.array_equal(graphed.cell_start().cpu().numpy(), eager.cell_start().cpu().numpy())
+        assert np.array_equal(graphed.replica_counters(), eager.replica_counters())
+    torch.cuda.synchronize()
+    eager.close()
+    graphed.close()
+
+
+def test_last_error_names_the_call_and_the_reason():
+    D, _ = _gpu()
+    from paper_1512_08042_amd._lib import EINVAL, ESTATE, DsmcError
+
+    b = D.Batch(REPS[:2])
+    with pytest.raises(DsmcError) as e:
+        b.step(-1)
+    assert e.value.code == EINVAL
+    assert e.value.detail.startswith("dsmc_step: nsteps") and "invalid argument" in e.value.detail
+    with pytest.raises(DsmcError) as e:
+        b.map_to_lbm(9, 2)
+    assert e.value.code == ESTATE and "one channel only" in e.value.detail
+    b.step(1)  # a successful call leaves the message of the last failure
+    from paper_1512_08042_amd._lib import lib
+
+    assert lib().dsmc_last_error(b._h).decode().startswith("map_dsmc_to_lbm:")
+    b.close()
