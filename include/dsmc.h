@@ -249,6 +249,20 @@ int lbm_adjoint_workspace(const lbm_config *cfg, int32_t every, size_t *bytes);
 int lbm_adjoint_step(const lbm_config *cfg, const double *f_n, const double *lam_next, double *lam_out,
                      double *grad, void *work, void *stream);
 
+/* lbm_adjoint_step for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same step and results, with the per-block partial sums
+ * kept in a fixed array inside the library instead of a caller workspace.
+ * The array (2 doubles per block of 256 nodes, 256 KB) exists once on every
+ * GPU the library runs on, from the first call on that device until the
+ * process ends; the call itself allocates nothing.  Calls that overlap on
+ * one GPU (other streams, other threads) share the array and race: run them
+ * one after another.  Errors: DSMC_EINVAL (as lbm_adjoint_step),
+ * DSMC_ECAPACITY when nx * ny exceeds 4,194,304 nodes (16,384 blocks),
+ * DSMC_EHIP. */
+int lbm_adjoint_step_noalloc(const lbm_config *cfg, const double *f_n, const double *lam_next, double *lam_out,
+                             double *grad, void *stream);
+
 /* Reverse pass of nsteps lbm_step steps from the checkpoints that
  * lbm_step_checkpointed wrote with the same cfg and every: each segment's
  * states are recomputed into the workspace, then the adjoint steps run from

@@ -25,7 +25,7 @@ EXPORTS = ("dsmc_query_sizes", "dsmc_init", "dsmc_step", "dsmc_sample_moments", 
            "lbm_hermite_moments", "lbm_hermite_moments_adjoint", "dsmc_project_moments_adjoint",
            "dsmc_batch_query_sizes", "dsmc_batch_init", "dsmc_set_tiling", "dsmc_autotune", "dsmc_replica_counters",
            "dsmc_graph_create", "dsmc_graph_launch", "dsmc_project_equilibrium", "dsmc_hybrid_cycle",
-           "dsmc_last_error")
+           "dsmc_last_error", "lbm_adjoint_step_noalloc")
 
 
 class Config(ctypes.Structure):
@@ -99,6 +99,7 @@ def lib():
         L.lbm_step_checkpointed.argtypes = [P(LbmConfig), c_p, c_p, c_p, c_i32, c_i32, c_p]
         L.lbm_adjoint_workspace.argtypes = [P(LbmConfig), c_i32, P(c_sz)]
         L.lbm_adjoint_step.argtypes = [P(LbmConfig), c_p, c_p, c_p, c_p, c_p, c_p]
+        L.lbm_adjoint_step_noalloc.argtypes = [P(LbmConfig), c_p, c_p, c_p, c_p, c_p]
         L.lbm_adjoint.argtypes = [P(LbmConfig), c_p, c_i32, c_i32, c_p, c_p, c_p, c_p]
         L.lbm_hermite_moments.argtypes = [c_i32, c_i32, c_p, c_i64, c_p, c_i32, c_p, c_p]
         L.lbm_hermite_moments_adjoint.argtypes = [c_i32, c_i32, c_p, c_p, c_i32, c_p, c_i64, c_p]

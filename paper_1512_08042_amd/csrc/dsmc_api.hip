@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1214,6 +1215,54 @@ int settle(dsmc_ctx *x, hipStream_t s)
 }
 }  // namespace
 
+// ---- the adjoint step without a caller workspace -----------------------------
+// lbm_adjoint_step_noalloc keeps the per-block partial sums of dJ/dg and
+// dJ/dtau (2 doubles per block of 256 nodes) in this array instead of a
+// workspace: every device the library runs on holds one copy of it until the
+// process ends.  Each adjoint launch writes every slot it later reads, so the
+// array needs no clearing between calls.
+constexpr int NOALLOC_MAX_BLOCKS = 16384;  // 4,194,304 nodes
+static __device__ __align__(256) double scratch[2 * NOALLOC_MAX_BLOCKS];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+double *noalloc_ptr[NOALLOC_MAX_DEVICES];  // the array's address on each device, once looked up
+
+// The device address of `scratch` on the current device.  The host-side name
+// of a __device__ array is not a device address; it is looked up once per
+// device (with that device current) and only the looked-up address is used.
+int noalloc_scratch(double **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return DSMC_EHIP;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return DSMC_EINVAL;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DSMC_EHIP;
+        noalloc_ptr[dev] = (double *)p;
+    }
+    *out = noalloc_ptr[dev];
+    return DSMC_OK;
+}
+
+// one adjoint step with the per-block partial sums in `partial` (>= 2 nblk doubles)
+int adjoint_step_on(const lbm_config *cfg, const double *f_n, const double *lam_next, double *lam_out,
+                    double *grad, double *partial, hipStream_t s)
+{
+    LbmArgs a;
+    if (!lbm_args(cfg, a) || !adjoint_supported(cfg) || !f_n || !lam_next || !lam_out || !grad || !partial)
+        return DSMC_EINVAL;
+    if (lam_next == lam_out) return DSMC_EINVAL;
+    const AdjLayout W = adj_layout(cfg, a.L.Q, 0);
+    LbmAdjArgs b = adj_args(a, f_n, lam_next, lam_out, partial + W.partial / sizeof(double), 0);
+    launch_lbm_adjoint(b, (unsigned)W.nblk, s);
+    k_adjoint_finish<<<1, 256, 0, s>>>(b.partial, (int)W.nblk, grad);
+    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+}  // namespace
+
 extern "C" {
 
 static int dsmc_step_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
@@ -1483,17 +1532,19 @@ int lbm_adjoint_workspace(const lbm_config *cfg, int32_t every, size_t *bytes)
 int lbm_adjoint_step(const lbm_config *cfg, const double *f_n, const double *lam_next, double *lam_out,
                      double *grad, void *work, void *stream)
 {
+    if (!work) return DSMC_EINVAL;
+    return adjoint_step_on(cfg, f_n, lam_next, lam_out, grad, (double *)work, S(stream));
+}
+
+int lbm_adjoint_step_noalloc(const lbm_config *cfg, const double *f_n, const double *lam_next, double *lam_out,
+                             double *grad, void *stream)
+{
     LbmArgs a;
-    if (!lbm_args(cfg, a) || !adjoint_supported(cfg) || !f_n || !lam_next || !lam_out || !grad || !work)
-        return DSMC_EINVAL;
-    if (lam_next == lam_out) return DSMC_EINVAL;
-    const AdjLayout W = adj_layout(cfg, a.L.Q, 0);
-    hipStream_t s = S(stream);
-    double *partial = (double *)((char *)work + W.partial);
-    LbmAdjArgs b = adj_args(a, f_n, lam_next, lam_out, partial, 0);
-    launch_lbm_adjoint(b, (unsigned)W.nblk, s);
-    k_adjoint_finish<<<1, 256, 0, s>>>(partial, (int)W.nblk, grad);
-    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+    if (!lbm_args(cfg, a)) return DSMC_EINVAL;
+    if (adj_layout(cfg, a.L.Q, 0).nblk > (size_t)NOALLOC_MAX_BLOCKS) return DSMC_ECAPACITY;
+    double *partial = nullptr;
+    TRY(noalloc_scratch(&partial));
+    return adjoint_step_on(cfg, f_n, lam_next, lam_out, grad, partial, S(stream));
 }
 
 int lbm_adjoint(const lbm_config *cfg, const double *ckpt, int32_t nsteps, int32_t every, double *lam,
