@@ -218,8 +218,8 @@ int far_cap_of(const dsmc_config &c)
 }
 
 struct Layout {
-    size_t cs0, cs1, grp0, grp1, countnew, farcnt, blocksum, far0, far1, nbar, sigcmax, rem, mom, mark, prm, nnew, perm,
-        tstat, kc, ctr, rep, tiles, cell_rep, rstat, total;
+    size_t cs0, cs1, grp0, grp1, plan, countnew, farcnt, blocksum, far0, far1, nbar, sigcmax, rem, mom, mark, prm, nnew,
+        perm, tstat, kc, ctr, rep, tiles, cell_rep, rstat, total;
 };
 
 // nc: cells of all channels together; nrep: channels
@@ -238,6 +238,7 @@ Layout make_layout(const dsmc_config &c, size_t nc, size_t nrep)
     L.cs1 = take((nc + 1) * 4);
     L.grp0 = take(GSTRIDE * nc * 4);
     L.grp1 = take(GSTRIDE * nc * 4);
+    L.plan = take(2 * NDIR * nc * 4);
     L.countnew = take(nc * 4);
     L.farcnt = take(2 * nc * 4);
     L.blocksum = take(nblk * 4);
@@ -327,7 +328,7 @@ struct dsmc_ctx {
     dsmc_config cfg;
     void *st[2][5];  // double, or float when state32
     int32_t *cs[2];
-    int32_t *grp[2], *countnew, *farcnt, *blocksum, *far[2], *mark, *nnew, *perm;
+    int32_t *grp[2], *plan, *countnew, *farcnt, *blocksum, *far[2], *mark, *nnew, *perm;
     double *nbar, *sigcmax, *rem, *mom, *prm;
     Counters *ctr;
     unsigned long long *tstat;
@@ -467,6 +468,7 @@ int upload_tile_const(dsmc_ctx *x, hipStream_t s)
         k.far[b] = x->far[b];
         k.farcnt[b] = x->farcnt + (size_t)b * x->ncells;
     }
+    k.plan = x->plan;
     k.scr = (double *)x->perm;
     k.scr_i = (int32_t *)((char *)x->perm + (size_t)x->cfg.capacity * 8);
     k.ctr = x->ctr;
@@ -904,6 +906,7 @@ int init_ctx(const dsmc_config *cfg, const dsmc_replica *reps, int32_t nrep, con
     x->cs[1] = (int32_t *)(w + L.cs1);
     x->grp[0] = (int32_t *)(w + L.grp0);
     x->grp[1] = (int32_t *)(w + L.grp1);
+    x->plan = (int32_t *)(w + L.plan);
     x->countnew = (int32_t *)(w + L.countnew);
     x->farcnt = (int32_t *)(w + L.farcnt);
     x->blocksum = (int32_t *)(w + L.blocksum);
@@ -1299,6 +1302,7 @@ static int dsmc_step_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, voi
         const int p = (int)(x->step & 1);
         CellArgs c;
         c.grp = x->grp[p];
+        c.plan = x->plan;
         c.farcnt = x->farcnt + (size_t)p * nc;
         c.countnew = x->countnew;
         c.blocksum = x->blocksum;

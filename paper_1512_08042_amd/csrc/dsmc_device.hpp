@@ -147,7 +147,9 @@ __device__ __forceinline__ void sincos_turn(double r, double &s, double &c)
 // natural log of x in (0, 1] (a normal double): x = m 2^e with m in
 // [sqrt(1/2), sqrt(2)), log m = 2 atanh(s), s = (m-1)/(m+1), |s| < 0.1716,
 // atanh by its odd series to s^27 (remainder below 1e-22); e ln 2 with ln 2
-// split in a short high part and a correction.
+// split in a short high part and a correction (the Cody-Waite split used by
+// fdlibm's e_log.c, whose high part has trailing zero bits so that e times it
+// is exact).
 __device__ __forceinline__ double log_unit(double x)
 {
     const long long bits = __double_as_longlong(x);
@@ -306,6 +308,35 @@ __device__ __forceinline__ int source_cell(int nx, int ny, int cix, int ciy, int
     return siy * nx + six;
 }
 
+// The near groups arriving in cell (cix, ciy) of a channel whose first cell
+// is cb, in the order of the stable sort by new cell: by source cell.  For
+// each rank k, dir[k] is the direction of the k-th group and key[k] its
+// source cell (cb + index inside the channel), INT_MAX for a direction
+// without a source (beyond a wall, or an alias when nx <= 2); those come last.
+// Source cells of different directions differ, so the order is strict.
+__device__ __forceinline__ void arrival_order(int nx, int ny, int cix, int ciy, int cb, int *key, int *dir)
+{
+    int kd[NDIR];
+#pragma unroll
+    for (int d = 0; d < NDIR; ++d) {
+        const int sc = source_cell(nx, ny, cix, ciy, d);
+        kd[d] = sc >= 0 ? cb + sc : 0x7fffffff;
+    }
+#pragma unroll
+    for (int d = 0; d < NDIR; ++d) {
+        int rank = 0;
+#pragma unroll
+        for (int e = 0; e < NDIR; ++e) rank += (kd[e] < kd[d] || (kd[e] == kd[d] && e < d)) ? 1 : 0;
+#pragma unroll
+        for (int k = 0; k < NDIR; ++k) {
+            if (k == rank) {
+                key[k] = kd[d];
+                dir[k] = d;
+            }
+        }
+    }
+}
+
 // ---- wave64 helpers --------------------------------------------------------
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
@@ -313,6 +344,14 @@ __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 __device__ __forceinline__ int rank_below(uint64_t m)
 {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// the value of v on lane u (u wave-uniform), read into scalar registers
+__device__ __forceinline__ unsigned long long lane_u64(unsigned long long v, int u)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), u);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 __device__ __forceinline__ double wave_sum(double v)

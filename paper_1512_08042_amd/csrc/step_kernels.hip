@@ -95,25 +95,27 @@ struct TileLds {
     S v[3][CAP];                   // vx, vy, vz of the tile's particles (stored precision), in new-slot order;
                                    // positions stay in registers of the lane that owns the slot
     // arrays of different phases share their space (each phase ends at a
-    // barrier): the raw groups (set-up), the NTC draws (collisions) and the
-    // long jumps' source slots (gather), then the group keys (move to write)
+    // barrier): the NTC draws (collisions) and the long jumps' source slots
+    // (gather), then the group keys (move to write)
     union {
         int32_t kr[CAP];           // next-step group (low 6 bits) and rank inside it, per slot
         struct {
             double dr[5][NTC_ROUND];   // one round of NTC draws: R, cos(theta), sin(theta), cos(phi), sin(phi)
             int32_t di[2][NTC_ROUND];  // ... and the candidate pairs (i, j)
         };
-        int32_t raw[3][TC * NDIR]; // near groups before ordering: source cell, size, first source slot
     };
     long long mc[TC];              // NTC candidates of each cell this step
     int32_t csn[TC + 1];           // cell starts of the tile after the sort
     int32_t tix[TC], tiy[TC];      // cell coordinates
     int32_t anyfar;                // long jumps arrive in some cell of the tile
-    int32_t ng[TC];                // near groups arriving in each cell
-    int32_t gkey[TC][NDIR];        // their source cells, ascending
+    // the 9 near groups arriving in each cell, in the order of the sort (by
+    // source cell; groups without a source last, empty); the keys and sizes
+    // only where long jumps arrive
     int32_t gsrc[TC][NDIR];        // their first source slots
-    int32_t gn[TC][NDIR];          // their sizes
     int32_t gstart[TC][NDIR];      // their first slots inside the cell
+    int32_t gkey[TC][NDIR];        // their source cells (INT_MAX: none)
+    int32_t gn[TC][NDIR];          // their sizes
+    int32_t nfin[TC];              // long jumps arriving in each cell
     int32_t rsrc[TC];              // classify after a reseed: first old slot of a kept cell, -1 for a new one
     int32_t run[TC * NGRP];        // sizes of the next step's groups of the tile's cells ...
     int32_t excl[TC * NGRP];       // ... and their offsets inside each cell
@@ -130,16 +132,21 @@ __device__ __forceinline__ int tile_cell(const TileLds<TC, CH, S> &L, int ntc, i
 }
 
 // source slot of the particle that the sort puts at offset r of tile cell t
-// when a near group holds that offset; -1 otherwise (a long jump's slot)
+// when a near group holds that offset; -1 otherwise (a long jump's slot).
+// The group is the last one starting at or before r (empty groups start where
+// the next one does).  Without long jumps in the tile (`gaps` false) the near
+// groups fill the cell from offset 0 and every offset is in its group; with
+// them, offsets before the first group or after a group's end are long
+// jumps' slots.
 template <int TC, int CH, class S>
-__device__ __forceinline__ int tile_source(const TileLds<TC, CH, S> &L, int t, int r)
+__device__ __forceinline__ int tile_source(const TileLds<TC, CH, S> &L, int t, int r, bool gaps)
 {
-    // entries ng .. NDIR-1 of the table are padding (start INT_MAX, size 0)
     int k = 0;
 #pragma unroll
     for (int u = 1; u < NDIR; ++u) k += (r >= L.gstart[t][u]) ? 1 : 0;
     const int off = r - L.gstart[t][k];
-    return (off >= 0 && off < L.gn[t][k]) ? L.gsrc[t][k] + off : -1;
+    if (gaps && (off < 0 || off >= L.gn[t][k])) return -1;
+    return L.gsrc[t][k] + off;
 }
 
 // ---- long jumps (moves of more than one cell; rare) ---------------------------
@@ -170,7 +177,6 @@ template <int TC, int CH, class S>
 __device__ void tile_far_shift(const StepArgs &a, TileLds<TC, CH, S> &L, int t, int c, int nfin)
 {
     const uint32_t nf = a.K().ctr->nfar[a.far_in_slot()];
-    const int ng = L.ng[t];
     int shift[NDIR];
 #pragma unroll
     for (int k = 0; k < NDIR; ++k) shift[k] = 0;
@@ -181,11 +187,10 @@ __device__ void tile_far_shift(const StepArgs &a, TileLds<TC, CH, S> &L, int t, 
         const int o = a.far_in()[4 * (size_t)e + 1];
 #pragma unroll
         for (int k = 0; k < NDIR; ++k)
-            if (k < ng && o < L.gkey[t][k]) shift[k] += 1;
+            if (o < L.gkey[t][k]) shift[k] += 1;
     }
 #pragma unroll
-    for (int k = 0; k < NDIR; ++k)
-        if (k < ng) L.gstart[t][k] += shift[k];
+    for (int k = 0; k < NDIR; ++k) L.gstart[t][k] += shift[k];
     if (found != nfin) atomicOr(&a.K().ctr->status, ST_INTERNAL);
     a.farcnt_in()[c] = 0;
 }
@@ -216,7 +221,7 @@ __device__ void tile_far_shift_scan(const StepArgs &a, TileLds<TC, CH, S> &L, in
                 found[u] += 1;
 #pragma unroll
                 for (int k = 0; k < NDIR; ++k)
-                    if (k < L.ng[u] && o < L.gkey[u][k]) shift[u][k] += 1;
+                    if (o < L.gkey[u][k]) shift[u][k] += 1;
             }
         }
     }
@@ -235,8 +240,7 @@ __device__ void tile_far_shift_scan(const StepArgs &a, TileLds<TC, CH, S> &L, in
     for (int t = 0; t < TC; ++t) {
         if (t != lane || t >= ntc) continue;
 #pragma unroll
-        for (int k = 0; k < NDIR; ++k)
-            if (k < L.ng[t]) L.gstart[t][k] += shift[t][k];
+        for (int k = 0; k < NDIR; ++k) L.gstart[t][k] += shift[t][k];
         if (found[t] != nfin) atomicOr(&a.K().ctr->status, ST_INTERNAL);
         if (nfin > 0) a.farcnt_in()[c0 + t] = 0;
     }
@@ -247,7 +251,7 @@ template <int TC, int CH, class S>
 __device__ __forceinline__ int near_before(const TileLds<TC, CH, S> &L, int t, int o)
 {
     int r = 0;
-    for (int k = 0; k < L.ng[t]; ++k)
+    for (int k = 0; k < NDIR; ++k)
         if (L.gkey[t][k] < o) r += L.gn[t][k];
     return r;
 }
@@ -346,85 +350,43 @@ __device__ void tile_far_gather(const StepArgs &a, const TileLds<TC, CH, S> &L, 
     }
 }
 
-// near group (source cell, size, first source slot) of lane t * NDIR + d:
-// move d into tile cell t; the partitioned state makes it the run
-// grp[s][d] .. grp[s][d+1] of source cell s
-template <int TC>
-__device__ __forceinline__ void tile_raw_group(const StepArgs &a, int c0, int ntc, int lane, int &s, int &n, int &src)
-{
-    s = -1;
-    n = 0;
-    src = 0;
-    if (lane >= TC * NDIR) return;
-    const int t = lane / NDIR, d = lane - t * NDIR;
-    if (t >= ntc) return;
-    const int cb = a.R().cbase, nx = a.R().G.nx;
-    const int c = c0 + t - cb, ciy = c / nx, cix = c - ciy * nx;
-    const int sc = source_cell(nx, a.R().G.ny, cix, ciy, d);  // inside the channel
-    if (sc < 0) return;
-    const int32_t *g = a.grp_in() + (size_t)(cb + sc) * GSTRIDE + d;
-    src = g[0];
-    n = g[1] - g[0];
-    if (n > 0) s = cb + sc;
-}
-
 // The groups arriving in every cell of the tile, in the order of the stable
 // sort: by source cell, each group in source-slot order.  The state read
 // here keeps every old cell's particles partitioned by move direction, so a
 // near group (source cell s, direction d) is the contiguous run that starts
-// after the groups 0 .. d-1 of s.
+// after the groups 0 .. d-1 of s; the cell pass before the step wrote each
+// cell's plan: the first source slot and the offset inside the cell of its 9
+// near groups in sorted order (plan[c][0..8] and plan[c][9..17]), loaded with
+// the tile's other per-cell data.  Where long jumps arrive (rare), the
+// groups' source cells and sizes are rebuilt and every group preceded by long
+// jumps from smaller source cells is shifted.
 template <int TC, int CH, class S>
 __device__ void tile_groups(const StepArgs &a, TileLds<TC, CH, S> &L, int ntc, int nfin)
 {
     const int lane = threadIdx.x, nx = a.geo().nx;
-    // L.raw holds the near groups (filled with the tile's other loads)
-    if (lane < TC * NDIR) {
-        const int t = lane / NDIR, d = lane - t * NDIR;
-        const int s = L.raw[0][lane];
-        int rank = 0, pre = 0, ng = 0;
-#pragma unroll
-        for (int e = 0; e < NDIR; ++e) {
-            const int se = L.raw[0][t * NDIR + e];
-            const bool before = se >= 0 && se < s;
-            ng += se >= 0 ? 1 : 0;
-            rank += before ? 1 : 0;
-            pre += before ? L.raw[1][t * NDIR + e] : 0;
-        }
-        if (s >= 0) {
-            L.gkey[t][rank] = s;
-            L.gn[t][rank] = L.raw[1][lane];
-            L.gsrc[t][rank] = L.raw[2][lane];
-            L.gstart[t][rank] = pre;
-        }
-        if (d >= ng) {  // padding; position 0 of a cell without groups too
-            L.gkey[t][d] = INT_MAX;
-            L.gn[t][d] = 0;
-            L.gsrc[t][d] = 0;
-            L.gstart[t][d] = d == 0 ? 0 : INT_MAX;
-        }
-    }
-    if (lane < TC) {
-        int ng = 0, tot = 0;
-        for (int e = 0; e < NDIR; ++e) {
-            if (L.raw[0][lane * NDIR + e] >= 0) {
-                ++ng;
-                tot += L.raw[1][lane * NDIR + e];
-            }
-        }
-        L.ng[lane] = ng;
-        if (lane < ntc && tot + nfin != L.csn[lane + 1] - L.csn[lane]) atomicOr(&a.K().ctr->status, ST_INTERNAL);
-    }
+    if (lane < TC) L.nfin[lane] = nfin;
     if (lane == 0) L.anyfar = 0;
     __syncthreads();
-    if (ballot64(lane < ntc && nfin > 0) != 0) {  // long jumps arrive in the tile (rare)
-        if (far_listed(a)) {
-            if (lane < ntc && nfin > 0)
-                tile_far_shift<TC, CH, S>(a, L, lane, a.R().cbase + L.tiy[lane] * nx + L.tix[lane], nfin);
-        } else {
-            tile_far_shift_scan<TC, CH, S>(a, L, a.R().cbase + L.tiy[0] * nx + L.tix[0], ntc, nfin);
-        }
-        if (lane == 0) L.anyfar = 1;
+    if (ballot64(lane < ntc && nfin > 0) == 0) return;  // no long jumps arrive in the tile
+    if (lane < TC * NDIR) {
+        const int t = lane / NDIR, k = lane - t * NDIR;
+        int key[NDIR], dir[NDIR];
+        arrival_order(nx, a.geo().ny, L.tix[t], L.tiy[t], a.R().cbase, key, dir);
+        int kk = 0;
+#pragma unroll
+        for (int u = 0; u < NDIR; ++u) kk = u == k ? key[u] : kk;
+        L.gkey[t][k] = kk;
+        const int end = k + 1 < NDIR ? L.gstart[t][k + 1] : L.csn[t + 1] - L.csn[t] - L.nfin[t];
+        L.gn[t][k] = t < ntc ? end - L.gstart[t][k] : 0;
     }
+    __syncthreads();
+    if (far_listed(a)) {
+        if (lane < ntc && nfin > 0)
+            tile_far_shift<TC, CH, S>(a, L, lane, a.R().cbase + L.tiy[lane] * nx + L.tix[lane], nfin);
+    } else {
+        tile_far_shift_scan<TC, CH, S>(a, L, a.R().cbase + L.tiy[0] * nx + L.tix[0], ntc, nfin);
+    }
+    if (lane == 0) L.anyfar = 1;
     __syncthreads();
 }
 
@@ -728,7 +690,7 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
             if (i < nt) {
                 if (GATHER) {
                     const int t = tile_cell<TC, CH, S>(L, ntc, D0, i);
-                    src = tile_source<TC, CH, S>(L, t, i - (L.csn[t] - D0));
+                    src = tile_source<TC, CH, S>(L, t, i - (L.csn[t] - D0), L.anyfar != 0);
                     if (src >= n_old) {
                         src = -1;
                         atomicOr(&a.K().ctr->status, ST_INTERNAL);
@@ -791,7 +753,7 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
     } else if (GATHER) {
         for (int i = lane; i < nt; i += 64) {
             const int t = tile_cell<TC, CH, S>(L, ntc, D0, i);
-            const int src = tile_source<TC, CH, S>(L, t, i - (L.csn[t] - D0));
+            const int src = tile_source<TC, CH, S>(L, t, i - (L.csn[t] - D0), L.anyfar != 0);
             if (src >= n_old) atomicOr(&a.K().ctr->status, ST_INTERNAL);
             if (src < 0 || src >= n_old) continue;
 #pragma unroll
@@ -1017,12 +979,16 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     const int n_old = GATHER ? a.cs_old()[nc] : 0;
     // running counters of the tile, kept at its first cell (valid for any tiling)
     unsigned long long *const tst = a.K().tstat + 3 * (size_t)c0 + (lane < 3 ? lane : 0);
-    if (GATHER && lane < TC * NDIR) {
-        int s, n, src;
-        tile_raw_group<TC>(a, c0, ntc, lane, s, n, src);
-        L.raw[0][lane] = s;
-        L.raw[1][lane] = n;
-        L.raw[2][lane] = src;
+    if (GATHER) {  // the tile's cells' plans (see tile_groups), in the same round of loads
+#pragma unroll
+        for (int e = lane; e < TC * 2 * NDIR; e += 64) {
+            const int t = e / (2 * NDIR), f = e - t * (2 * NDIR);
+            const int v = t < ntc ? a.K().plan[(size_t)(c0 + t) * (2 * NDIR) + f] : 0;
+            if (f < NDIR)
+                L.gsrc[t][f] = v;
+            else
+                L.gstart[t][f - NDIR] = v;
+        }
     }
     __syncthreads();
     if (GATHER) tile_groups<TC, CH, S>(a, L, ntc, nfin);
@@ -1039,13 +1005,20 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
         tile_body<TC, CH, S, GATHER, MOVE, false, NT>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev,
                                                mdst, ncoll, ncand, walls, limit);
 
-    // the tile's running counters.  Every tile owns its entry; the add is an
-    // atomic without return only so that the wave need not wait for a read,
-    // which would queue behind all of the tile's stores
-    ncoll = wave_sum_u64(ncoll);
-    ncand = wave_sum_u64(ncand);
-    const unsigned long long wsum = wave_sum_u64((unsigned long long)walls);
-    if (lane < 3) atomicAdd(tst, lane == 0 ? ncoll : (lane == 1 ? ncand : wsum));
+    // the tile's running counters.  Collisions and candidates were counted by
+    // the lanes that ran the cells' collisions (lanes below TC); wall hits on
+    // any lane, and in most tiles on none.  Every tile owns its entry; the
+    // add is an atomic without return only so that the wave need not wait for
+    // a read, which would queue behind all of the tile's stores.
+    unsigned long long tcoll = 0, tcand = 0, twall = 0;
+#pragma unroll
+    for (int u = 0; u < TC; ++u) {
+        tcoll += lane_u64(ncoll, u);
+        tcand += lane_u64(ncand, u);
+    }
+    if (ballot64(walls != 0) != 0) twall = wave_sum_u64((unsigned long long)walls);
+    const unsigned long long tadd = lane == 0 ? tcoll : (lane == 1 ? tcand : twall);
+    if (lane < 3 && tadd != 0) atomicAdd(tst, tadd);
     if (MOVE && ballot64(limit) != 0 && lane == 0) atomicOr(&a.K().ctr->status, ST_WALL_LIMIT);
 }
 
@@ -1091,7 +1064,11 @@ DSMC_TILE_INSTANCES(2, 8, float)
 DSMC_TILE_INSTANCES(1, 8, float)
 #undef DSMC_TILE_INSTANCES
 
-// particles arriving in every cell with the step's sort, and their block sums
+// Particles arriving in every cell with the step's sort, their block sums,
+// and the cell's plan for the step kernel: its 9 near groups in the order of
+// the stable sort (by source cell, sources beyond a wall or aliased last and
+// empty), plan[c][k] the first source slot and plan[c][9 + k] the offset
+// inside the cell of the k-th (long jumps not counted: the step shifts them)
 __global__ __launch_bounds__(256) void k_cell_count(CellArgs a)
 {
     __shared__ int lds[4];
@@ -1106,11 +1083,20 @@ __global__ __launch_bounds__(256) void k_cell_count(CellArgs a)
             cb = R.cbase;
         }
         const int cix = (c - cb) % nx, ciy = (c - cb) / nx;
+        int key[NDIR], dir[NDIR];
+        arrival_order(nx, ny, cix, ciy, cb, key, dir);
+        int32_t *const pl = a.plan + (size_t)c * (2 * NDIR);
 #pragma unroll
-        for (int d = 0; d < NDIR; ++d) {
-            const int src = source_cell(nx, ny, cix, ciy, d);  // inside the channel
-            if (src >= 0)
-                total += a.grp[(size_t)(cb + src) * GSTRIDE + d + 1] - a.grp[(size_t)(cb + src) * GSTRIDE + d];
+        for (int k = 0; k < NDIR; ++k) {
+            int first = 0, n = 0;
+            if (key[k] != 0x7fffffff) {
+                const int32_t *g = a.grp + (size_t)key[k] * GSTRIDE + dir[k];
+                first = g[0];
+                n = g[1] - g[0];
+            }
+            pl[k] = first;
+            pl[NDIR + k] = total;
+            total += n;
         }
         total += a.farcnt[c];
         a.countnew[c] = total;

@@ -48,6 +48,7 @@ struct TileConst {
     int32_t *grp[2];         // [ncells][GSTRIDE] first slot of every group and the cell end, by step parity
     int32_t *far[2];         // long-jump lists, by step parity
     int32_t *farcnt[2];      // [ncells] long jumps arriving per cell, by step parity
+    const int32_t *plan;     // [ncells][2 * NDIR] arriving near groups of the step (see k_cell_count)
     double *scr;             // [capacity] scratch of oversized tiles
     int32_t *scr_i;          // [capacity] scratch of oversized tiles
     Counters *ctr;
@@ -147,6 +148,7 @@ struct StepArgs {
 
 struct CellArgs {
     const int32_t *grp;      // [ncells][GSTRIDE] group starts and cell end of the moved state
+    int32_t *plan;           // [ncells][2 * NDIR] out: each cell's arriving near groups, in sorted order
     const int32_t *farcnt;   // [ncells] long jumps arriving per cell
     int32_t *countnew;
     int32_t *blocksum;
