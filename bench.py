@@ -20,8 +20,15 @@ Printed JSON line: metric, value, ..., plus
             scaled by what the counters read for a plain 1 GiB copy), taken
             from the committed summary under profiles/ while the kernel
             sources are unchanged since it was made, else null;
-  cpu_baseline: the FP64 oracle timed on this host on one cycle of the same
-            workload (single-threaded);
+  cpu_baseline: the FP64 oracle timed on this host on a few cycles of the
+            same workload, built with OpenMP on all the cores OpenMP is
+            given (value, cores) and single-threaded (the parity build),
+            with the core count and CPU model of the host;
+  c1:       the quasi-1-D Poiseuille channel (1 x 64 cells, 50 particles per
+            cell, Kn 0.1, seed 1) run in full: 2000 DSMC steps sampled every
+            step with the D2Q9 projection of the cumulative averages every
+            10 steps, on the GPU and, beside it, with the oracle (both
+            builds); the final populations of the two are compared;
   adjoint:  the gradient of the coupling-node moment mismatch with respect to
             the body force and the relaxation time (and to the initial
             populations and the DSMC moment averages) on a D2Q37 1024 x 512
@@ -45,13 +52,15 @@ Printed JSON line: metric, value, ..., plus
             the full projection: cycles per second, and the velocity profiles
             at x = L0/4 (DSMC), the buffer layer and x = 3 L0/4 (lattice);
   precision: the FP32-state form against plain FP64 on a 2048 x 1024 x 50
-            channel (Kn 0.02, Ma 0.1): particle-steps/s of each, and per
-            moment order the RMS and mean over cells of z = (m32 - m64) / SE,
-            m the time-averaged Hermite moments of each run and SE their
-            sampling error under the Maxwellian (consecutive steps counted as
-            independent, which overstates z), beside the same z between two
-            FP64 runs of different seeds: the FP32 form's moment error is
-            stated against that sampling noise.
+            channel (Kn 0.02, Ma 0.1), 500 steps sampled every step in 20
+            batches of 25: particle-steps/s of each, and per moment order
+            the RMS and mean over cells of z = dm / SE, dm the difference of
+            the time-averaged Hermite moments of FP32 (seed 5) and FP64
+            (seed 4), SE from batch means (paired, per run combined, and of
+            the FP64 run alone), beside the same z of FP64 (seed 5) against
+            the same FP64 run -- the sampling noise -- and the values z takes
+            without any error; the batch-means SE is also set against the SE
+            of independent steps, and against that of batches twice as long.
 """
 from __future__ import annotations
 
@@ -74,11 +83,13 @@ STEPS_PER_CYCLE, STRIP = 10, 16
 
 # algorithmic bytes per unit (FP64): a particle is 5 doubles = 40 B
 BYTES = {
-    # one DSMC step: read the moved state once and write it once (80 B per
-    # particle); per cell the cell_start pair (8 B), the group sizes read and
-    # written (40 + 40 B), the NTC state nbar/sigcmax/rem read + written
-    # (48 B) and the 11 moment sums read + written (176 B, sampling every step)
-    "step": (80.0, 8 + 80 + 48 + 176),
+    # one DSMC step: read the state once and write it once (80 B per
+    # particle); per cell the cell_start pair (8 B), the NTC state
+    # nbar/sigcmax/rem read + written (48 B) and the 11 moment sums read +
+    # written (176 B, sampling every step).  The library's own per-cell
+    # bookkeeping (its gather tables) is not counted: it is how this
+    # implementation moves particles, not what the method must move.
+    "step": (80.0, 8 + 48 + 176),
     # the move of a settled state, in place: read + write the state, write
     # the group sizes
     "classify": (80.0, 4 + 40),
@@ -87,11 +98,11 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_512x256x100_fp64_traffi
 TRACE_SUMMARY = os.path.join(ROOT, "profiles", "dsmc_cycle_512x256x100_fp64_kernel_trace.md")
 # the commands whose output the summaries condense (run from the repository root)
 TRACE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace -o trace -- "
-             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-precision --no-adjoint --no-batched --no-hybrid")
+             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-precision --no-adjoint --no-batched --no-hybrid --no-c1")
 PMC_CMDS = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --no-hybrid --copy-calibration",
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --no-hybrid --no-c1 --copy-calibration",
             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --no-hybrid --copy-calibration")
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --no-hybrid --no-c1 --copy-calibration")
 # kernel-name prefixes of the library's kernels, by profiling id
 KERNEL_PREFIX = {"step": "void dsmc::k_step<", "classify": "void dsmc::k_classify<"}
 ADJ_TRACE_SUMMARY = os.path.join(ROOT, "profiles", "lbm_adjoint_1024x512_d2q37_kernel_trace.md")
@@ -103,78 +114,227 @@ ADJ_PMC_CMDS = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/ad
                 "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/adj_write -o write -- "
                 "python3 bench.py --adjoint-only --copy-calibration")
 ADJ_KERNEL_PREFIX = {"lbm_adjoint": "void dsmc::k_lbm_adjoint<", "lbm_step": "void dsmc::k_lbm<"}
+# the precision workload's two state widths, a few steps each, and the batched
+# workload's steps (profiled apart from the timed runs)
+C4_TRACE_SUMMARY = os.path.join(ROOT, "profiles", "k_step_2048x1024x50_fp32_fp64_kernel_trace.md")
+C4_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_2048x1024x50_fp32_fp64_traffic.md")
+C4_TRACE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/c4_trace -o trace -- "
+                "python3 bench.py --profile-c4")
+C4_PMC_CMDS = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/c4_fetch -o fetch -- "
+               "python3 bench.py --profile-c4 --copy-calibration",
+               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/c4_write -o write -- "
+               "python3 bench.py --profile-c4 --copy-calibration")
+C4_KERNEL_PREFIX = {"step_fp64": ("void dsmc::k_step<", "double"), "step_fp32": ("void dsmc::k_step<", "float"),
+                    "classify_fp64": ("void dsmc::k_classify<", "double"),
+                    "classify_fp32": ("void dsmc::k_classify<", "float")}
+BAT_TRACE_SUMMARY = os.path.join(ROOT, "profiles", "k_step_batched_256_replicas_kernel_trace.md")
+BAT_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_batched_256_replicas_traffic.md")
+BAT_TRACE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/bat_trace -o trace -- "
+                 "python3 bench.py --profile-batched")
+BAT_PMC_CMDS = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/bat_fetch -o fetch -- "
+                "python3 bench.py --profile-batched --copy-calibration",
+                "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/bat_write -o write -- "
+                "python3 bench.py --profile-batched --copy-calibration")
 
 
-# the precision workload (FP32 state vs FP64)
-PREC = dict(nx=2048, ny=1024, ppc=50, kn=0.02, mach=0.1, seed=4)
-PREC_WARM, PREC_STEPS = 20, 100
+# the precision workload (FP32 state vs FP64): 500 steps sampled every step,
+# in 20 batches of 25 steps whose per-cell means give the standard errors
+PREC = dict(nx=2048, ny=1024, ppc=50, kn=0.02, mach=0.1)
+PREC_SEED_REF, PREC_SEED_ALT = 4, 5
+PREC_BATCHES, PREC_BATCH_STEPS = 20, 25
 # Hermite components per order: (sum indices, unit-Maxwellian variance), from
 # the 11 per-cell sums N, x, y, xx, xy, yy, xxx, xxy, xyy, yyy, zz
 HERMITE = {1: [((1,), 1.0), ((2,), 1.0)],
            2: [((3, -1), 2.0), ((4,), 1.0), ((5, -1), 2.0)],
            3: [((6, 1, -3), 6.0), ((7, 2, -1), 2.0), ((8, 1, -1), 2.0), ((9, 2, -3), 6.0)]}
+# rows of the per-cell Hermite stack: order of each row and its variance
+HROWS = [(0, None)] + [(o, var) for o, comps in HERMITE.items() for _, var in comps]
 
 
-def _moment_z(a, b, steps):
-    """Per moment order: z = (m_a - m_b) / SE over cells (and components)."""
-    import numpy as np
+def _hermite_stack(avg):
+    """[10][ncells] per-cell Hermite moments of one batch from its 11 averaged
+    sums: the mean count, then per order the velocity Hermite components
+    (per-particle means, in units of sqrt(kT/m))."""
+    import torch
 
-    N = 0.5 * (a[0] + b[0])
-    ok = N > 0
-    S = float(steps)
-    z = {0: (a[0] - b[0])[ok] / np.sqrt(N[ok] / S)}
-    for order, comps in HERMITE.items():
-        zs = []
-        for idx, var in comps:
-            def hermite(m):
-                inv = 1.0 / np.where(m[0] > 0, m[0], 1.0)
-                h = m[idx[0]] * inv
-                if len(idx) == 2:  # x_i x_j - delta_ij
-                    h = h + idx[1]
-                elif len(idx) == 3:  # cubic - c * linear
-                    h = h + idx[2] * m[idx[1]] * inv
-                return h
-            se = np.sqrt(var / (N * S))
-            zs.append(((hermite(a) - hermite(b)) / se)[ok])
-        z[order] = np.concatenate(zs)
-    return {str(k): {"rms": round(float(np.sqrt(np.mean(v ** 2))), 3), "mean": round(float(np.mean(v)), 3)}
-            for k, v in z.items()}
+    n = avg[0]
+    inv = 1.0 / torch.where(n > 0, n, torch.ones_like(n))
+    rows = [n]
+    for comps in HERMITE.values():
+        for idx, _ in comps:
+            h = avg[idx[0]] * inv
+            if len(idx) == 2:  # x_i x_j - delta_ij
+                h = h + idx[1]
+            elif len(idx) == 3:  # cubic - c * linear
+                h = h + idx[2] * avg[idx[1]] * inv
+            rows.append(h)
+    return torch.stack(rows)
 
 
-def precision_comparison():
-    """FP32-state vs FP64 on the precision workload: rates and moment error,
-    beside the seed-to-seed difference of two FP64 runs (the sampling noise)."""
+def _precision_run(bits, seed):
+    """One run of the precision workload: its per-batch Hermite stacks
+    ([batches][rows][cells], on the GPU) and its stepping rate."""
     import torch
 
     from paper_1512_08042_amd import ChannelConfig
     from paper_1512_08042_amd import dsmc as D
 
-    res, avgs = {}, {}
-    n = PREC["nx"] * PREC["ny"] * PREC["ppc"]
-    for bits, seed in ((64, PREC["seed"]), (32, PREC["seed"]), (64, PREC["seed"] + 1)):
-        cfg = dict(PREC)
-        cfg["seed"] = seed
-        ch = D.Channel(ChannelConfig(state_bits=bits, **cfg))
-        ch.step(PREC_WARM)
-        ch.reset_moments()
+    ch = D.Channel(ChannelConfig(state_bits=bits, seed=seed, **PREC))
+    n = ch.status()["n"]
+    batches, t_step = [], 0.0
+    for _ in range(PREC_BATCHES):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ch.step(PREC_STEPS, sample_every=1)
+        ch.step(PREC_BATCH_STEPS, sample_every=1)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        if seed == PREC["seed"]:
-            res["fp%d_particle_steps_per_s" % bits] = n * PREC_STEPS / (t1 - t0)
-        avgs[(bits, seed)] = ch.sample_moments().cpu().numpy()
+        t_step += time.perf_counter() - t0
+        batches.append(_hermite_stack(ch.sample_moments(reset=True)))
+    ch.close()
+    del ch
+    torch.cuda.empty_cache()
+    return torch.stack(batches), n * PREC_BATCHES * PREC_BATCH_STEPS / t_step
+
+
+def _z_stats(a, b):
+    """Per moment order, z of the time-averaged per-cell moments of runs a and
+    b (each [batches][rows][cells]) under three standard errors:
+      paired:   the batch means of the differences d_k = a_k - b_k,
+                z = mean(d) / (sd(d) / sqrt(B)) (Student t, B - 1 dof);
+      combined: each run's own batch-means SE, z = dm / sqrt(SE_a^2 + SE_b^2);
+      single:   the SE of run b alone, z = dm / SE_b (for two independent
+                runs without error, RMS z = sqrt(2) times the t inflation)."""
+    import math
+
+    import torch
+
+    B = a.shape[0]
+    d = a - b
+    dm = d.mean(0)
+    se_pair = d.std(0) / math.sqrt(B)
+    se_a, se_b = a.std(0) / math.sqrt(B), b.std(0) / math.sqrt(B)
+    ok = (a[:, 0] > 0).all(0) & (b[:, 0] > 0).all(0)
+    out = {}
+    for order in range(4):
+        rows = [i for i, (o, _) in enumerate(HROWS) if o == order]
+        r = {}
+        for name, se in (("paired", se_pair), ("combined", torch.sqrt(se_a ** 2 + se_b ** 2)), ("single", se_b)):
+            z = (dm[rows] / se[rows])[:, ok].flatten()
+            z2 = z * z
+            rms = float(torch.sqrt(z2.mean()))
+            # uncertainty of the RMS from the spread of z^2 over cells
+            unc = float(z2.std() / math.sqrt(z2.numel())) / (2.0 * rms)
+            r[name] = {"rms": round(rms, 4), "rms_unc": round(unc, 4), "mean": round(float(z.mean()), 4)}
+        r["n"] = int(ok.sum()) * len(rows)
+        out[str(order)] = r
+    return out
+
+
+def _se_calibration(a):
+    """For one run: per order, the mean over cells of its batch-means SE over
+    the SE of independent steps (variance / (N S), the sampling noise of
+    Section 5 with consecutive steps counted as independent), and of the SE
+    from batches twice as long over that from the batches used."""
+    import math
+
+    import torch
+
+    B = a.shape[0]
+    S = B * PREC_BATCH_STEPS
+    se = a.std(0) / math.sqrt(B)
+    a2 = 0.5 * (a[0::2] + a[1::2])
+    se2 = a2.std(0) / math.sqrt(B // 2)
+    N = a[:, 0].mean(0)
+    ok = (a[:, 0] > 0).all(0)
+    out = {}
+    for order in range(4):
+        rows = [i for i, (o, _) in enumerate(HROWS) if o == order]
+        fr = []
+        for i in rows:
+            var = HROWS[i][1]
+            f = torch.sqrt(N / S) if var is None else torch.sqrt(var / (N * S))
+            fr.append((se[i] / f)[ok])
+        out[str(order)] = {"se_batch_over_independent_steps": round(float(torch.cat(fr).mean()), 3),
+                           "se_batch50_over_batch25": round(float((se2[rows] / se[rows])[:, ok].mean()), 3)}
+    return out
+
+
+def profile_c4():
+    """8 sampled steps of the precision workload per state width (FP64, then
+    FP32): the run the C4 summaries profile.  Returns the step times."""
+    import torch
+
+    from paper_1512_08042_amd import ChannelConfig
+    from paper_1512_08042_amd import dsmc as D
+
+    out = {}
+    for bits in (64, 32):
+        ch = D.Channel(ChannelConfig(state_bits=bits, seed=PREC_SEED_REF, **PREC))
+        ch.step(2, sample_every=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.step(6, sample_every=1)
+        torch.cuda.synchronize()
+        out["fp%d_ms_per_step" % bits] = round(1e3 * (time.perf_counter() - t0) / 6, 4)
+        ch.close()
         del ch
         torch.cuda.empty_cache()
-    out = {"workload": "2048x1024 cells x 50 particles/cell, Kn 0.02, Ma 0.1; %d warm-up steps, %d sampled steps; "
-                       "FP32 and FP64 from seed %d, a second FP64 run from seed %d" %
-                       (PREC_WARM, PREC_STEPS, PREC["seed"], PREC["seed"] + 1)}
-    out.update({k: float("%.4g" % v) for k, v in res.items()})
-    out["fp32_speedup"] = round(res["fp32_particle_steps_per_s"] / res["fp64_particle_steps_per_s"], 3)
-    s0, s1 = PREC["seed"], PREC["seed"] + 1
-    out["moment_z_by_order"] = {"fp32_vs_fp64": _moment_z(avgs[(32, s0)], avgs[(64, s0)], PREC_STEPS),
-                                "fp64_seed_to_seed": _moment_z(avgs[(64, s1)], avgs[(64, s0)], PREC_STEPS)}
+    return out
+
+
+def profile_batched():
+    """The batched workload's autotuner steps and 10 steps under its choice:
+    the run the batched summaries profile."""
+    import torch
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import inputs
+
+    from paper_1512_08042_amd import dsmc as D
+
+    B = BATCH
+    reps = inputs.replica_params(B["seed"], B["nrep"])
+    for r in reps:
+        r["mach"] = B["mach"]
+    b = D.Batch(reps)
+    tune = b.autotune(B["tune_steps"], 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(10, 1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = b.status()["n"]
+    b.close()
+    return {"chosen": tune["chosen"], "ms_per_step": round(1e3 * dt / 10, 4), "particles": n}
+
+
+def precision_comparison():
+    """FP32-state vs FP64 on the precision workload: rates, and the moment
+    error of FP32 (seed 5) against FP64 (seed 4) beside that of FP64 (seed 5)
+    against the same FP64 run: the sampling noise the FP32 error is stated
+    against.  Standard errors from batch means."""
+    import math
+
+    ref, v64 = _precision_run(64, PREC_SEED_REF)
+    alt64, _ = _precision_run(64, PREC_SEED_ALT)
+    z64 = _z_stats(alt64, ref)
+    calib = _se_calibration(ref)
+    del alt64
+    alt32, v32 = _precision_run(32, PREC_SEED_ALT)
+    z32 = _z_stats(alt32, ref)
+    del alt32, ref
+    B = PREC_BATCHES
+    t_infl = math.sqrt((B - 1) / (B - 3))
+    out = {"workload": "2048x1024 cells x 50 particles/cell (104,857,600 particles), Kn 0.02, Ma 0.1, from the "
+                       "Maxwellian start; %d steps sampled every step, in %d batches of %d; FP64 seed %d (reference), "
+                       "FP64 seed %d, FP32 state seed %d" % (B * PREC_BATCH_STEPS, B, PREC_BATCH_STEPS,
+                                                             PREC_SEED_REF, PREC_SEED_ALT, PREC_SEED_ALT),
+           "fp64_particle_steps_per_s": float("%.4g" % v64),
+           "fp32_particle_steps_per_s": float("%.4g" % v32),
+           "fp32_speedup": round(v32 / v64, 3),
+           "moment_z_by_order": {"fp32_seed5_vs_fp64_seed4": z32, "fp64_seed5_vs_fp64_seed4": z64},
+           "expected_rms_z_without_error": {"paired": round(t_infl, 4), "combined": round(
+               math.sqrt((2 * B - 2) / (2 * B - 4)), 4), "single": round(math.sqrt(2.0) * t_infl, 4)},
+           "se_calibration_fp64_seed4": calib}
     return out
 
 
@@ -379,9 +539,20 @@ def batched_comparison():
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     same = 0
+    zsq = {o: [0.0, 0] for o in range(4)}
     for i, c in enumerate(chans):
         c0, c1 = b.replica_cells(i)
-        eq = np.array_equal(c.sample_moments().cpu().numpy(), avg_b[:, c0:c1])
+        avg_p = c.sample_moments()
+        # per-order z of the batched form against the plain one, SE of the
+        # time averages with steps counted as independent
+        hb = _hermite_stack(torch.from_numpy(avg_b[:, c0:c1]).to(avg_p.device))
+        hp = _hermite_stack(avg_p)
+        N = hp[0].clamp(min=1.0)
+        for row, (order, var) in enumerate(HROWS):
+            se = torch.sqrt((N if var is None else var / N) / steps_timed)
+            zsq[order][0] += float((((hb[row] - hp[row]) / se) ** 2).sum())
+            zsq[order][1] += int(N.numel())
+        eq = np.array_equal(avg_p.cpu().numpy(), avg_b[:, c0:c1])
         eq = eq and all(torch.equal(p, q) for p, q in zip(c.particles(), b.replica_particles(i)))
         same += int(eq)
         c.close()
@@ -406,6 +577,7 @@ def batched_comparison():
                      "seconds": round(t_tune, 3)},
         "replicas_bitwise_equal_to_plain": "%d/%d (particles, and moment sums over the %d timed steps)" % (
             same, B["nrep"], steps_timed),
+        "moment_z_by_order_vs_plain_fp64": {str(o): round((v[0] / max(v[1], 1)) ** 0.5, 6) for o, v in zsq.items()},
         "step_roofline_frac": round(80.0 * v_b / 1e9 / HBM_PEAK_GBPS, 4),
         "status_bits": st["bits"],
     }
@@ -542,7 +714,28 @@ SUMMARIES = {
         note=["Each gradient: the DSMC2LB projection, 200 forward steps (every 20th keeps a checkpoint), the",
               "Hermite coefficients and their adjoint, then per 20-step segment 19 recomputed forward steps and",
               "20 adjoint steps; the bench also times the two lattice kernels alone and runs central differences."]),
+    "c4": dict(
+        title="DSMC steps, 2048x1024 cells x 50 particles/cell (104,857,600 particles), FP64 and FP32 state",
+        trace_cmd=C4_TRACE_CMD, pmc_cmds=C4_PMC_CMDS, prefixes=C4_KERNEL_PREFIX,
+        trace_file=C4_TRACE_SUMMARY, traffic_file=C4_TRAFFIC_SUMMARY,
+        note=["Per state width: one channel from its Maxwellian start (Kn 0.02, Ma 0.1, seed 4), 8 DSMC steps",
+              "sampled every step (k_classify once, then cell kernels + k_step per step), FP64 first."]),
+    "batched": dict(
+        title="256 channel replicas stepped together (about 7.55 million particles), FP64",
+        trace_cmd=BAT_TRACE_CMD, pmc_cmds=BAT_PMC_CMDS, prefixes=KERNEL_PREFIX,
+        trace_file=BAT_TRACE_SUMMARY, traffic_file=BAT_TRAFFIC_SUMMARY,
+        note=["The batched workload (nx 1, ny U{32..512}, ppc U{20..200}, Kn log-U[0.01,1], Ma 0.1, seeds",
+              "1000+r): the autotuner's 8 steps over four tilings, then 10 steps under the tiling it chose,",
+              "sampled every step."]),
 }
+
+
+def _kernel_of(name, spec):
+    """Whether kernel `name` belongs to a profiling id: a name prefix, or a
+    (prefix, text the name must also hold) pair."""
+    if isinstance(spec, tuple):
+        return name.startswith(spec[0]) and spec[1] in name
+    return name.startswith(spec)
 
 
 def summarize(which, trace_dir, fetch_dir, write_dir):
@@ -562,7 +755,7 @@ def summarize(which, trace_dir, fetch_dir, write_dir):
     out.append("Mean duration per profiling id (all template variants, weighted by calls):")
     out.append("")
     for kid, pre in sorted(W["prefixes"].items()):
-        calls = [(float(r["Calls"]), float(r["AverageNs"])) for r in stats if r["Name"].startswith(pre)]
+        calls = [(float(r["Calls"]), float(r["AverageNs"])) for r in stats if _kernel_of(r["Name"], pre)]
         if calls:
             n = sum(c for c, _ in calls)
             out.append("mean_us %s: %.1f" % (kid, sum(c * a for c, a in calls) / n / 1e3))
@@ -599,7 +792,7 @@ def summarize(which, trace_dir, fetch_dir, write_dir):
         mb = (mf * f_fetch + mw * f_write) * 1024 / 1e6
         out.append("| `%s` | %d | %.0f | %.0f | %.1f |" % (name, len(fetch[name]), mf, mw, mb))
         for kid, pre in W["prefixes"].items():
-            if name.startswith(pre):
+            if _kernel_of(name, pre):
                 per_id.setdefault(kid, []).extend(
                     [(a * f_fetch + b * f_write) * 1024 for a, b in zip(fetch[name], write[name])])
     out.append("")
@@ -620,7 +813,10 @@ def _parse():
     ap.add_argument("--steps", type=int, default=20, help="timed coupling cycles")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=8, help="coupling cycles the CPU oracle is timed on")
+    ap.add_argument("--cpu-cycles", type=int, default=8, help="coupling cycles the OpenMP oracle is timed on")
+    ap.add_argument("--cpu-cycles-single", type=int, default=2,
+                    help="coupling cycles the single-threaded oracle is timed on")
+    ap.add_argument("--no-c1", action="store_true", help="skip the quasi-1-D channel run")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32-vs-FP64 comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-replica workload")
@@ -637,18 +833,47 @@ def _parse():
                     help="write the profiles/ summaries from rocprofv3 output directories and exit")
     ap.add_argument("--summarize-adjoint", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="the same for the differentiation workload")
+    ap.add_argument("--summarize-c4", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="the same for the precision workload's steps (--profile-c4)")
+    ap.add_argument("--summarize-batched", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="the same for the batched workload's steps (--profile-batched)")
+    ap.add_argument("--profile-c4", action="store_true",
+                    help="run only a few precision-workload steps in FP64 and FP32 state (for rocprofv3)")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="run only a few batched-workload steps (for rocprofv3)")
     return ap.parse_args()
 
 
-def cpu_baseline(strip, cycles):
-    """`cycles` coupling cycles of the same workload with the FP64 oracle on the host."""
+def _host():
+    """Cores this process may run on and the CPU model, from the OS."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"nproc": nproc, "cpu_count": os.cpu_count(), "cpu_model": model,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
+def _oracle_cycles(strip, cycles, threads):
+    """`cycles` coupling cycles of the C2 workload with the FP64 oracle;
+    returns particle-steps/s and seconds (the Maxwellian start untimed)."""
     import numpy as np
 
     from oracle import oracle as O
 
     dt = O.default_dt(KN, NY)
     g = O.body_force_for_mach(KN, NY, MACH)
-    sim = O.Sim(NX, NY, PPC, KN, dt=dt, g=g, seed=SEED, capacity=int(NX * NY * PPC * 1.25) + 1024)
+    sim = O.Sim(NX, NY, PPC, KN, dt=dt, g=g, seed=SEED, capacity=int(NX * NY * PPC * 1.25) + 1024,
+                threads=threads)
     sim.init_maxwell()
     olat = O.lattice(37)
     tau = O.lbm_tau(KN, NY, olat["r"])
@@ -656,17 +881,90 @@ def cpu_baseline(strip, cycles):
     t0 = time.perf_counter()
     for _ in range(cycles):
         sim.step(STEPS_PER_CYCLE, sample_every=1)
-        f = O.dsmc2lb(sim.averages(), PPC, olat, 3)
+        f = O.dsmc2lb(sim.averages(), PPC, olat, 3, threads=threads)
         sim.reset_moments()
-        f = O.lbm_step(f, olat, NX, NY, tau, g / olat["r"], 1, 1)
+        f = O.lbm_step(f, olat, NX, NY, tau, g / olat["r"], 1, 1, threads=threads)
         sim.lb2dsmc(olat, 3, f, cells)
     t1 = time.perf_counter()
-    n = NX * NY * PPC
-    return {"value": n * STEPS_PER_CYCLE * cycles / (t1 - t0), "unit": "particle-steps/s", "cores": 1,
-            "kind": "oracle",
+    return NX * NY * PPC * STEPS_PER_CYCLE * cycles / (t1 - t0), t1 - t0
+
+
+def cpu_baseline(strip, cycles, cycles_single):
+    """The FP64 oracle on the host: OpenMP build on the cores OpenMP is given
+    (the reported value) and the single-threaded parity build."""
+    from oracle import oracle as O
+
+    host = _host()
+    threads = O.threads_in_use(0)
+    v_omp, s_omp = _oracle_cycles(strip, cycles, 0)
+    v_one, s_one = _oracle_cycles(strip, cycles_single, None)
+    return {"value": v_omp, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
             "sample": "%d coupling cycles (each 10 DSMC steps with sampling, D2Q37 projection of all cells, one BGK "
-                      "step, strip reseed) of the same 512x256x100 channel after its Maxwellian start, "
-                      "single-threaded C, %.1f s" % (cycles, t1 - t0)}
+                      "step, strip reseed) of the same 512x256x100 channel after its Maxwellian start, C oracle "
+                      "built with OpenMP on %d threads, %.1f s; single-threaded build: %d cycles, %.1f s"
+                      % (cycles, threads, s_omp, cycles_single, s_one),
+            "single_thread": {"value": v_one, "unit": "particle-steps/s", "cores": 1, "cycles": cycles_single,
+                              "seconds": round(s_one, 2)},
+            "omp": {"threads": threads, "cycles": cycles, "seconds": round(s_omp, 2),
+                    "speedup_over_single": round(v_omp / v_one, 2)},
+            **host}
+
+
+C1 = dict(nx=1, ny=64, ppc=50, kn=0.1, mach=0.1, seed=1, steps=2000, map_every=10)
+
+
+def c1_benchmark():
+    """The quasi-1-D channel in full on the GPU and with the oracle."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as O
+    from paper_1512_08042_amd import ChannelConfig
+    from paper_1512_08042_amd import dsmc as D
+
+    c = C1
+    n = c["nx"] * c["ny"] * c["ppc"]
+    events = c["steps"] // c["map_every"]
+    cfg = ChannelConfig(nx=c["nx"], ny=c["ny"], ppc=c["ppc"], kn=c["kn"], mach=c["mach"], seed=c["seed"]).resolved()
+
+    def gpu_run():
+        ch = D.Channel(cfg)
+        f = torch.empty((9, c["nx"] * c["ny"]), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(events):
+            ch.step(c["map_every"], sample_every=1)
+            ch.map_to_lbm(9, 2, out=f)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out = f.cpu().numpy()
+        st = ch.status()
+        ch.close()
+        return dt, out, st
+
+    gpu_run()  # first launches (code loading) untimed
+    t_gpu, f_gpu, st = gpu_run()
+    lat = O.lattice(9)
+    res = {}
+    for name, threads in (("single_thread", None), ("omp", 0)):
+        sim = O.Sim(c["nx"], c["ny"], c["ppc"], c["kn"], dt=cfg.dt, g=cfg.body_force_x, seed=c["seed"],
+                    capacity=2 * n + 64, threads=threads)
+        sim.init_maxwell()
+        t0 = time.perf_counter()
+        for _ in range(events):
+            sim.step(c["map_every"], sample_every=1)
+            f_or = O.dsmc2lb(sim.averages(), c["ppc"], lat, 2, threads=threads)
+        dt = time.perf_counter() - t0
+        res[name] = {"particle_steps_per_s": n * c["steps"] / dt, "seconds": round(dt, 4),
+                     "cores": O.threads_in_use(threads)}
+    scale = np.abs(f_or).max()
+    return {"workload": "1x64 cells x 50 particles/cell (3,200 particles), Kn 0.1, Ma 0.1, seed 1, FP64; 2000 "
+                        "steps sampled every step, D2Q9 projection of the cumulative averages every 10 steps",
+            "gpu": {"particle_steps_per_s": n * c["steps"] / t_gpu, "seconds": round(t_gpu, 4),
+                    "us_per_step": 1e6 * t_gpu / c["steps"], "cell_maps_per_s": c["nx"] * c["ny"] * events / t_gpu,
+                    "status_bits": st["bits"]},
+            "oracle": res,
+            "final_populations_max_abs_diff_over_max": float(np.abs(f_gpu - f_or).max() / scale)}
 
 
 def main():
@@ -676,6 +974,12 @@ def main():
         return
     if args.summarize_adjoint:
         summarize("adjoint", *args.summarize_adjoint)
+        return
+    if args.summarize_c4:
+        summarize("c4", *args.summarize_c4)
+        return
+    if args.summarize_batched:
+        summarize("batched", *args.summarize_batched)
         return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the hot path here is a single-GPU build "
@@ -705,6 +1009,12 @@ def main():
         return
     if args.hybrid_only:
         print(json.dumps({"hybrid": hybrid_benchmark()}), flush=True)
+        return
+    if args.profile_c4:
+        print(json.dumps({"profile_c4": profile_c4()}), flush=True)
+        return
+    if args.profile_batched:
+        print(json.dumps({"profile_batched": profile_batched()}), flush=True)
         return
     cfg = ChannelConfig(nx=NX, ny=NY, ppc=PPC, kn=KN, mach=MACH, seed=SEED).resolved()
     ch = D.Channel(cfg)
@@ -802,8 +1112,10 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_precision:
         out["precision"] = precision_comparison()
+    if not args.no_c1:
+        out["c1"] = c1_benchmark()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(strip, args.cpu_cycles)
+        out["cpu_baseline"] = cpu_baseline(strip, args.cpu_cycles, args.cpu_cycles_single)
     print(json.dumps(out), flush=True)
 
 

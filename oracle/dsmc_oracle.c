@@ -8,9 +8,16 @@
  * load it.  It shares no code, header, table or constant generator with the
  * GPU library; the quadrature tables it uses are derived by oracle/oracle.py.
  *
- * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC (oracle/build.py).
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC (oracle/oracle.py).
  * Contraction is off so that every floating-point operation is rounded exactly
  * as written, which is what lets the GPU side reproduce the integer decisions.
+ * The same source built with -fopenmp runs its per-particle and per-cell loops
+ * on all host cores (the CPU baseline of the benchmark).  Every loop so split
+ * is over independent particles or cells (draws are keyed by slot or cell,
+ * sums per cell keep their order), counters are integer reductions, and the
+ * counting sort gives each thread's slot range its own offsets inside each
+ * cell, so the threaded build's results are bit-identical to the single-
+ * threaded one (checked by the tests).
  *
  * Conventions (the paper works in SI units; the unit system below is the
  * nondimensionalisation of its appendix "Scaling factors"):
@@ -27,6 +34,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_NMOM 11
 #define OR_MAX_BOUNCES 16
@@ -96,6 +106,29 @@ void or_box_muller(double r1, double r2, double out[2])
     double ang = 6.283185307179586 * r2;
     out[0] = rad * cos(ang);
     out[1] = rad * sin(ang);
+}
+
+/* ------------------------------------------------------------------------ */
+/* threads of the OpenMP build (1 in the plain build)                       */
+/* ------------------------------------------------------------------------ */
+int32_t or_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return (int32_t)omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+static int nthreads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------ */
@@ -189,35 +222,54 @@ static double inside(int32_t i, double r)
 }
 
 /* stable counting sort of the particle set by cell index (ties keep slot
- * order), rebuilding cell_start. */
+ * order), rebuilding cell_start.  With T threads, thread t owns the slot
+ * range [t n / T, (t+1) n / T); inside every cell the ranges follow each
+ * other in thread order, each in slot order, which is the serial order. */
 static void sort_by_cell(or_sim *s)
 {
     int32_t nc = s->ncells;
-    int32_t *cnt = (int32_t *)xalloc((size_t)(nc + 1) * 4);
-    for (int64_t p = 0; p < s->n; ++p) {
-        s->cellid[p] = cell_of(s, s->x[p], s->y[p]);
-        cnt[s->cellid[p]] += 1;
+    int T = nthreads();
+    int32_t *cnt = (int32_t *)xalloc((size_t)T * (nc + 1) * 4);
+#pragma omp parallel num_threads(T)
+    {
+#ifdef _OPENMP
+        int t = omp_get_thread_num();
+#else
+        int t = 0;
+#endif
+        int64_t lo = s->n * t / T, hi = s->n * (t + 1) / T;
+        int32_t *mine = cnt + (size_t)t * (nc + 1);
+        for (int64_t p = lo; p < hi; ++p) {
+            s->cellid[p] = cell_of(s, s->x[p], s->y[p]);
+            mine[s->cellid[p]] += 1;
+        }
+#pragma omp barrier
+#pragma omp single
+        {
+            int32_t acc = 0;
+            for (int32_t c = 0; c < nc; ++c) {
+                s->cell_start[c] = acc;
+                for (int u = 0; u < T; ++u) {
+                    int32_t k = cnt[(size_t)u * (nc + 1) + c];
+                    cnt[(size_t)u * (nc + 1) + c] = acc;
+                    acc += k;
+                }
+            }
+            s->cell_start[nc] = acc;
+        }
+        for (int64_t p = lo; p < hi; ++p) {
+            int32_t c = s->cellid[p];
+            int64_t d = mine[c]++;
+            s->tx[d] = s->x[p]; s->ty[d] = s->y[p];
+            s->tvx[d] = s->vx[p]; s->tvy[d] = s->vy[p]; s->tvz[d] = s->vz[p];
+        }
     }
-    int32_t acc = 0;
-    for (int32_t c = 0; c < nc; ++c) {
-        s->cell_start[c] = acc;
-        acc += cnt[c];
-        cnt[c] = 0;
-    }
-    s->cell_start[nc] = acc;
-    for (int64_t p = 0; p < s->n; ++p) {
-        int32_t c = s->cellid[p];
-        int64_t d = (int64_t)s->cell_start[c] + cnt[c];
-        cnt[c] += 1;
-        s->tx[d] = s->x[p]; s->ty[d] = s->y[p];
-        s->tvx[d] = s->vx[p]; s->tvy[d] = s->vy[p]; s->tvz[d] = s->vz[p];
-    }
-    double *t;
-    t = s->x; s->x = s->tx; s->tx = t;
-    t = s->y; s->y = s->ty; s->ty = t;
-    t = s->vx; s->vx = s->tvx; s->tvx = t;
-    t = s->vy; s->vy = s->tvy; s->tvy = t;
-    t = s->vz; s->vz = s->tvz; s->tvz = t;
+    double *tp;
+    tp = s->x; s->x = s->tx; s->tx = tp;
+    tp = s->y; s->y = s->ty; s->ty = tp;
+    tp = s->vx; s->vx = s->tvx; s->tvx = tp;
+    tp = s->vy; s->vy = s->tvy; s->tvy = tp;
+    tp = s->vz; s->vz = s->tvz; s->tvz = tp;
     free(cnt);
 }
 
@@ -233,6 +285,7 @@ void or_init_maxwell(or_sim *s)
     int64_t n = (int64_t)s->ncells * s->ppc;
     if (n > s->capacity) { s->status |= OR_ST_CAPACITY; n = 0; }
     s->n = n;
+#pragma omp parallel for schedule(static)
     for (int32_t c = 0; c < s->ncells; ++c) {
         int32_t ix = c % s->nx, iy = c / s->nx;
         for (int32_t k = 0; k < s->ppc; ++k) {
@@ -286,7 +339,8 @@ int or_load(or_sim *s, int64_t n, const double *x, const double *y, const double
  * normal speed from the flux-weighted (Rayleigh) law, tangential components
  * Gaussian.  Bounce b of the particle in slot p at step s draws from counters
  * (2b, p, s, WALL) and (2b+1, p, s, WALL). */
-static void move_one(or_sim *s, int64_t p, double *px, double *py, double *pvx, double *pvy, double *pvz)
+static int move_one(const or_sim *s, int64_t p, double *px, double *py, double *pvx, double *pvy, double *pvz,
+                    int *limit)
 {
     double x = *px, y = *py, vx = *pvx, vy = *pvy, vz = *pvz;
     double g = s->g, H = s->H;
@@ -310,12 +364,11 @@ static void move_one(or_sim *s, int64_t p, double *px, double *py, double *pvx, 
             vy = (wall == 0.0) ? vn : -vn;
             t = t - th;
             b += 1;
-            s->nwall += 1;
             continue;
         }
         if (yn < 0.0 || yn > H) {
             /* bounce limit reached: stop the particle on the wall it hits */
-            s->status |= OR_ST_WALL_LIMIT;
+            *limit = 1;
             double wall = (yn < 0.0) ? 0.0 : H;
             double th = (wall - y) / vy;
             x = x + vx * th + 0.5 * g * th * th;
@@ -334,6 +387,7 @@ static void move_one(or_sim *s, int64_t p, double *px, double *py, double *pvx, 
     if (xw < 0.0) xw = xw + Lx;
     if (xw >= Lx) xw = 0.0;
     *px = stv(s, xw); *py = stv(s, y); *pvx = stv(s, vx); *pvy = stv(s, vy); *pvz = stv(s, vz);
+    return b;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -347,7 +401,7 @@ static void move_one(or_sim *s, int64_t p, double *px, double *py, double *pvx, 
  * (sigma_T c_r)_max / sigma_T, a speed, and grows when exceeded.
  * Candidate k of cell c at step s draws from counters (2k, c, s, COLL) and,
  * when accepted, (2k+1, c, s, COLL). */
-static void collide_cell(or_sim *s, int32_t c)
+static void collide_cell(or_sim *s, int32_t c, int64_t *pcand, int64_t *pcoll)
 {
     int32_t start = s->cell_start[c];
     int32_t N = s->cell_start[c + 1] - start;
@@ -373,7 +427,7 @@ static void collide_cell(or_sim *s, int32_t c)
         double cr = sqrt(dx * dx + dy * dy + dz * dz);
         if (cr > s->sigcmax[c]) s->sigcmax[c] = cr;
         double R = or_u53(u[2], u[3]);
-        s->ncand += 1;
+        *pcand += 1;
         if (cr / s->sigcmax[c] > R) {
             uint32_t w[4];
             draw(s->seed, (uint32_t)(2 * k + 1), (uint32_t)c, (uint32_t)s->step, OR_TAG_COLL, 0u, w);
@@ -388,7 +442,7 @@ static void collide_cell(or_sim *s, int32_t c)
             double mz = 0.5 * (s->vz[pi] + s->vz[pj]);
             s->vx[pi] = stv(s, mx + 0.5 * rx); s->vy[pi] = stv(s, my + 0.5 * ry); s->vz[pi] = stv(s, mz + 0.5 * rz);
             s->vx[pj] = stv(s, mx - 0.5 * rx); s->vy[pj] = stv(s, my - 0.5 * ry); s->vz[pj] = stv(s, mz - 0.5 * rz);
-            s->ncoll += 1;
+            *pcoll += 1;
         }
     }
 }
@@ -402,6 +456,7 @@ static void collide_cell(or_sim *s, int32_t c)
 static void sample_all(or_sim *s)
 {
     int32_t nc = s->ncells;
+#pragma omp parallel for schedule(static)
     for (int32_t c = 0; c < nc; ++c) {
         double acc[OR_NMOM];
         for (int k = 0; k < OR_NMOM; ++k) acc[k] = 0.0;
@@ -428,9 +483,18 @@ static void sample_all(or_sim *s)
 void or_step(or_sim *s, int32_t nsteps, int32_t sample_every)
 {
     for (int32_t it = 0; it < nsteps; ++it) {
-        for (int64_t p = 0; p < s->n; ++p) move_one(s, p, &s->x[p], &s->y[p], &s->vx[p], &s->vy[p], &s->vz[p]);
+        int64_t nw = 0, ncand = 0, ncoll = 0;
+        int lim = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nw) reduction(| : lim)
+        for (int64_t p = 0; p < s->n; ++p)
+            nw += move_one(s, p, &s->x[p], &s->y[p], &s->vx[p], &s->vy[p], &s->vz[p], &lim);
+        s->nwall += nw;
+        if (lim) s->status |= OR_ST_WALL_LIMIT;
         sort_by_cell(s);
-        for (int32_t c = 0; c < s->ncells; ++c) collide_cell(s, c);
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : ncand, ncoll)
+        for (int32_t c = 0; c < s->ncells; ++c) collide_cell(s, c, &ncand, &ncoll);
+        s->ncand += ncand;
+        s->ncoll += ncoll;
         if (sample_every > 0 && ((s->step + 1) % sample_every) == 0) sample_all(s);
         s->step += 1;
     }
@@ -502,6 +566,7 @@ void or_dsmc2lb(const double *avg, int32_t ncells, int32_t ppc, double kT, int32
                 const double *w, const double *xi, double *f)
 {
     double s1 = sqrt(kT);
+#pragma omp parallel for schedule(static)
     for (int32_t c = 0; c < ncells; ++c) {
         double m[OR_NMOM];
         for (int k = 0; k < OR_NMOM; ++k) m[k] = avg[(size_t)k * ncells + c];
@@ -668,6 +733,8 @@ int or_lb2dsmc(or_sim *s, int32_t Q, int32_t order, const double *xi, const doub
     double *prm = (double *)xalloc((size_t)(nsel > 0 ? nsel : 1) * 12 * 8);
     int32_t *nnew = (int32_t *)xalloc((size_t)(nsel > 0 ? nsel : 1) * 4);
     int64_t total = 0;
+    uint32_t st = 0;
+#pragma omp parallel for schedule(static) reduction(+ : total) reduction(| : st)
     for (int32_t c = 0; c < nc; ++c) {
         if (!mark[c]) { total += s->cell_start[c + 1] - s->cell_start[c]; continue; }
         int32_t i = mark[c] - 1;
@@ -679,23 +746,32 @@ int or_lb2dsmc(or_sim *s, int32_t Q, int32_t order, const double *xi, const doub
         int32_t nn = 0;
         int finite = 1;
         for (int k = 0; k < 12; ++k) if (!isfinite(pr[k])) finite = 0;
-        if (!finite) { s->status |= OR_ST_NONFINITE; nn = 0; }
-        else if (target >= 16777215.0) { s->status |= OR_ST_NNEW_LIMIT; nn = 16777215; }
+        if (!finite) { st |= OR_ST_NONFINITE; nn = 0; }
+        else if (target >= 16777215.0) { st |= OR_ST_NNEW_LIMIT; nn = 16777215; }
         else if (target >= 1.0) nn = (int32_t)floor(target);
         if (!(pr[0] > 0.0)) nn = 0;
         nnew[i] = nn;
         total += nn;
     }
+    s->status |= st;
     if (total > s->capacity) {
         s->status |= OR_ST_CAPACITY;
         free(mark); free(prm); free(nnew);
         s->reseed_events += 1;
         return -2;
     }
+    /* new cell starts first, then every cell's slots independently */
     int32_t *ncs = (int32_t *)xalloc((size_t)(nc + 1) * 4);
     int64_t d = 0;
     for (int32_t c = 0; c < nc; ++c) {
         ncs[c] = (int32_t)d;
+        d += mark[c] ? nnew[mark[c] - 1] : s->cell_start[c + 1] - s->cell_start[c];
+    }
+    ncs[nc] = (int32_t)d;
+    st = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : st)
+    for (int32_t c = 0; c < nc; ++c) {
+        int64_t d = ncs[c];
         if (!mark[c]) {
             for (int32_t p = s->cell_start[c]; p < s->cell_start[c + 1]; ++p, ++d) {
                 s->tx[d] = s->x[p]; s->ty[d] = s->y[p];
@@ -708,7 +784,7 @@ int or_lb2dsmc(or_sim *s, int32_t Q, int32_t order, const double *xi, const doub
         int32_t ix = c % s->nx, iy = c / s->nx;
         for (int32_t k = 0; k < nnew[i]; ++k, ++d) {
             double z[2], zz[2];
-            ar_sample(s->seed, pr, (uint32_t)c, e, (uint32_t)k, s->ar_max_tries, z, &s->status);
+            ar_sample(s->seed, pr, (uint32_t)c, e, (uint32_t)k, s->ar_max_tries, z, &st);
             uint32_t a[4], b[4];
             draw(s->seed, 0u, (uint32_t)c, e, OR_TAG_RESEED_POS, (uint32_t)k, a);
             draw(s->seed, 1u, (uint32_t)c, e, OR_TAG_RESEED_POS, (uint32_t)k, b);
@@ -720,7 +796,7 @@ int or_lb2dsmc(or_sim *s, int32_t Q, int32_t order, const double *xi, const doub
             s->tvz[d] = stv(s, s->s_th * zz[0]);
         }
     }
-    ncs[nc] = (int32_t)d;
+    s->status |= st;
     s->n = d;
     memcpy(s->cell_start, ncs, (size_t)(nc + 1) * 4);
     double *t;
@@ -759,14 +835,15 @@ void or_lbm_step(int32_t nx, int32_t ny, int32_t Q, const int32_t *ex, const int
                  int32_t nsteps)
 {
     int64_t nn = (int64_t)nx * ny;
+    if (Q > 64) abort(); /* the per-row population buffer holds D2Q9 and D2Q37 */
     int32_t K = 0;
     for (int32_t a = 0; a < Q; ++a) if (abs(ey[a]) > K) K = abs(ey[a]);
-    double *fe = (double *)xalloc((size_t)Q * 8);
     /* mass each node sends into the lower and the upper wall (y_mode 2) */
     double *wall_lo = (double *)xalloc((size_t)nn * 8);
     double *wall_hi = (double *)xalloc((size_t)nn * 8);
     for (int32_t st = 0; st < nsteps; ++st) {
         for (int64_t node = 0; node < nn; ++node) wall_lo[node] = wall_hi[node] = 0.0;
+#pragma omp parallel for schedule(static)
         for (int32_t iy = 0; iy < ny; ++iy) {
             for (int32_t ix = 0; ix < nx; ++ix) {
                 int64_t node = (int64_t)iy * nx + ix;
@@ -776,7 +853,11 @@ void or_lbm_step(int32_t nx, int32_t ny, int32_t Q, const int32_t *ex, const int
                 }
             }
         }
+        /* every (direction, destination) pair has one source node: the rows
+         * are independent */
+#pragma omp parallel for schedule(static)
         for (int32_t iy = 0; iy < ny; ++iy) {
+            double fe[64];
             for (int32_t ix = 0; ix < nx; ++ix) {
                 int64_t node = (int64_t)iy * nx + ix;
                 int held = ((y_mode == 1) && (iy < K || iy >= ny - K)) || ix < x_buffer;
@@ -838,7 +919,6 @@ void or_lbm_step(int32_t nx, int32_t ny, int32_t Q, const int32_t *ex, const int
         }
         memcpy(f, ftmp, (size_t)Q * nn * 8);
     }
-    free(fe);
     free(wall_lo);
     free(wall_hi);
 }

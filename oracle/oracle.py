@@ -27,6 +27,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dsmc_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 
 NMOM = 11
 MOMENT_NAMES = ("N", "vx", "vy", "vxvx", "vxvy", "vyvy", "vxvxvx", "vxvxvy", "vxvyvy", "vyvyvy", "vzvz")
@@ -39,25 +40,31 @@ ST_NNEW_LIMIT = 0x20
 ST_BAD_CELL = 0x40
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with contraction off and no fast-math."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+def build(force: bool = False, omp: bool = False) -> str:
+    """Compile the oracle with contraction off and no fast-math; ``omp`` gives
+    the same source built with OpenMP (its loops on all host cores)."""
+    path = _OMP_PATH if omp else _LIB_PATH
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-Wall", "-Wno-unknown-pragmas"] + (["-fopenmp"] if omp else []) + ["-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, path)
+    return path
 
 
-_lib = None
+_libs = {}
+_omp_default = [1]
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB_PATH)
+def lib(threads=None):
+    """The single-threaded oracle, or (``threads`` an int) the OpenMP build set
+    to that many threads (0: OpenMP's default, OMP_NUM_THREADS if set, else
+    all cores).  Both give the same bits."""
+    omp = threads is not None
+    L = _libs.get(omp)
+    if L is None:
+        L = ctypes.CDLL(build(omp=omp))
         P = ctypes.c_void_p
         d, i32, i64, u64, u32 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32
         L.or_create.restype = P
@@ -92,8 +99,19 @@ def lib():
         L.or_lb2dsmc.restype = ctypes.c_int
         L.or_lbm_step.argtypes = [i32, i32, i32, P, P, P, P, d, d, i32, i32, P, P, i32]
         L.or_dsmc2lb_eq.argtypes = [P, i32, i32, d, i32, i32, P, P, P]
-        _lib = L
-    return _lib
+        L.or_threads.argtypes = [i32]
+        L.or_threads.restype = i32
+        if omp:
+            _omp_default[0] = int(L.or_threads(0))  # OMP_NUM_THREADS, else all cores
+        _libs[omp] = L
+    if omp:
+        L.or_threads(int(threads) if threads else _omp_default[0])
+    return L
+
+
+def threads_in_use(threads=None) -> int:
+    """Threads the oracle build selected by ``threads`` runs its loops on."""
+    return int(lib(threads).or_threads(0))
 
 
 def _ptr(a: np.ndarray):
@@ -298,92 +316,98 @@ def lbm_tau(kn: float, ny: int, r: float) -> float:
 # --------------------------------------------------------------------------
 class Sim:
     def __init__(self, nx, ny, ppc, kn, dt=None, g=0.0, kT=1.0, sigcr0=6.0, seed=1, capacity=None,
-                 nbar_mode=0, ar_max_tries=65536, state32=False):
+                 nbar_mode=0, ar_max_tries=65536, state32=False, threads=None):
         """state32: particle values are stored in FP32 (every write rounds to the
-        nearest float); the arithmetic stays FP64."""
+        nearest float); the arithmetic stays FP64.  threads: None runs the
+        single-threaded build, an int the OpenMP build on that many threads
+        (0 = OpenMP's default), with the same results bit for bit."""
+        self.threads = threads
         self.nx, self.ny, self.ppc = int(nx), int(ny), int(ppc)
         self.ncells = self.nx * self.ny
         self.kn, self.kT, self.g = float(kn), float(kT), float(g)
         self.dt = float(dt) if dt is not None else default_dt(kn, ny, kT)
         self.capacity = int(capacity) if capacity is not None else self.ncells * self.ppc * 2 + 64
         self.seed = int(seed)
-        self._h = lib().or_create(self.nx, self.ny, self.ppc, int(nbar_mode), self.capacity, self.kn, self.dt,
+        self._h = self._lib().or_create(self.nx, self.ny, self.ppc, int(nbar_mode), self.capacity, self.kn, self.dt,
                                   self.g, self.kT, float(sigcr0), self.seed, int(ar_max_tries))
         if not self._h:
             raise ValueError("oracle rejected the configuration")
         self.state32 = bool(state32)
-        lib().or_set_state32(self._h, 1 if self.state32 else 0)
+        self._lib().or_set_state32(self._h, 1 if self.state32 else 0)
+
+    def _lib(self):
+        return lib(self.threads)
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().or_destroy(h)
+            self._lib().or_destroy(h)
             self._h = None
 
     def init_maxwell(self):
-        lib().or_init_maxwell(self._h)
+        self._lib().or_init_maxwell(self._h)
 
     def load(self, x, y, vx, vy, vz):
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, vx, vy, vz)]
-        rc = lib().or_load(self._h, len(arrs[0]), *[_ptr(a) for a in arrs])
+        rc = self._lib().or_load(self._h, len(arrs[0]), *[_ptr(a) for a in arrs])
         if rc != 0:
             raise ValueError("load failed")
 
     def step(self, nsteps=1, sample_every=0):
-        lib().or_step(self._h, int(nsteps), int(sample_every))
+        self._lib().or_step(self._h, int(nsteps), int(sample_every))
 
     def sample_now(self):
-        lib().or_sample_now(self._h)
+        self._lib().or_sample_now(self._h)
 
     @property
     def n(self):
-        return int(lib().or_count(self._h))
+        return int(self._lib().or_count(self._h))
 
     def particles(self):
         n = self.n
         out = [np.zeros(n) for _ in range(5)]
-        lib().or_get_particles(self._h, *[_ptr(a) for a in out])
+        self._lib().or_get_particles(self._h, *[_ptr(a) for a in out])
         return out
 
     def cells(self):
         cs = np.zeros(self.ncells + 1, dtype=np.int32)
         nbar, sig, rem = (np.zeros(self.ncells) for _ in range(3))
-        lib().or_get_cells(self._h, _ptr(cs), _ptr(nbar), _ptr(sig), _ptr(rem))
+        self._lib().or_get_cells(self._h, _ptr(cs), _ptr(nbar), _ptr(sig), _ptr(rem))
         return cs, nbar, sig, rem
 
     def set_cells(self, nbar, sigcmax, rem):
         a = [np.ascontiguousarray(v, dtype=np.float64) for v in (nbar, sigcmax, rem)]
-        lib().or_set_cells(self._h, *[_ptr(v) for v in a])
+        self._lib().or_set_cells(self._h, *[_ptr(v) for v in a])
 
     def counters(self):
         out = np.zeros(8, dtype=np.int64)
-        lib().or_get_counters(self._h, _ptr(out))
+        self._lib().or_get_counters(self._h, _ptr(out))
         keys = ("step", "nsamples", "ncoll", "ncand", "nwall", "reseed_events", "status", "n")
         return dict(zip(keys, (int(v) for v in out)))
 
     def set_step(self, step):
-        lib().or_set_step(self._h, int(step))
+        self._lib().or_set_step(self._h, int(step))
 
     def averages(self):
         out = np.zeros((NMOM, self.ncells))
-        lib().or_averages(self._h, _ptr(out))
+        self._lib().or_averages(self._h, _ptr(out))
         return out
 
     def reset_moments(self):
-        lib().or_reset_moments(self._h)
+        self._lib().or_reset_moments(self._h)
 
     def lb2dsmc(self, lat, order, f, cells):
         f = np.ascontiguousarray(f, dtype=np.float64)
         cells = np.ascontiguousarray(cells, dtype=np.int32)
         assert f.shape == (lat["Q"], self.ncells)
-        return lib().or_lb2dsmc(self._h, lat["Q"], int(order), _ptr(lat["xi"]), _ptr(f), _ptr(cells), len(cells))
+        return self._lib().or_lb2dsmc(self._h, lat["Q"], int(order), _ptr(lat["xi"]), _ptr(f), _ptr(cells), len(cells))
 
 
-def dsmc2lb(avg, ppc, lat, order, kT=1.0):
+def dsmc2lb(avg, ppc, lat, order, kT=1.0, threads=None):
     avg = np.ascontiguousarray(avg, dtype=np.float64)
     ncells = avg.shape[1]
     f = np.zeros((lat["Q"], ncells))
-    lib().or_dsmc2lb(_ptr(avg), ncells, int(ppc), float(kT), lat["Q"], int(order), _ptr(lat["w"]),
+    lib(threads).or_dsmc2lb(_ptr(avg), ncells, int(ppc), float(kT), lat["Q"], int(order), _ptr(lat["w"]),
                      _ptr(lat["xi"]), _ptr(f))
     return f
 
@@ -409,24 +433,24 @@ def ar_sample(prm, n, seed=1, cell=0, event=0, max_tries=65536):
     return xi, int(tries), int(st[0])
 
 
-def lbm_step(f, lat, nx, ny, tau, gx, y_mode, nsteps, x_buffer=0):
+def lbm_step(f, lat, nx, ny, tau, gx, y_mode, nsteps, x_buffer=0, threads=None):
     f = np.array(f, dtype=np.float64, copy=True, order="C")
     assert f.shape == (lat["Q"], nx * ny)
     tmp = np.zeros_like(f)
     e = lat["e"]
     ex = np.ascontiguousarray(e[:, 0], dtype=np.int32)
     ey = np.ascontiguousarray(e[:, 1], dtype=np.int32)
-    lib().or_lbm_step(int(nx), int(ny), lat["Q"], _ptr(ex), _ptr(ey), _ptr(lat["w"]), _ptr(lat["xi"]), float(tau),
+    lib(threads).or_lbm_step(int(nx), int(ny), lat["Q"], _ptr(ex), _ptr(ey), _ptr(lat["w"]), _ptr(lat["xi"]), float(tau),
                       float(gx), int(y_mode), int(x_buffer), _ptr(f), _ptr(tmp), int(nsteps))
     return f
 
 
-def dsmc2lb_eq(avg, ppc, lat, order=2, kT=1.0):
+def dsmc2lb_eq(avg, ppc, lat, order=2, kT=1.0, threads=None):
     """The equilibrium mapping of Eq. (feq_dsmc) (order 2; order 3 adds the
     third-order equilibrium term)."""
     avg = np.ascontiguousarray(avg, dtype=np.float64)
     ncells = avg.shape[1]
     f = np.zeros((lat["Q"], ncells))
-    lib().or_dsmc2lb_eq(_ptr(avg), ncells, int(ppc), float(kT), lat["Q"], int(order), _ptr(lat["w"]),
+    lib(threads).or_dsmc2lb_eq(_ptr(avg), ncells, int(ppc), float(kT), lat["Q"], int(order), _ptr(lat["w"]),
                         _ptr(lat["xi"]), _ptr(f))
     return f
