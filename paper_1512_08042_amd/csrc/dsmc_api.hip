@@ -448,6 +448,7 @@ StepArgs step_args(const dsmc_ctx *x, int32_t cur, int64_t step, bool sample, bo
     a.tiles = x->tiles;
     a.r = 0;
     a.c_first = -1;
+    a.band = 0;
     a.dev_step = x->capturing ? 1 : 0;
     a.reseed = 0;
     a.step = (uint32_t)step;
@@ -570,6 +571,11 @@ int set_tiling(dsmc_ctx *x, int ppt, hipStream_t s)
     return hipStreamSynchronize(s) == hipSuccess ? DSMC_OK : DSMC_EHIP;
 }
 
+// Tiles per band of a one-channel launch (see StepArgs::band): the tiles
+// that read a cell's source groups run within about two band rows of each
+// other, close enough to share the cache lines those groups split
+constexpr int TILE_BAND = 8;
+
 // the launches of one pass of the tile kernels, one per tile group: kind 0
 // = k_classify, 1 = k_step.  The groups touch disjoint cells; with side
 // streams the second and later groups run beside the first.
@@ -588,8 +594,11 @@ int launch_tiles(const dsmc_ctx *x, int kind, bool move, hipStream_t s, const St
         StepArgs a = a0;
         a.tiles = x->tiles + 2 * (size_t)g.tile0;
         if (g.rep >= 0) {  // one channel: tiles follow from the block index
+            const RepConst &R = x->reps[g.rep];
             a.r = g.rep;
-            a.c_first = x->reps[g.rep].cbase;
+            a.c_first = R.cbase;
+            // rows of whole tiles at least two bands wide run band by band
+            a.band = (R.G.nx % g.tc == 0 && R.G.nx / g.tc >= 2 * TILE_BAND) ? TILE_BAND : 0;
         }
         const unsigned n = (unsigned)g.ntiles;
 #define DSMC_LAUNCH(TC, CH, S)                                   \

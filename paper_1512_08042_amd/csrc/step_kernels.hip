@@ -919,7 +919,17 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     const int tx = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int tile = (a0.step & 1u) ? (int)gridDim.x - 1 - tx : tx;
     int c0;
-    if (a0.c_first >= 0) {
+    if (a0.c_first >= 0 && a0.band > 0) {
+        // bands of `band` tiles across x, each taken row by row: the tiles of
+        // the rows above and below a cell, which read its source groups, run
+        // a few tiles apart instead of a whole row apart (rows hold a whole
+        // number of tiles here)
+        const int bx = a0.R().G.nx, by = a0.R().G.ny, tpr = bx / TC;
+        const int b = tile / (a0.band * by), rest = tile - b * (a0.band * by);
+        const int w = min(a0.band, tpr - b * a0.band);
+        const int iy = rest / w;
+        c0 = a0.c_first + iy * bx + (b * a0.band + rest - iy * w) * TC;
+    } else if (a0.c_first >= 0) {
         c0 = a0.c_first + tile * TC;
     } else {
         const __attribute__((address_space(4))) int32_t *td =
@@ -1072,7 +1082,8 @@ DSMC_TILE_INSTANCES(1, 8, float)
 __global__ __launch_bounds__(256) void k_cell_count(CellArgs a)
 {
     __shared__ int lds[4];
-    const int c = blockIdx.x * 256 + threadIdx.x;
+    __shared__ int32_t stage[256 * 2 * NDIR];  // the block's plans, stored out in one contiguous sweep
+    const int c0 = blockIdx.x * 256, c = c0 + threadIdx.x;
     int total = 0;
     if (c < a.ncells) {
         int nx = a.nx1, ny = a.ny1, cb = 0;
@@ -1085,7 +1096,7 @@ __global__ __launch_bounds__(256) void k_cell_count(CellArgs a)
         const int cix = (c - cb) % nx, ciy = (c - cb) / nx;
         int key[NDIR], dir[NDIR];
         arrival_order(nx, ny, cix, ciy, cb, key, dir);
-        int32_t *const pl = a.plan + (size_t)c * (2 * NDIR);
+        int32_t *const pl = stage + threadIdx.x * (2 * NDIR);
 #pragma unroll
         for (int k = 0; k < NDIR; ++k) {
             int first = 0, n = 0;
@@ -1101,6 +1112,14 @@ __global__ __launch_bounds__(256) void k_cell_count(CellArgs a)
         total += a.farcnt[c];
         a.countnew[c] = total;
     }
+    __syncthreads();
+    // 16-byte stores of consecutive plan words (a block's plans start on a
+    // 16-byte boundary: 256 * 72 bytes apart)
+    const int nwords = min(256, a.ncells - c0) * (2 * NDIR);
+    int4 *const dst = (int4 *)(a.plan + (size_t)c0 * (2 * NDIR));
+    const int4 *const src = (const int4 *)stage;
+    for (int i = threadIdx.x; i < nwords / 4; i += 256) dst[i] = src[i];
+    for (int i = (nwords / 4) * 4 + threadIdx.x; i < nwords; i += 256) a.plan[(size_t)c0 * (2 * NDIR) + i] = stage[i];
     const int bsum = block_reduce_256(total, lds);
     if (threadIdx.x == 0) a.blocksum[blockIdx.x] = bsum;
 }

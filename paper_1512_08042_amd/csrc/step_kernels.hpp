@@ -79,7 +79,9 @@ struct StepArgs {
     uint32_t step;
     int cur, sample, classify;
     int r;                 // replica of the tile (the launch's, or set by the tile kernel from the table)
-    int c_first;           // >= 0: every tile is in replica r, tile b starts at cell c_first + b * TC
+    int c_first;           // >= 0: every tile is in replica r, at a cell that follows from its index (band)
+    int band;              // with c_first: 0 = tile b starts at cell c_first + b * TC; > 0 = the tiles
+                           // run in bands of `band` tiles across x, all rows of a band in turn
     int dev_step;          // step graphs: add the device step base to `step`
     int reseed;            // k_classify: complete a pending reseed (see above)
 
