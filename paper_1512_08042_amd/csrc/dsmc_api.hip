@@ -256,7 +256,7 @@ Layout make_layout(const dsmc_config &c, size_t nc, size_t nrep)
     L.kc = take(REP_OFFSET + nrep * sizeof(RepConst));  // TileConst, then the channels' constants
     L.ctr = take(sizeof(Counters));
     L.rep = L.kc + REP_OFFSET;
-    L.tiles = take(2 * nc * 4);  // at most one tile per cell
+    L.tiles = take(TILE_WORDS * nc * 4);  // at most one tile per cell
     L.cell_rep = take(nc * 4);
     L.rstat = take(3 * nrep * 8);
     L.total = o;
@@ -348,7 +348,6 @@ struct dsmc_ctx {
     unsigned long long *rstat;
     struct TileGroup {
         int tc, ch, tile0, ntiles;
-        int rep;  // the group's one channel, or -1 when it spans several
     };
     std::vector<TileGroup> groups;
     // batches: the tile groups after the first run on side streams forked
@@ -447,8 +446,6 @@ StepArgs step_args(const dsmc_ctx *x, int32_t cur, int64_t step, bool sample, bo
     a.kc = x->kc;
     a.tiles = x->tiles;
     a.r = 0;
-    a.c_first = -1;
-    a.band = 0;
     a.dev_step = x->capturing ? 1 : 0;
     a.reseed = 0;
     a.step = (uint32_t)step;
@@ -542,27 +539,35 @@ int set_tiling(dsmc_ctx *x, int ppt, hipStream_t s)
     }
     x->groups.clear();
     x->tiles_host.clear();
+    auto add_tile = [&](int r, int c) {
+        const RepConst &R = x->reps[r];
+        const int nx = R.G.nx, ci = c - R.cbase;
+        x->tiles_host.insert(x->tiles_host.end(), {c, r, ci / nx, ci % nx});
+    };
     for (int k = 0; k < 4; ++k) {
         dsmc_ctx::TileGroup g;
         g.tc = SHAPES[f32][k][0];
         g.ch = SHAPES[f32][k][1];
-        g.tile0 = (int)(x->tiles_host.size() / 2);
+        g.tile0 = (int)(x->tiles_host.size() / TILE_WORDS);
         for (int r = 0; r < x->nrep; ++r) {
             if (shape_of[r] != k) continue;
-            for (int c = x->reps[r].cbase; c < x->reps[r].cend; c += g.tc) {
-                x->tiles_host.push_back(c);
-                x->tiles_host.push_back(r);
+            const RepConst &R = x->reps[r];
+            const int nx = R.G.nx, ny = R.G.ny, tpr = nx / g.tc;
+            if (nx % g.tc == 0 && tpr >= 2 * TILE_BAND) {
+                // rows of whole tiles at least two bands wide: band by band,
+                // each band row by row
+                for (int b0 = 0; b0 < tpr; b0 += TILE_BAND)
+                    for (int iy = 0; iy < ny; ++iy)
+                        for (int t = b0; t < std::min(b0 + TILE_BAND, tpr); ++t)
+                            add_tile(r, R.cbase + iy * nx + t * g.tc);
+            } else {
+                for (int c = R.cbase; c < R.cend; c += g.tc) add_tile(r, c);
             }
         }
-        g.ntiles = (int)(x->tiles_host.size() / 2) - g.tile0;
-        g.rep = -1;
-        for (int r = 0, n = 0; r < x->nrep; ++r) {
-            if (shape_of[r] != k) continue;
-            g.rep = (n++ == 0) ? r : -1;
-        }
+        g.ntiles = (int)(x->tiles_host.size() / TILE_WORDS) - g.tile0;
         if (g.ntiles > 0) x->groups.push_back(g);
     }
-    x->ntiles = (int)(x->tiles_host.size() / 2);
+    x->ntiles = (int)(x->tiles_host.size() / TILE_WORDS);
     x->particles_per_tile = ppt;
     if (hipMemcpyAsync(x->tiles, x->tiles_host.data(), x->tiles_host.size() * 4, hipMemcpyHostToDevice, s) !=
         hipSuccess)
@@ -570,11 +575,6 @@ int set_tiling(dsmc_ctx *x, int ppt, hipStream_t s)
     // the host table must outlive the copy
     return hipStreamSynchronize(s) == hipSuccess ? DSMC_OK : DSMC_EHIP;
 }
-
-// Tiles per band of a one-channel launch (see StepArgs::band): the tiles
-// that read a cell's source groups run within about two band rows of each
-// other, close enough to share the cache lines those groups split
-constexpr int TILE_BAND = 8;
 
 // the launches of one pass of the tile kernels, one per tile group: kind 0
 // = k_classify, 1 = k_step.  The groups touch disjoint cells; with side
@@ -592,14 +592,7 @@ int launch_tiles(const dsmc_ctx *x, int kind, bool move, hipStream_t s, const St
             if (hipStreamWaitEvent(gs, x->ev_fork, 0) != hipSuccess) return DSMC_EHIP;
         }
         StepArgs a = a0;
-        a.tiles = x->tiles + 2 * (size_t)g.tile0;
-        if (g.rep >= 0) {  // one channel: tiles follow from the block index
-            const RepConst &R = x->reps[g.rep];
-            a.r = g.rep;
-            a.c_first = R.cbase;
-            // rows of whole tiles at least two bands wide run band by band
-            a.band = (R.G.nx % g.tc == 0 && R.G.nx / g.tc >= 2 * TILE_BAND) ? TILE_BAND : 0;
-        }
+        a.tiles = x->tiles + TILE_WORDS * (size_t)g.tile0;
         const unsigned n = (unsigned)g.ntiles;
 #define DSMC_LAUNCH(TC, CH, S)                                   \
     do {                                                         \

@@ -89,8 +89,21 @@ __device__ __forceinline__ void record_far(int32_t *far, int32_t *farcnt, Counte
 // ---- tiles of cells, one wave each ------------------------------------------------
 constexpr int NTC_ROUND = 32;  // NTC candidates drawn per round (all cells of a tile)
 
+// Tiles of four cells keep their cells' NTC state and running moment sums
+// in LDS from the set-up to their use: held in registers across the gather,
+// these spilled to scratch (about 3 KB of scratch traffic per tile).  The
+// smaller tiles keep them in registers and their LDS at 8 KB.
+template <int TC, bool STASH = (TC == 4)>
+struct CellStash {
+};
+template <int TC>
+struct CellStash<TC, true> {
+    double ntcs[3][TC];            // nbar, sigcmax, rem of each cell
+    double mprev[NMOM][TC];        // the moment sums before this step
+};
+
 template <int TC, int CH, class S>
-struct TileLds {
+struct TileLds : CellStash<TC> {
     static constexpr int CAP = 64 * CH;
     S v[3][CAP];                   // vx, vy, vz of the tile's particles (stored precision), in new-slot order;
                                    // positions stay in registers of the lane that owns the slot
@@ -588,56 +601,54 @@ __device__ void move_chunk_walls(const StepArgs &a, const TileLds<TC, CH, S> &L,
 }
 
 // Stable rank of every particle of one chunk inside its next-step group
-// (key t * NGRP + d, in kr), continuing from earlier chunks: lane k of `run`
-// holds the size of group k so far.  One ballot per bit of the direction
-// code, masked to the lanes of the particle's own cell, ranks all lanes.
+// (key t * NGRP + d, in kr), continuing from earlier chunks: L.run[key]
+// holds the size of each group so far (zero before the first chunk).  One
+// ballot per bit of the key gives every lane the chunk's lanes that share
+// its key; its rank is the count of those below it, and the highest of them
+// adds the chunk's share to the group size.
 template <int TC, int CH, class S>
-__device__ __forceinline__ void rank_chunk(const TileLds<TC, CH, S> &L, int32_t *kr, int ntc, int nt, int b0, int &run)
+__device__ __forceinline__ void rank_chunk(TileLds<TC, CH, S> &L, int32_t *kr, int nt, int b0)
 {
+    constexpr int KB = TC * NGRP > 32 ? 6 : (TC * NGRP > 16 ? 5 : 4);  // bits of a key
     const int lane = threadIdx.x;
-    const int D0 = L.csn[0];
     const int i = b0 + lane;
     const bool act = i < nt;
     const int key = act ? kr[i] : 0;
-    const int t = key / NGRP, d = key - t * NGRP;
-    const uint64_t actm = ballot64(act);
-    const uint64_t b0m = ballot64(act && (d & 1)), b1m = ballot64(act && (d & 2));
-    const uint64_t b2m = ballot64(act && (d & 4)), b3m = ballot64(act && (d & 8));
-    auto with_code = [&](int e) -> uint64_t {
-        uint64_t m = actm;
-        m &= (e & 1) ? b0m : ~b0m;
-        m &= (e & 2) ? b1m : ~b1m;
-        m &= (e & 4) ? b2m : ~b2m;
-        m &= (e & 8) ? b3m : ~b3m;
-        return m;
-    };
-    // lanes of this chunk from the first lane of tile cell u on
-    auto from_cell = [&](int u) -> uint64_t {
-        const int lo = min(max(L.csn[u] - D0 - b0, 0), 64);
-        return lo >= 64 ? 0ull : (~0ull << lo);
-    };
-    const int before = __shfl(run, key, 64);
-    if (act) kr[i] = ((before + rank_below(with_code(d) & from_cell(t))) << 6) | key;
-    if (lane < ntc * NGRP) {
-        const int u = lane / NGRP, e = lane - u * NGRP;
-        run += __popcll(with_code(e) & from_cell(u) & ~from_cell(u + 1));
+    uint64_t same = ballot64(act);
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+        const bool bit = ((key >> b) & 1) != 0;
+        const uint64_t m = ballot64(act && bit);
+        same &= bit ? m : ~m;
+    }
+    if (act) {
+        const int below = rank_below(same);
+        const int before = L.run[key];
+        kr[i] = ((before + below) << 6) | key;
+        if ((same >> lane) == 1ull) L.run[key] = before + below + 1;  // the last of its key in the chunk
     }
 }
 
-// offsets of the tile cells' next-step groups inside each cell (sizes held
-// by lane t * NGRP + d), published as absolute first slots with the cell end
+// offsets of the tile cells' next-step groups inside each cell (sizes in
+// L.run), published as absolute first slots with the cell end: lane
+// t * NGRP + d scans the sizes of cell t's groups below d across its lanes
 template <int TC, int CH, class S>
-__device__ __forceinline__ void tile_group_offsets(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int ntc, int run)
+__device__ __forceinline__ void tile_group_offsets(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int ntc)
 {
     const int lane = threadIdx.x;
-    if (lane < TC * NGRP) L.run[lane] = run;
     __syncthreads();
-    if (lane < ntc * NGRP) {
-        const int t = lane / NGRP, d = lane - t * NGRP;
-        int ex = 0;
-        for (int e = 0; e < d; ++e) ex += L.run[t * NGRP + e];
-        L.excl[lane] = ex;
-        a.grp_out()[(size_t)(c0 + t) * GSTRIDE + d] = L.csn[t] + ex;
+    const int t = lane / NGRP, d = lane - t * NGRP;
+    const bool act = lane < ntc * NGRP;
+    const int own = act ? L.run[lane] : 0;
+    int inc = own;
+#pragma unroll
+    for (int off = 1; off < NGRP; off <<= 1) {
+        const int v = __shfl_up(inc, off, 64);
+        if (d >= off) inc += v;
+    }
+    if (act) {
+        L.excl[lane] = inc - own;
+        a.grp_out()[(size_t)(c0 + t) * GSTRIDE + d] = L.csn[t] + inc - own;
     }
     if (lane < ntc) a.grp_out()[(size_t)(c0 + lane) * GSTRIDE + NGRP] = L.csn[lane + 1];
     __syncthreads();
@@ -776,6 +787,13 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
 
     // 2. collisions and 3. sample
     if (GATHER) {
+        if constexpr (TC == 4) {
+            if (own_ntc) {
+                nbar = L.ntcs[0][lane];
+                sig = L.ntcs[1][lane];
+                rem = L.ntcs[2][lane];
+            }
+        }
         tile_ntc<TC, CH, S>(s[2], s[3], s[4], L, a.N(), c0, ntc, own_ntc, nbar, sig, rem, ncoll, ncand);
         if (own_ntc) {  // the cells' NTC state is final here (stored now: nothing stays live to the end)
             a.K().nbar[c0 + lane] = nbar;
@@ -784,6 +802,14 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
         }
         if (!STAGED) __threadfence();
         __syncthreads();
+        if constexpr (TC == 4) {  // the moment sums' address is formed again here rather than held
+            constexpr int T = 64 / TC, SPAN = T / 16;
+            const int team = lane / T, lt = lane - team * T;
+            if (mown) {
+                mprev = L.mprev[lt / SPAN][team];
+                mdst = a.K().mom + (size_t)(lt / SPAN) * a.K().ncells + c0 + team;
+            }
+        }
         if (a.sample) tile_sample<TC, CH, S>(s[2], s[3], s[4], L, ntc, mown, mprev, mdst);
     }
 
@@ -836,9 +862,8 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
         if (!STAGED) __threadfence();
         __syncthreads();
     }
-    int run = 0;
-    for (int b0 = 0; b0 < nt; b0 += 64) rank_chunk<TC, CH, S>(L, kr, ntc, nt, b0, run);
-    tile_group_offsets<TC, CH, S>(a, L, c0, ntc, run);
+    for (int b0 = 0; b0 < nt; b0 += 64) rank_chunk<TC, CH, S>(L, kr, nt, b0);
+    tile_group_offsets<TC, CH, S>(a, L, c0, ntc);
 
     // 5. write out, partitioned by group inside each cell
     if (STAGED) {
@@ -918,25 +943,11 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     StepArgs a = a0;
     const int tx = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int tile = (a0.step & 1u) ? (int)gridDim.x - 1 - tx : tx;
-    int c0;
-    if (a0.c_first >= 0 && a0.band > 0) {
-        // bands of `band` tiles across x, each taken row by row: the tiles of
-        // the rows above and below a cell, which read its source groups, run
-        // a few tiles apart instead of a whole row apart (rows hold a whole
-        // number of tiles here)
-        const int bx = a0.R().G.nx, by = a0.R().G.ny, tpr = bx / TC;
-        const int b = tile / (a0.band * by), rest = tile - b * (a0.band * by);
-        const int w = min(a0.band, tpr - b * a0.band);
-        const int iy = rest / w;
-        c0 = a0.c_first + iy * bx + (b * a0.band + rest - iy * w) * TC;
-    } else if (a0.c_first >= 0) {
-        c0 = a0.c_first + tile * TC;
-    } else {
-        const __attribute__((address_space(4))) int32_t *td =
-            (const __attribute__((address_space(4))) int32_t *)a0.tiles + 2 * (size_t)tile;
-        c0 = td[0];
-        a.r = td[1];
-    }
+    const __attribute__((address_space(4))) int32_t *td =
+        (const __attribute__((address_space(4))) int32_t *)a0.tiles + TILE_WORDS * (size_t)tile;
+    const int c0 = td[0];
+    a.r = td[1];
+    const int iy0 = td[2], ix0 = td[3];
     // a step graph is captured with steps counted from 0 and replayed from
     // the step the host sets (an even one, so every parity is unchanged)
     if (a0.dev_step) a.step += ((const __attribute__((address_space(4))) Counters *)a.K().ctr)->step_base;
@@ -957,6 +968,7 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     __builtin_amdgcn_s_setprio(2);
     // set-up: every per-cell quantity of the tile is loaded in one round
     if (lane <= TC) L.csn[lane] = (rerr ? cs_old : a.cs_new())[min(c0 + lane, ce)];
+    if (lane < TC * NGRP) L.run[lane] = 0;  // the next step's group sizes, counted by the rank
     if (rs && lane < TC) {
         const int c = min(c0 + lane, ce - 1);
         const bool fresh = !rerr && lane < ntc && a.K().mark[c] != 0;
@@ -967,28 +979,44 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
         }
         if (rerr && lane == 0 && c0 + ntc == ce) a.K().cs[a.cur][ce] = cs_old[ce];
     }
-    if (lane < TC) {
-        const int c = min(c0 + lane, ce - 1) - cb;  // position inside the channel
-        L.tiy[lane] = c / nx;
-        L.tix[lane] = c - (c / nx) * nx;
+    if (lane < TC) {  // the cells' rows and columns (a tile may run over row ends in narrow channels)
+        int ix = ix0 + min(lane, ce - 1 - c0), iy = iy0;
+#pragma unroll
+        for (int u = 1; u < TC; ++u)
+            if (ix >= nx) {
+                ix -= nx;
+                iy += 1;
+            }
+        L.tix[lane] = ix;
+        L.tiy[lane] = iy;
     }
     double nbar = 0.0, sig = 0.0, rem = 0.0;
     int nfin = 0;
     if (GATHER && lane < ntc) nfin = a.farcnt_in()[c0 + lane];
     const bool own_ntc = GATHER && lane < ntc;  // this lane runs the collisions of tile cell `lane`
     if (own_ntc) {
-        nbar = a.K().nbar[c0 + lane];
-        sig = a.K().sigcmax[c0 + lane];
-        rem = a.K().rem[c0 + lane];
+        if constexpr (TC == 4) {
+            L.ntcs[0][lane] = a.K().nbar[c0 + lane];
+            L.ntcs[1][lane] = a.K().sigcmax[c0 + lane];
+            L.ntcs[2][lane] = a.K().rem[c0 + lane];
+        } else {
+            nbar = a.K().nbar[c0 + lane];
+            sig = a.K().sigcmax[c0 + lane];
+            rem = a.K().rem[c0 + lane];
+        }
     }
     const int team = lane / T, lt = lane - team * T, mslot = lt / SPAN;
     const bool mown = GATHER && a.sample && team < ntc && (lt % SPAN) == 0 && mslot < NMOM;
     double *const mdst = a.K().mom + (size_t)(mown ? mslot : 0) * nc + c0 + (mown ? team : 0);
     double mprev = 0.0;
-    if (mown) mprev = *mdst;
+    if (mown) {
+        if constexpr (TC == 4)
+            L.mprev[mslot][team] = *mdst;
+        else
+            mprev = *mdst;
+    }
+    double *const mdst_held = TC == 4 ? nullptr : mdst;
     const int n_old = GATHER ? a.cs_old()[nc] : 0;
-    // running counters of the tile, kept at its first cell (valid for any tiling)
-    unsigned long long *const tst = a.K().tstat + 3 * (size_t)c0 + (lane < 3 ? lane : 0);
     if (GATHER) {  // the tile's cells' plans (see tile_groups), in the same round of loads
 #pragma unroll
         for (int e = lane; e < TC * 2 * NDIR; e += 64) {
@@ -1009,11 +1037,11 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     int walls = 0;
     bool limit = false;
     if (nt <= TileLds<TC, CH, S>::CAP)
-        tile_body<TC, CH, S, GATHER, MOVE, true, NT>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev, mdst,
+        tile_body<TC, CH, S, GATHER, MOVE, true, NT>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev, mdst_held,
                                               ncoll, ncand, walls, limit);
     else
         tile_body<TC, CH, S, GATHER, MOVE, false, NT>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev,
-                                               mdst, ncoll, ncand, walls, limit);
+                                               mdst_held, ncoll, ncand, walls, limit);
 
     // the tile's running counters.  Collisions and candidates were counted by
     // the lanes that ran the cells' collisions (lanes below TC); wall hits on
@@ -1028,16 +1056,18 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     }
     if (ballot64(walls != 0) != 0) twall = wave_sum_u64((unsigned long long)walls);
     const unsigned long long tadd = lane == 0 ? tcoll : (lane == 1 ? tcand : twall);
-    if (lane < 3 && tadd != 0) atomicAdd(tst, tadd);
+    // running counters of the tile, kept at its first cell (valid for any tiling)
+    if (lane < 3 && tadd != 0) atomicAdd(a.K().tstat + 3 * (size_t)c0 + lane, tadd);
     if (MOVE && ballot64(limit) != 0 && lane == 0) atomicOr(&a.K().ctr->status, ST_WALL_LIMIT);
 }
 
-// tiles of four chunks at five waves per SIMD: without the collisions and
-// the sampling they fit 96 VGPRs (a few spills in the cold wall path), and
-// the FP64 2 x 4 tile takes exactly 8 KB of LDS, so 20 tiles share a CU;
-// eight-chunk tiles would spill in the move and stay at four
+// FP32 tiles of four chunks at five waves per SIMD: without the collisions
+// and the sampling they fit 96 VGPRs with a few spills in the cold wall
+// path.  FP64 tiles stay at four: at five their positions spill around the
+// rank and the write-out (measured 367 against 425 us on a 512 x 256 x 100
+// channel).
 template <int TC, int CH, class S>
-__global__ __launch_bounds__(64, CH == 4 ? 5 : 4) void k_classify(StepArgs a)
+__global__ __launch_bounds__(64, (CH == 4 && sizeof(S) == 4) ? 5 : 4) void k_classify(StepArgs a)
 {
     tile_kernel<TC, CH, S, false, true, true>(a);  // whole cells, read once: non-temporal
 }

@@ -65,6 +65,15 @@ struct TileConst {
 // tile reaches its channel's fields with one scalar load from the argument
 constexpr size_t REP_OFFSET = (sizeof(TileConst) + 63) & ~size_t(63);
 
+// The tile table: per tile its first cell, its channel, and that cell's row
+// and column in the channel.  A channel whose rows hold a whole number of
+// tiles, at least two bands wide, lists its tiles in bands of TILE_BAND tiles
+// across x, each band row by row: the tiles of the rows above and below a
+// cell, which read its source groups, then run a few tiles apart instead of
+// a whole row apart and share the cache lines those groups split.
+constexpr int TILE_WORDS = 4;
+constexpr int TILE_BAND = 8;
+
 // One launch of a step kernel.  k_step: the DSMC step `step` (collisions
 // of that step, then the move of step + 1), reading buffer cur and writing
 // 1 - cur.  k_classify (classify = 1): the move of step `step` for the
@@ -75,13 +84,10 @@ constexpr size_t REP_OFFSET = (sizeof(TileConst) + 63) & ~size_t(63);
 // the partition read by the step's sort.
 struct StepArgs {
     const TileConst *kc;
-    const int32_t *tiles;  // [tiles][2]: first cell and replica of every tile of the launch
+    const int32_t *tiles;  // [tiles][TILE_WORDS]: first cell, replica, and the first cell's row and column
     uint32_t step;
     int cur, sample, classify;
     int r;                 // replica of the tile (the launch's, or set by the tile kernel from the table)
-    int c_first;           // >= 0: every tile is in replica r, at a cell that follows from its index (band)
-    int band;              // with c_first: 0 = tile b starts at cell c_first + b * TC; > 0 = the tiles
-                           // run in bands of `band` tiles across x, all rows of a band in turn
     int dev_step;          // step graphs: add the device step base to `step`
     int reseed;            // k_classify: complete a pending reseed (see above)
 
