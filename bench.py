@@ -104,7 +104,18 @@ PMC_CMDS = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fe
             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
             "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --no-hybrid --no-c1 --copy-calibration")
 # kernel-name prefixes of the library's kernels, by profiling id
-KERNEL_PREFIX = {"step": "void dsmc::k_step<", "classify": "void dsmc::k_classify<"}
+KERNEL_PREFIX = {"step": "void dsmc::k_step<", "classify": "void dsmc::k_classify<", "project": "void dsmc::k_project<",
+                 "reseed_gen": "void dsmc::k_reseed_gen<", "lbm": "void dsmc::k_lbm<"}
+# VALU instruction counts of the same cycle (one counter pass): the reseed's
+# FP64 work against the FP64 peak
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "dsmc_cycle_512x256x100_fp64_valu.md")
+VALU_COUNTERS = ("SQ_INSTS_VALU SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_TRANS_F64 "
+                 "SQ_WAVES SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64")
+VALU_CMD = ("rocprofv3 --pmc " + VALU_COUNTERS + " --output-format csv -d gpurun_out/valu -o valu -- "
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --no-hybrid --no-c1")
+FP64_PEAK_TFLOPS = 78.6
+# the chip's vector issue: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 ADJ_TRACE_SUMMARY = os.path.join(ROOT, "profiles", "lbm_adjoint_1024x512_d2q37_kernel_trace.md")
 ADJ_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "lbm_adjoint_1024x512_d2q37_traffic.md")
 ADJ_TRACE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/adj_trace -o trace -- "
@@ -676,6 +687,65 @@ def source_hash() -> str:
     return h.hexdigest()
 
 
+def _stored(summary: str, key: str):
+    """{profiling id: value} of the `key` lines of a committed summary, or {}
+    when the summary is missing or the sources changed since it was made."""
+    try:
+        with open(summary) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return {}
+    got, src = {}, None
+    for ln in lines:
+        if ln.startswith("source_sha256:"):
+            src = ln.split(":", 1)[1].strip()
+        elif ln.startswith(key + " "):
+            kid, v = ln[len(key) + 1:].split(":", 1)
+            got[kid.strip()] = float(v)
+    return got if src == source_hash() else {}
+
+
+def summarize_valu(valu_dir):
+    """VALU instruction counts per launch of the cycle's kernels (one pass of
+    VALU_COUNTERS), written to VALU_SUMMARY."""
+    rows = _counter_rows(glob.glob(os.path.join(valu_dir, "*counter_collection.csv"))[0])
+    per = {}
+    for r in rows:
+        per.setdefault((r["Kernel_Name"], r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    out = ["# VALU instructions per launch: coupling cycle, 512x256 cells x 100 particles/cell, FP64", "",
+           "Command (from the repository root, on one MI355X):", "", "    " + VALU_CMD, "",
+           "Counts are wave instructions (64 lanes).  FP64 flop slots = 64 x (ADD + MUL + TRANS) + 128 x FMA: the",
+           "FP64 work the kernel issues, every lane counted.", "",
+           "| kernel | dispatches | waves | VALU | FP64 add | FP64 mul | FP64 fma | FP64 trans | int32 | int64 |",
+           "|---|---|---|---|---|---|---|---|---|---|"]
+    by_name = {}
+    for (name, _), d in per.items():
+        by_name.setdefault(name, []).append(d)
+    per_id = {}
+    for name in sorted(by_name):
+        if "dsmc::" not in name:
+            continue
+        ds = by_name[name]
+        mean = {c: sum(d.get(c, 0.0) for d in ds) / len(ds) for c in ds[0]}
+        g = lambda c: mean.get("SQ_INSTS_" + c, 0.0)
+        out.append("| `%s` | %d | %.0f | %.0f | %.0f | %.0f | %.0f | %.0f | %.0f | %.0f |" % (
+            name, len(ds), mean.get("SQ_WAVES", 0.0), g("VALU"), g("VALU_ADD_F64"), g("VALU_MUL_F64"),
+            g("VALU_FMA_F64"), g("VALU_TRANS_F64"), g("VALU_INT32"), g("VALU_INT64")))
+        for kid, pre in KERNEL_PREFIX.items():
+            if _kernel_of(name, pre):
+                fl = 64 * (g("VALU_ADD_F64") + g("VALU_MUL_F64") + g("VALU_TRANS_F64")) + 128 * g("VALU_FMA_F64")
+                per_id.setdefault(kid, []).append((len(ds), g("VALU"), fl))
+    out += ["", "Per profiling id (all template variants, weighted by dispatches):", ""]
+    for kid, v in sorted(per_id.items()):
+        n = sum(a for a, _, _ in v)
+        out.append("valu_insts_per_launch %s: %.0f" % (kid, sum(a * b for a, b, _ in v) / n))
+        out.append("fp64_flop_slots_per_launch %s: %.0f" % (kid, sum(a * c for a, _, c in v) / n))
+    out += ["", "source_sha256: " + source_hash()]
+    with open(VALU_SUMMARY, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("wrote", VALU_SUMMARY)
+
+
 def stored_traffic(kernel: str, summary: str = TRAFFIC_SUMMARY):
     """HBM bytes per launch of `kernel` from a committed counter summary, or
     None when the summary is missing or the sources changed since."""
@@ -759,6 +829,8 @@ def summarize(which, trace_dir, fetch_dir, write_dir):
         if calls:
             n = sum(c for c, _ in calls)
             out.append("mean_us %s: %.1f" % (kid, sum(c * a for c, a in calls) / n / 1e3))
+    out.append("")
+    out.append("source_sha256: " + source_hash())
     with open(W["trace_file"], "w") as fh:
         fh.write("\n".join(out) + "\n")
 
@@ -833,6 +905,8 @@ def _parse():
                     help="write the profiles/ summaries from rocprofv3 output directories and exit")
     ap.add_argument("--summarize-adjoint", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="the same for the differentiation workload")
+    ap.add_argument("--summarize-valu", metavar="VALU_DIR",
+                    help="write the VALU-count summary of the cycle from a rocprofv3 --pmc directory and exit")
     ap.add_argument("--summarize-c4", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="the same for the precision workload's steps (--profile-c4)")
     ap.add_argument("--summarize-batched", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
@@ -978,6 +1052,9 @@ def main():
     if args.summarize_c4:
         summarize("c4", *args.summarize_c4)
         return
+    if args.summarize_valu:
+        summarize_valu(args.summarize_valu)
+        return
     if args.summarize_batched:
         summarize("batched", *args.summarize_batched)
         return
@@ -1073,6 +1150,32 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": stored_traffic(dom), "kernel": dom,
                 "bytes_per_launch": nb}
     step_bytes = 80.0 * value  # algorithmic floor of a particle step (read + write the state once)
+    # the mapping kernels, from the committed trace and counter summaries of
+    # this cycle (null when the sources changed since they were made)
+    means = _stored(TRACE_SUMMARY, "mean_us")
+    valu = _stored(VALU_SUMMARY, "valu_insts_per_launch")
+    flops = _stored(VALU_SUMMARY, "fp64_flop_slots_per_launch")
+    project_roof = {"bytes_per_launch": 384 * ncells, "event_us": round(kernels["project"]["us_mean"], 2)
+                    if "project" in kernels else None, "trace_us": means.get("project")}
+    for src in ("event", "trace"):
+        t = project_roof[src + "_us"]
+        project_roof[src + "_frac"] = round(384 * ncells / (t * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4) if t else None
+    if roof is not None and valu.get(dom):
+        # share of the chip's vector-instruction issue the kernel uses
+        roof["valu_issue_frac"] = round(valu[dom] / (kernels[dom]["us_mean"] * 1e-6) / VALU_ISSUE_PER_S, 4)
+    nnew = STRIP * NY * PPC  # about one cell's worth of particles per reseeded cell
+    reseed_roof = None
+    if means.get("reseed_gen") and flops.get("reseed_gen"):
+        t = means["reseed_gen"] * 1e-6
+        reseed_roof = {
+            "kernel": "k_reseed_gen", "trace_us": means["reseed_gen"],
+            "hbm_bytes_per_launch": 296 * len(strip) + 40 * nnew,
+            "hbm_frac": round((296 * len(strip) + 40 * nnew) / t / 1e9 / HBM_PEAK_GBPS, 4),
+            "fp64_flop_slots_per_launch": flops["reseed_gen"],
+            "fp64_flop_slots_per_new_particle": round(flops["reseed_gen"] / nnew, 1),
+            "fp64_tflops": round(flops["reseed_gen"] / t / 1e12, 2), "fp64_peak_tflops": FP64_PEAK_TFLOPS,
+            "fp64_frac": round(flops["reseed_gen"] / t / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "valu_issue_frac": round(valu["reseed_gen"] / t / VALU_ISSUE_PER_S, 4) if valu.get("reseed_gen") else None}
     out = {
         "metric": "particle-steps/s + cell-maps/s; chosen form vs plain FP64 at equal moment error",
         "value": value,
@@ -1094,6 +1197,8 @@ def main():
         "step_roofline": {"bytes_per_particle_step": 80, "achieved_GBps": round(step_bytes / 1e9, 1),
                           "frac": round(step_bytes / 1e9 / HBM_PEAK_GBPS, 4)},
         "roofline": roof,
+        "project_roofline": project_roof,
+        "reseed_roofline": reseed_roof,
         "kernels_us_per_launch": {k: round(v["us_mean"], 2) for k, v in kernels.items()},
         "kernel_ms_per_cycle": {k: round(v["ms_total"] / args.steps, 4) for k, v in kernels.items()},
         "profiled_ms_per_step": 1e3 * (tp1 - tp0) / args.steps,

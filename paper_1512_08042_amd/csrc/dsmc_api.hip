@@ -1362,13 +1362,14 @@ static int project(dsmc_ctx *x, const double *mom, double S_, int64_t ncells, in
         return fail(DSMC_EINVAL, "the third-order equilibrium needs D2Q37");
     ProjectArgs a;
     a.mom = mom;
-    a.S = S_;
     a.f = f_out;
-    a.L = *L;
+    a.L.Q = L->Q;
+    a.L.r = L->r;
+    for (int q = 0; q < L->Q; ++q) a.L.ws[L->Q == 9 ? VelSet<9>::sh[q] : VelSet<37>::sh[q]] = L->w[q];
+    a.rho_scale = 1.0 / (S_ * (double)ppc);
+    a.is1 = 1.0 / std::sqrt(kT);
     a.ncells = (int)ncells;
-    a.ppc = ppc;
     a.order = order;
-    a.s1 = std::sqrt(kT);
     a.equilibrium = equilibrium;
     a.n = n < 0 ? (int)ncells : n;
     a.c_off = c_off;
@@ -1377,7 +1378,12 @@ static int project(dsmc_ctx *x, const double *mom, double S_, int64_t ncells, in
     a.n_stride = n_stride;
     a.nn_out = nn_out < 0 ? ncells : nn_out;
     if (a.n == 0) return DSMC_OK;
-    return launch(x, DSMC_K_PROJECT, s, [&] { k_project<<<grid_threads((size_t)a.n), 256, 0, s>>>(a); });
+    return launch(x, DSMC_K_PROJECT, s, [&] {
+        if (L->Q == 9)
+            k_project<9><<<grid_threads((size_t)a.n), 256, 0, s>>>(a);
+        else
+            k_project<37><<<grid_threads((size_t)a.n), 256, 0, s>>>(a);
+    });
 }
 
 static int map_dsmc_to_lbm_impl(dsmc_ctx *x, int32_t lattice, int32_t order, double *f_out, void *stream)

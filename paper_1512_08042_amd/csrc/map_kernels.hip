@@ -5,15 +5,26 @@
 
 namespace dsmc {
 
-// ---- DSMC2LB (Eq. (discretefunctions)), one thread per cell ------------------
+// ---- DSMC2LB (Eq. (discretefunctions)) -------------------------------------
 // From the cumulative averages of the sampled sums: rho = <N>/ppc (the mass
 // scale of the appendix), the absolute-frame Hermite coefficients a(1..3)
 // of Eq. (nordercoefficients) from the raw velocity moments (in units of
 // sqrt(kT/m)), and f_a = w_a sum_{n<=order} a(n):H(n)(xi_a)/n!.  D2Q9
 // cannot carry H_xxx and H_yyy (they vanish on its nodes): those terms are
-// left out there.
+// left out there.  With `equilibrium` only rho and u enter, a(n) being
+// those of the local equilibrium (rho u, rho u u, rho u u u): Eq.
+// (feq_dsmc).
+// With xi_a = r e_a (e_a integer), the sum over n is a cubic polynomial in
+// e_a whose ten coefficients are formed once per cell; each population is
+// then a few multiply-adds with e_a's components folded in at compile time,
+// all Q stores of a thread issued back to back.  (Splitting a cell's
+// populations over two to eight threads, for more waves in flight, was no
+// faster: 10.4 to 12.0 us against 10.4 us for 131,072 cells on D2Q37.)
+template <int Q>
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
 {
+#pragma clang fp contract(fast)
+    using V = VelSet<Q>;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
     const int c = a.c_off + i * a.c_stride;
@@ -21,56 +32,79 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
     const int nc = a.ncells;
     double m[NMOM];
 #pragma unroll
-    for (int k = 0; k < NMOM; ++k) m[k] = a.mom[(size_t)k * nc + c] / a.S;
-    const int Q = a.L.Q;
-    if (!(m[0] > 0.0)) {
-        for (int q = 0; q < Q; ++q) a.f[(size_t)q * a.nn_out + node] = 0.0;
-        return;
-    }
-    const double s1 = a.s1;
-    const double rho = m[0] / (double)a.ppc;
-    const double ex = (m[1] / m[0]) / s1, ey = (m[2] / m[0]) / s1;
-    const int order = a.order;
-    if (a.equilibrium) {
-        // Eq. (feq_dsmc): w rho [1 + xi.u + ((xi.u)^2 - u.u)/2] (+ the
-        // third-order equilibrium term on a lattice that carries it)
-        const double uu = ex * ex + ey * ey;
-        for (int q = 0; q < Q; ++q) {
-            const double cu = a.L.xi[q][0] * ex + a.L.xi[q][1] * ey;
-            double eq = 1.0 + cu + 0.5 * (cu * cu - uu);
-            if (order >= 3) eq += cu * (cu * cu - 3.0 * uu) / 6.0;
-            a.f[(size_t)q * a.nn_out + node] = a.L.w[q] * rho * eq;
+    for (int k = 0; k < NMOM; ++k) m[k] = a.mom[(size_t)k * nc + c];
+    // coefficients of e^0, e_x, e_y, e_x^2, e_x e_y, e_y^2, e_x^3, e_x^2 e_y, e_x e_y^2, e_y^3
+    double p0 = 0.0, px = 0.0, py = 0.0, pxx = 0.0, pxy = 0.0, pyy = 0.0;
+    double pxxx = 0.0, pxxy = 0.0, pxyy = 0.0, pyyy = 0.0;
+    if (m[0] > 0.0) {
+        const int order = a.order;
+        const double r = a.L.r, r2 = r * r, r3 = r2 * r;
+        const double rho = m[0] * a.rho_scale;
+        const double im = a.is1 / m[0];
+        const double ex = m[1] * im, ey = m[2] * im;
+        double a1x = 0.0, a1y = 0.0, a2xx = 0.0, a2xy = 0.0, a2yy = 0.0;
+        double a3xxx = 0.0, a3xxy = 0.0, a3xyy = 0.0, a3yyy = 0.0;
+        if (order >= 1) {
+            a1x = rho * ex;
+            a1y = rho * ey;
         }
-        return;
-    }
-    const double s2 = s1 * s1, s3 = s2 * s1;
-    const double exx = (m[3] / m[0]) / s2, exy = (m[4] / m[0]) / s2, eyy = (m[5] / m[0]) / s2;
-    const double exxx = (m[6] / m[0]) / s3, exxy = (m[7] / m[0]) / s3;
-    const double exyy = (m[8] / m[0]) / s3, eyyy = (m[9] / m[0]) / s3;
-    const double a1x = rho * ex, a1y = rho * ey;
-    const double a2xx = rho * (exx - 1.0), a2xy = rho * exy, a2yy = rho * (eyy - 1.0);
-    const double a3xxx = rho * (exxx - 3.0 * ex), a3xxy = rho * (exxy - ey);
-    const double a3xyy = rho * (exyy - ex), a3yyy = rho * (eyyy - 3.0 * ey);
-    for (int q = 0; q < Q; ++q) {
-        const double x = a.L.xi[q][0], y = a.L.xi[q][1];
-        double v = rho;
-        if (order >= 1) v += a1x * x + a1y * y;
-        if (order >= 2) {
-            const double hxx = x * x - 1.0, hxy = x * y, hyy = y * y - 1.0;
-            v += 0.5 * (a2xx * hxx + 2.0 * a2xy * hxy + a2yy * hyy);
-        }
-        if (order >= 3) {
-            const double hxxy = x * x * y - y, hxyy = x * y * y - x;
-            double t3 = 3.0 * a3xxy * hxxy + 3.0 * a3xyy * hxyy;
-            if (Q != 9) {
-                const double hxxx = x * x * x - 3.0 * x, hyyy = y * y * y - 3.0 * y;
-                t3 += a3xxx * hxxx + a3yyy * hyyy;
+        if (a.equilibrium) {
+            if (order >= 2) {
+                a2xx = a1x * ex;
+                a2xy = a1x * ey;
+                a2yy = a1y * ey;
             }
-            v += t3 / 6.0;
+            if (order >= 3) {
+                a3xxx = a2xx * ex;
+                a3xxy = a2xx * ey;
+                a3xyy = a2xy * ey;
+                a3yyy = a2yy * ey;
+            }
+        } else {
+            const double im2 = im * a.is1, im3 = im2 * a.is1;
+            if (order >= 2) {
+                a2xx = rho * (m[3] * im2 - 1.0);
+                a2xy = rho * (m[4] * im2);
+                a2yy = rho * (m[5] * im2 - 1.0);
+            }
+            if (order >= 3) {
+                a3xxx = rho * (m[6] * im3 - 3.0 * ex);
+                a3xxy = rho * (m[7] * im3 - ey);
+                a3xyy = rho * (m[8] * im3 - ex);
+                a3yyy = rho * (m[9] * im3 - 3.0 * ey);
+            }
         }
-        a.f[(size_t)q * a.nn_out + node] = a.L.w[q] * v;
+        if (Q == 9) a3xxx = a3yyy = 0.0;
+        // a(2):H(2)/2 and a(3):H(3)/6 written out in powers of e = xi / r
+        p0 = rho - 0.5 * (a2xx + a2yy);
+        px = r * (a1x - 0.5 * (a3xxx + a3xyy));
+        py = r * (a1y - 0.5 * (a3yyy + a3xxy));
+        pxx = 0.5 * r2 * a2xx;
+        pxy = r2 * a2xy;
+        pyy = 0.5 * r2 * a2yy;
+        pxxx = r3 * a3xxx * (1.0 / 6.0);
+        pxxy = 0.5 * r3 * a3xxy;
+        pxyy = 0.5 * r3 * a3xyy;
+        pyyy = r3 * a3yyy * (1.0 / 6.0);
     }
+    static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int X = V::ex[q], Y = V::ey[q];
+        double v = p0;
+        cmad<X>(v, px);
+        cmad<Y>(v, py);
+        cmad<X * X>(v, pxx);
+        cmad<X * Y>(v, pxy);
+        cmad<Y * Y>(v, pyy);
+        cmad<X * X * X>(v, pxxx);
+        cmad<X * X * Y>(v, pxxy);
+        cmad<X * Y * Y>(v, pxyy);
+        cmad<Y * Y * Y>(v, pyyy);
+        a.f[(size_t)q * a.nn_out + node] = a.L.ws[V::sh[q]] * v;
+    });
 }
+template __global__ void k_project<9>(ProjectArgs);
+template __global__ void k_project<37>(ProjectArgs);
 
 // ---- LB2DSMC (Section 2.2, Table 1) ------------------------------------------
 // Table 1 steps 1-3 on node populations f[q * stride]: rho, u, comoving and

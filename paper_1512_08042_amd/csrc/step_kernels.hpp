@@ -187,19 +187,6 @@ struct AdoptArgs {
     int64_t n;
 };
 
-struct ProjectArgs {
-    const double *mom;  // sums [11][ncells]
-    double S;           // number of samples the sums hold (1 for averages)
-    double *f;          // [Q][nn_out]
-    Lattice L;
-    int ncells, ppc, order;
-    double s1;          // sqrt(kT/m)
-    int equilibrium;    // 1: only rho and u enter (Eq. (feq_dsmc)); 0: the full projection
-    // cells c_off + i c_stride (i < n) project to nodes n_off + i n_stride of f
-    int n, c_off, c_stride, n_off, n_stride;
-    int64_t nn_out;
-};
-
 struct ReseedArgs {
     const double *f;     // [Q][ncells]
     const int32_t *cells;
@@ -287,6 +274,19 @@ struct LatShells {
     double ws[8];  // weight of each shell
 };
 
+// DSMC2LB of n cells c_off + i c_stride into nodes n_off + i n_stride of f
+struct ProjectArgs {
+    const double *mom;  // sums [11][ncells]
+    double *f;          // [Q][nn_out]
+    LatShells L;        // r and the shell weights
+    double rho_scale;   // 1 / (samples the sums hold * particles per cell)
+    double is1;         // 1 / sqrt(kT/m)
+    int ncells, order;
+    int equilibrium;    // 1: only rho and u enter (Eq. (feq_dsmc)); 0: the full projection
+    int n, c_off, c_stride, n_off, n_stride;
+    int64_t nn_out;
+};
+
 struct LbmArgs {
     const double *f;
     double *ft;
@@ -359,6 +359,7 @@ __global__ void k_set_step_base(Counters *c, uint32_t step);
 __global__ void k_replica_stats(const unsigned long long *tstat, const RepConst *rep, unsigned long long *out);
 __global__ void k_far_reset(Counters *c, int slot);
 
+template <int Q>
 __global__ void k_project(ProjectArgs a);
 __global__ void k_reseed_prep(ReseedArgs a);
 __global__ void k_reseed_count(ReseedArgs a);
