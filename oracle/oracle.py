@@ -334,6 +334,7 @@ class Sim:
             raise ValueError("oracle rejected the configuration")
         self.state32 = bool(state32)
         self._lib().or_set_state32(self._h, 1 if self.state32 else 0)
+        self._destroy = self._lib().or_destroy  # held: at interpreter exit the module may be gone
 
     def _lib(self):
         return lib(self.threads)
@@ -341,7 +342,7 @@ class Sim:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            self._lib().or_destroy(h)
+            self._destroy(h)
             self._h = None
 
     def init_maxwell(self):

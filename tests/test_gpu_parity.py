@@ -129,6 +129,36 @@ def test_channel_c1_steps_and_moments(nbar_mode):
     assert np.allclose(f, O.dsmc2lb(want, 50, O.lattice(9), 3), rtol=1e-11, atol=1e-14)
 
 
+def test_channel_c1_full_run():
+    # the quasi-1-D channel in full, as the benchmark runs it: 2000 steps
+    # sampled every step, the D2Q9 projection of the cumulative averages
+    # every 10 steps (200 events); every event's populations against the
+    # oracle's, then the cells and counters (exact) and the state at the end.
+    # Over 2000 steps the few-ulp differences of the transcendental functions
+    # enter at every collision and wall bounce, and a bounce divides by the
+    # normal speed: measured after 2000 steps, positions differ by up to
+    # 3.8e-10 cell and velocities by 6e-14 (thermal speed 1), while every
+    # integer decision is the oracle's.  The bars are 1e-8 and 1e-11.
+    from paper_1512_08042_amd.config import body_force
+
+    g = body_force(0.1, 64, 0.1)
+    ch, ref, _ = _pair(1, 64, 50, 0.1, g=g, seed=1)
+    lat = O.lattice(9)
+    for ev in range(200):
+        ch.step(10, sample_every=1)
+        ref.step(10, sample_every=1)
+        f = ch.map_to_lbm(9, 2).cpu().numpy()
+        want = O.dsmc2lb(ref.averages(), 50, lat, 2)
+        err = float(np.abs(f - want).max() / np.abs(want).max())
+        assert err <= 1e-12, "event %d: populations differ by %.3g of their largest" % (ev, err)
+    assert np.array_equal(ch.cell_start().cpu().numpy(), ref.cells()[0]), "cell_start after 2000 steps"
+    _assert_cells(ch, ref)
+    _assert_counters(ch, ref)
+    for name, g, w, tol in zip("x y vx vy vz".split(), ch.particles(), ref.particles(), (1e-8, 1e-8, 1e-11, 1e-11, 1e-11)):
+        d = float(np.abs(g.cpu().numpy() - w).max())
+        assert d <= tol, "%s differs by %.3g after 2000 steps" % (name, d)
+
+
 def test_long_jumps_and_small_nx():
     # a time step of several cells makes many particles jump more than one
     # cell: they go through the long-jump list; nx = 1 and 2 alias the x

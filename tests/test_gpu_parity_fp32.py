@@ -168,3 +168,33 @@ def test_fp32_full_size_one_step():
     ref.step(1, sample_every=1)
     _assert_state32(ch, ref, what="512x256x100 after 1 step")
     _assert_counters(ch, ref)
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+def test_precision_workload_full_size(bits):
+    # the precision workload at its full size, in the launch configuration
+    # the benchmark times: 2048 x 1024 cells x 50 particles (104,857,600),
+    # Kn 0.02, Ma 0.1, seed 4, from the Maxwellian start; two steps sampled
+    # every step, against the oracle (its OpenMP build, the same bits as the
+    # serial one) element by element
+    D, ChannelConfig = _gpu()
+    cfg = ChannelConfig(nx=2048, ny=1024, ppc=50, kn=0.02, mach=0.1, seed=4, state_bits=bits).resolved()
+    ch = D.Channel(cfg)
+    ch.step(2, sample_every=1)
+    ref = O.Sim(2048, 1024, 50, 0.02, dt=cfg.dt, g=cfg.body_force_x, seed=4, capacity=cfg.capacity,
+                state32=bits == 32, threads=0)
+    ref.init_maxwell()
+    ref.step(2, sample_every=1)
+    assert np.array_equal(ch.cell_start().cpu().numpy(), ref.cells()[0]), "cell_start"
+    _assert_counters(ch, ref)
+    tol = F32_TOL if bits == 32 else 1e-12
+    for name, g, w in zip("x y vx vy vz".split(), ch.particles(), ref.particles()):
+        g = g.cpu().numpy().astype(np.float64)
+        bad = ~np.isclose(g, w, rtol=tol, atol=tol)
+        assert not bad.any(), "%s (%d-bit) differs at %d slots (first %s)" % (name, bits, bad.sum(), np.where(bad)[0][:3])
+        del g, w, bad
+    avg = ch.sample_moments().cpu().numpy()
+    want = ref.averages()
+    scale = np.abs(want).max(axis=1, keepdims=True) + 1.0
+    assert np.all(np.abs(avg - want) <= 1e-12 * scale), "moment averages"
+    ch.close()
