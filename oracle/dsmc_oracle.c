@@ -233,11 +233,11 @@ static void sort_by_cell(or_sim *s)
 #pragma omp parallel num_threads(T)
     {
 #ifdef _OPENMP
-        int t = omp_get_thread_num();
+        const int t = omp_get_thread_num(), Tn = omp_get_num_threads(); /* Tn <= T */
 #else
-        int t = 0;
+        const int t = 0, Tn = 1;
 #endif
-        int64_t lo = s->n * t / T, hi = s->n * (t + 1) / T;
+        int64_t lo = s->n * t / Tn, hi = s->n * (t + 1) / Tn;
         int32_t *mine = cnt + (size_t)t * (nc + 1);
         for (int64_t p = lo; p < hi; ++p) {
             s->cellid[p] = cell_of(s, s->x[p], s->y[p]);
@@ -249,7 +249,7 @@ static void sort_by_cell(or_sim *s)
             int32_t acc = 0;
             for (int32_t c = 0; c < nc; ++c) {
                 s->cell_start[c] = acc;
-                for (int u = 0; u < T; ++u) {
+                for (int u = 0; u < Tn; ++u) {
                     int32_t k = cnt[(size_t)u * (nc + 1) + c];
                     cnt[(size_t)u * (nc + 1) + c] = acc;
                     acc += k;

@@ -933,8 +933,8 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     __shared__ TileLds<TC, CH, S> L;
     constexpr int T = 64 / TC, SPAN = T / 16;
     const int lane = threadIdx.x;
-    // the tile: up to TC consecutive cells of one channel (from the launch's
-    // arguments when it covers one channel, else from the tile table)
+    // the tile: up to TC consecutive cells of one channel, its entry in the
+    // tile table (first cell, channel, that cell's row and column)
     // Odd steps run the tiles in the opposite order.  The state is larger than
     // the memory-side cache, and each step reads what the one before wrote; run
     // backwards, a step starts on the lines written last, which are the ones
