@@ -256,7 +256,7 @@ Layout make_layout(const dsmc_config &c, size_t nc, size_t nrep)
     L.kc = take(REP_OFFSET + nrep * sizeof(RepConst));  // TileConst, then the channels' constants
     L.ctr = take(sizeof(Counters));
     L.rep = L.kc + REP_OFFSET;
-    L.tiles = take(TILE_WORDS * nc * 4);  // at most one tile per cell
+    L.tiles = take(2 * TILE_WORDS * nc * 4);  // at most one tile per cell, in two orders (see set_tiling)
     L.cell_rep = take(nc * 4);
     L.rstat = take(3 * nrep * 8);
     L.total = o;
@@ -356,7 +356,7 @@ struct dsmc_ctx {
     hipStream_t side[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
     bool forked = false;  // side streams and events exist
-    std::vector<int32_t> tiles_host;
+    std::vector<int32_t> tiles_host;       // the step's order, then the classify pass's
     int particles_per_tile;
     // a captured step graph: nsteps steps (a dsmc_step call) replayable from
     // any even step aligned with its sampling period
@@ -539,10 +539,11 @@ int set_tiling(dsmc_ctx *x, int ppt, hipStream_t s)
     }
     x->groups.clear();
     x->tiles_host.clear();
-    auto add_tile = [&](int r, int c) {
+    std::vector<int32_t> rows;  // the same tiles in row-major order
+    auto add_tile = [&](std::vector<int32_t> &v, int r, int c) {
         const RepConst &R = x->reps[r];
         const int nx = R.G.nx, ci = c - R.cbase;
-        x->tiles_host.insert(x->tiles_host.end(), {c, r, ci / nx, ci % nx});
+        v.insert(v.end(), {c, r, ci / nx, ci % nx});
     };
     for (int k = 0; k < 4; ++k) {
         dsmc_ctx::TileGroup g;
@@ -559,15 +560,17 @@ int set_tiling(dsmc_ctx *x, int ppt, hipStream_t s)
                 for (int b0 = 0; b0 < tpr; b0 += TILE_BAND)
                     for (int iy = 0; iy < ny; ++iy)
                         for (int t = b0; t < std::min(b0 + TILE_BAND, tpr); ++t)
-                            add_tile(r, R.cbase + iy * nx + t * g.tc);
+                            add_tile(x->tiles_host, r, R.cbase + iy * nx + t * g.tc);
             } else {
-                for (int c = R.cbase; c < R.cend; c += g.tc) add_tile(r, c);
+                for (int c = R.cbase; c < R.cend; c += g.tc) add_tile(x->tiles_host, r, c);
             }
+            for (int c = R.cbase; c < R.cend; c += g.tc) add_tile(rows, r, c);
         }
         g.ntiles = (int)(x->tiles_host.size() / TILE_WORDS) - g.tile0;
         if (g.ntiles > 0) x->groups.push_back(g);
     }
     x->ntiles = (int)(x->tiles_host.size() / TILE_WORDS);
+    x->tiles_host.insert(x->tiles_host.end(), rows.begin(), rows.end());
     x->particles_per_tile = ppt;
     if (hipMemcpyAsync(x->tiles, x->tiles_host.data(), x->tiles_host.size() * 4, hipMemcpyHostToDevice, s) !=
         hipSuccess)
@@ -592,7 +595,9 @@ int launch_tiles(const dsmc_ctx *x, int kind, bool move, hipStream_t s, const St
             if (hipStreamWaitEvent(gs, x->ev_fork, 0) != hipSuccess) return DSMC_EHIP;
         }
         StepArgs a = a0;
-        a.tiles = x->tiles + TILE_WORDS * (size_t)g.tile0;
+        // the classify pass reads whole cells in place and streams best in
+        // row order; the step's gathers read across rows and take the bands
+        a.tiles = x->tiles + TILE_WORDS * ((kind == 0 ? (size_t)x->ntiles : 0) + (size_t)g.tile0);
         const unsigned n = (unsigned)g.ntiles;
 #define DSMC_LAUNCH(TC, CH, S)                                   \
     do {                                                         \
