@@ -1001,23 +1001,32 @@ def c1_benchmark():
     events = c["steps"] // c["map_every"]
     cfg = ChannelConfig(nx=c["nx"], ny=c["ny"], ppc=c["ppc"], kn=c["kn"], mach=c["mach"], seed=c["seed"]).resolved()
 
-    def gpu_run():
+    def gpu_run(graph):
+        # eager steps, or the 10 steps of an event replayed from a HIP graph
+        # (the replays equal eager steps bit for bit)
         ch = D.Channel(cfg)
+        stream = torch.cuda.Stream()
         f = torch.empty((9, c["nx"] * c["ny"]), dtype=torch.float64, device="cuda")
+        if graph:
+            ch.graph_create(c["map_every"], sample_every=1, stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(events):
-            ch.step(c["map_every"], sample_every=1)
-            ch.map_to_lbm(9, 2, out=f)
-        torch.cuda.synchronize()
+            if graph:
+                ch.graph_launch(stream=stream)
+            else:
+                ch.step(c["map_every"], sample_every=1, stream=stream)
+            ch.map_to_lbm(9, 2, out=f, stream=stream)
+        stream.synchronize()
         dt = time.perf_counter() - t0
         out = f.cpu().numpy()
         st = ch.status()
         ch.close()
         return dt, out, st
 
-    gpu_run()  # first launches (code loading) untimed
-    t_gpu, f_gpu, st = gpu_run()
+    gpu_run(False)  # first launches (code loading) untimed
+    t_gpu, f_gpu, st = gpu_run(False)
+    t_graph, f_graph, _ = gpu_run(True)
     lat = O.lattice(9)
     res = {}
     for name, threads in (("single_thread", None), ("omp", 0)):
@@ -1037,6 +1046,10 @@ def c1_benchmark():
             "gpu": {"particle_steps_per_s": n * c["steps"] / t_gpu, "seconds": round(t_gpu, 4),
                     "us_per_step": 1e6 * t_gpu / c["steps"], "cell_maps_per_s": c["nx"] * c["ny"] * events / t_gpu,
                     "status_bits": st["bits"]},
+            "gpu_graph": {"particle_steps_per_s": n * c["steps"] / t_graph, "seconds": round(t_graph, 4),
+                          "us_per_step": 1e6 * t_graph / c["steps"],
+                          "cell_maps_per_s": c["nx"] * c["ny"] * events / t_graph,
+                          "equals_eager_bitwise": bool(np.array_equal(f_graph, f_gpu))},
             "oracle": res,
             "final_populations_max_abs_diff_over_max": float(np.abs(f_gpu - f_or).max() / scale)}
 
