@@ -159,3 +159,22 @@ def test_wall_and_inflow_modes_validate_without_gpu():
     assert L.dsmc_project_equilibrium(p, 0, 100, 1.0, 9, 2, p, None) == _lib.EINVAL
     h = _lib.Hybrid(walls, 4, 2, 0, 2, 0, 0)
     assert L.dsmc_hybrid_cycle(None, ctypes.byref(h), p, p, None, None) == _lib.EINVAL
+
+
+def test_size_limits():
+    # slots are 32-bit (capacity up to 2^31 - 1) and cells fit 30 bits
+    # (nx * ny < 2^30): the largest sizes pass, one more is rejected, and the
+    # sizes of the largest grid come out without overflow
+    L = _lib.lib()
+    s = _lib.Sizes()
+    c = _lib.Config(4, 8, 10, 0, 2 ** 31 - 1, 0.1, 0.1, 0.0, 1.0, 6.0, 1, 0, 0)
+    assert L.dsmc_query_sizes(ctypes.byref(c), ctypes.byref(s)) == 0
+    assert s.state_array_bytes == (2 ** 31 - 1) * 8
+    c.capacity = 2 ** 31
+    assert L.dsmc_query_sizes(ctypes.byref(c), ctypes.byref(s)) == _lib.EINVAL
+    big = _lib.Config(1, 2 ** 30 - 1, 1, 0, 2 ** 31 - 1, 0.1, 0.1, 0.0, 1.0, 6.0, 1, 0, 0)
+    assert L.dsmc_query_sizes(ctypes.byref(big), ctypes.byref(s)) == 0
+    assert s.ncells == 2 ** 30 - 1 and s.workspace_bytes > 100 * (2 ** 30 - 1)
+    for nx, ny in ((2 ** 15, 2 ** 15), (1, 2 ** 30), (70000, 40000)):
+        c = _lib.Config(nx, ny, 1, 0, 1000, 0.1, 0.1, 0.0, 1.0, 6.0, 1, 0, 0)
+        assert L.dsmc_query_sizes(ctypes.byref(c), ctypes.byref(s)) == _lib.EINVAL, (nx, ny)
