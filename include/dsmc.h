@@ -124,7 +124,7 @@ typedef struct dsmc_views {
 
 typedef struct dsmc_status {
     uint32_t bits;           /* DSMC_ST_* */
-    uint32_t reserved;
+    uint32_t moved;          /* 1: the state is moved for the coming step (see dsmc_step_moved) */
     int64_t n_particles;     /* current particle count */
     uint64_t ncoll;          /* accepted collisions since init */
     uint64_t ncand;          /* collision candidates since init */
@@ -157,6 +157,24 @@ int dsmc_init(const dsmc_config *cfg, const dsmc_buffers *buf, int32_t mode, int
  * sample_every > 0, one sample of the per-cell velocity moments (the
  * cumulative averages that feed DSMC2LB, Section 2.1).  Errors: DSMC_EINVAL. */
 int dsmc_step(dsmc_ctx *ctx, int32_t nsteps, int32_t sample_every, void *stream);
+
+/* dsmc_step that leaves the state moved.  Steps are those of dsmc_step
+ * (Eq. (collisionnumber) and the cycle of Section 2.1); internally every
+ * step ends by moving its particles for the next step and partitioning
+ * them by cell and direction, and a dsmc_step call's last step instead
+ * writes them settled (sorted into their cells), so that the next call
+ * begins with a pass that moves them again.  Here the last step moves as
+ * the others do and the next call (either kind) begins without that pass.
+ * Every later result is identical to a run of dsmc_step calls; the wall
+ * hits of the coming step's move are counted in this call.  While moved
+ * (dsmc_status.moved = 1) the state buffers do not hold cell-sorted
+ * particles, map_lbm_to_dsmc and dsmc_graph_launch of a dsmc_graph_create
+ * graph return DSMC_ESTATE, and a dsmc_step call with nsteps >= 1 settles
+ * the state again.  Moments, the mapping to the lattice and the status are
+ * available as usual.  nsteps = 0 runs only the moving pass (none on a
+ * moved state).  For loops that step and sample without reading particles
+ * between calls.  Errors: DSMC_EINVAL. */
+int dsmc_step_moved(dsmc_ctx *ctx, int32_t nsteps, int32_t sample_every, void *stream);
 
 /* The cumulative averages of the DSMC moments that DSMC2LB projects
  * (Section 2.1: the coupling cells' averaged hydrodynamic variables, scaled
@@ -415,6 +433,12 @@ int dsmc_replica_counters(dsmc_ctx *ctx, uint64_t *out, void *stream);
  * Errors: DSMC_EINVAL, DSMC_ESTATE, DSMC_EHIP. */
 int dsmc_graph_create(dsmc_ctx *ctx, int32_t nsteps, int32_t sample_every, void *stream);
 int dsmc_graph_launch(dsmc_ctx *ctx, void *stream);
+
+/* The same for dsmc_step_moved calls: the graph replays nsteps steps of a
+ * moved state and leaves it moved.  dsmc_graph_launch first runs the moving
+ * pass, eagerly, on a settled state; a graph from dsmc_graph_create needs a
+ * settled one.  Errors as dsmc_graph_create. */
+int dsmc_graph_create_moved(dsmc_ctx *ctx, int32_t nsteps, int32_t sample_every, void *stream);
 
 /* Synchronise the context's last stream and read the status word and
  * counters; clear != 0 resets the status bits.  Completes a pending reseed

@@ -25,7 +25,7 @@ EXPORTS = ("dsmc_query_sizes", "dsmc_init", "dsmc_step", "dsmc_sample_moments", 
            "lbm_hermite_moments", "lbm_hermite_moments_adjoint", "dsmc_project_moments_adjoint",
            "dsmc_batch_query_sizes", "dsmc_batch_init", "dsmc_set_tiling", "dsmc_autotune", "dsmc_replica_counters",
            "dsmc_graph_create", "dsmc_graph_launch", "dsmc_project_equilibrium", "dsmc_hybrid_cycle",
-           "dsmc_last_error", "lbm_adjoint_step_noalloc")
+           "dsmc_last_error", "lbm_adjoint_step_noalloc", "dsmc_step_moved", "dsmc_graph_create_moved")
 
 
 class Config(ctypes.Structure):
@@ -58,7 +58,7 @@ class Views(ctypes.Structure):
 
 
 class Status(ctypes.Structure):
-    _fields_ = [("bits", c_u32), ("reserved", c_u32), ("n_particles", c_i64), ("ncoll", c_u64), ("ncand", c_u64),
+    _fields_ = [("bits", c_u32), ("moved", c_u32), ("n_particles", c_i64), ("ncoll", c_u64), ("ncand", c_u64),
                 ("nwall", c_u64), ("nfar", c_u64)]
 
 
@@ -91,6 +91,7 @@ def lib():
         L.dsmc_query_sizes.argtypes = [P(Config), P(Sizes)]
         L.dsmc_init.argtypes = [P(Config), P(Buffers), c_i32, c_i64, c_p, P(c_p)]
         L.dsmc_step.argtypes = [c_p, c_i32, c_i32, c_p]
+        L.dsmc_step_moved.argtypes = [c_p, c_i32, c_i32, c_p]
         L.dsmc_sample_moments.argtypes = [c_p, c_p, c_i32, c_p]
         L.map_dsmc_to_lbm.argtypes = [c_p, c_i32, c_i32, c_p, c_p]
         L.dsmc_project_moments.argtypes = [c_p, c_i64, c_i32, c_d, c_i32, c_i32, c_p, c_p]
@@ -112,6 +113,7 @@ def lib():
         L.dsmc_autotune.argtypes = [c_p, c_i32, c_i32, P(Tuning), c_p]
         L.dsmc_replica_counters.argtypes = [c_p, P(c_u64), c_p]
         L.dsmc_graph_create.argtypes = [c_p, c_i32, c_i32, c_p]
+        L.dsmc_graph_create_moved.argtypes = [c_p, c_i32, c_i32, c_p]
         L.dsmc_graph_launch.argtypes = [c_p, c_p]
         L.dsmc_project_equilibrium.argtypes = [c_p, c_i64, c_i32, c_d, c_i32, c_i32, c_p, c_p]
         L.dsmc_hybrid_cycle.argtypes = [c_p, P(Hybrid), c_p, c_p, c_p, c_p]

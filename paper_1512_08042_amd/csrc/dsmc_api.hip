@@ -364,13 +364,14 @@ struct dsmc_ctx {
     hipGraph_t graph;
     hipGraphExec_t gexec;
     int32_t g_nsteps, g_sample_every, g_cur;
+    bool g_moved;  // captured from dsmc_graph_create_moved: replays a moved state and leaves it moved
     int64_t step, nsamples, reseed_events;
     // Inside a dsmc_step call the state between steps is kept already moved
     // for the coming step and partitioned by direction inside every cell
     // (with its group sizes and long-jump list, buffers of parity step & 1);
-    // at the end of every call it is settled (moved particles sorted into
-    // their cells, collided and sampled).  `classified` is true only inside
-    // a call.
+    // at the end of a dsmc_step call it is settled (moved particles sorted
+    // into their cells, collided and sampled), at the end of a
+    // dsmc_step_moved call it stays moved.  `classified`: the state is moved.
     bool classified;
     // A reseed leaves the state pending: buffer cur still holds the old
     // particles (cell starts cs[cur]), buffer 1 - cur the marked cells' new
@@ -1275,7 +1276,9 @@ int adjoint_step_on(const lbm_config *cfg, const double *f_n, const double *lam_
 
 extern "C" {
 
-static int dsmc_step_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
+// nsteps steps; the state ends settled, or with moved_end moved for the
+// coming step (the call's last step moves and partitions as the others do)
+static int step_run(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, bool moved_end, void *stream)
 {
     if (!x) return DSMC_EINVAL;
     if (nsteps < 0 || sample_every < 0) return fail(DSMC_EINVAL, "nsteps and sample_every must be >= 0");
@@ -1283,7 +1286,7 @@ static int dsmc_step_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, voi
     x->last = s;
     const int nc = x->ncells;
     int rc_tiles = DSMC_OK;
-    if (nsteps > 0 && !x->classified) {
+    if ((nsteps > 0 || moved_end) && !x->classified) {
         // moves of the coming step for a state set or changed from outside
         const int p = (int)(x->step & 1);
         TRY(fill_i32(x->farcnt, 2 * (size_t)nc, 0, s));
@@ -1324,7 +1327,7 @@ static int dsmc_step_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, voi
         }));
 
         const bool sample = sample_every > 0 && ((x->step + 1) % sample_every) == 0;
-        const bool move = it + 1 < nsteps;  // the call's last step leaves the state settled
+        const bool move = moved_end || it + 1 < nsteps;  // a dsmc_step call's last step leaves the state settled
         const StepArgs a = step_args(x, cur, x->step, sample, false);
         TRY(launch(x, DSMC_K_STEP, s, [&] { rc_tiles = launch_tiles(x, 1, move, s, a); }));
         TRY(rc_tiles);
@@ -1332,8 +1335,18 @@ static int dsmc_step_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, voi
         if (sample) x->nsamples += 1;
         x->step += 1;
     }
-    x->classified = false;
+    if (nsteps > 0) x->classified = moved_end;
     return DSMC_OK;
+}
+
+static int dsmc_step_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
+{
+    return step_run(x, nsteps, sample_every, false, stream);
+}
+
+static int dsmc_step_moved_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
+{
+    return step_run(x, nsteps, sample_every, true, stream);
 }
 
 static int dsmc_sample_moments_impl(dsmc_ctx *x, double *out, int32_t reset, void *stream)
@@ -1457,6 +1470,9 @@ static int map_lbm_to_dsmc_impl(dsmc_ctx *x, int32_t lattice, int32_t order, con
     if (!L || (order != 2 && order != 3) || !f_in || nsel < 0 || (nsel > 0 && !cell_ids))
         return fail(DSMC_EINVAL, "lattice must be 9 or 37, order 2 or 3, f_in non-NULL, nsel >= 0 with cell_ids");
     if (nsel > x->ncells) return fail(DSMC_EINVAL, "nsel exceeds the number of cells");
+    if (x->classified)
+        return fail(DSMC_ESTATE, "the state is moved (dsmc_step_moved): a reseed needs the settled state that a "
+                                 "dsmc_step call leaves");
     hipStream_t s = S(stream);
     x->last = s;
     TRY(settle(x, s));
@@ -1673,7 +1689,7 @@ static int dsmc_read_status_impl(dsmc_ctx *x, dsmc_status *out, int32_t clear, v
         return DSMC_EHIP;
     if (hipStreamSynchronize(s) != hipSuccess) return DSMC_EHIP;
     out->bits = h.status;
-    out->reserved = 0;
+    out->moved = x->classified ? 1u : 0u;
     out->n_particles = n;
     out->ncoll = h.ncoll;
     out->ncand = h.ncand;
@@ -1736,7 +1752,7 @@ static int dsmc_profile_read_impl(dsmc_ctx *x, int32_t kernel, double *ms_total,
     return DSMC_OK;
 }
 
-static int dsmc_graph_create_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
+static int graph_create(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, bool moved, void *stream)
 {
     if (!x) return DSMC_EINVAL;
     if (nsteps < 2 || (nsteps & 1) || sample_every < 0)
@@ -1745,19 +1761,22 @@ static int dsmc_graph_create_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_ev
         return fail(DSMC_EINVAL, "nsteps must be a multiple of sample_every");
     hipStream_t s = S(stream);
     if (s == nullptr) return fail(DSMC_EINVAL, "capture needs a created stream, not the null stream");
-    TRY(settle(x, s));                     // (the graph starts from a settled state)
+    TRY(settle(x, s));  // a pending reseed is completed first
     TRY(release_graph(x));
     // capture one dsmc_step call with steps counted from 0; the host-side
     // bookkeeping of the capture is undone afterwards (nothing ran)
+    // (a graph of dsmc_step calls begins with the moving pass of a settled
+    // state; one of dsmc_step_moved calls starts from, and ends in, a moved one)
     const int64_t step = x->step, nsamples = x->nsamples;
     const int cur = x->cur;
-    const bool prof = x->prof;
+    const bool prof = x->prof, classified = x->classified;
     x->step = 0;
     x->prof = false;
     x->capturing = true;
+    x->classified = moved;
     int rc = DSMC_OK;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = DSMC_EHIP;
-    const int rc_step = rc == DSMC_OK ? dsmc_step(x, nsteps, sample_every, stream) : DSMC_OK;
+    const int rc_step = rc == DSMC_OK ? step_run(x, nsteps, sample_every, moved, stream) : DSMC_OK;
     hipGraph_t g = nullptr;
     if (rc == DSMC_OK && hipStreamEndCapture(s, &g) != hipSuccess) rc = DSMC_EHIP;
     if (rc == DSMC_OK) rc = rc_step;
@@ -1767,7 +1786,7 @@ static int dsmc_graph_create_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_ev
     x->nsamples = nsamples;
     x->cur = cur;
     x->prof = prof;
-    x->classified = false;
+    x->classified = classified;
     if (rc != DSMC_OK) {
         if (g) (void)hipGraphDestroy(g);
         x->gexec = nullptr;
@@ -1777,6 +1796,7 @@ static int dsmc_graph_create_impl(dsmc_ctx *x, int32_t nsteps, int32_t sample_ev
     x->g_nsteps = nsteps;
     x->g_sample_every = sample_every;
     x->g_cur = cur;
+    x->g_moved = moved;
     return DSMC_OK;
 }
 
@@ -1793,7 +1813,14 @@ static int dsmc_graph_launch_impl(dsmc_ctx *x, void *stream)
     if (x->g_sample_every > 0 && x->step % x->g_sample_every != 0)
         return fail(DSMC_ESTATE, "the current step is not aligned with the graph's sampling period");
     if (x->step + x->g_nsteps > (int64_t)0xFFFFFFFF) return fail(DSMC_ESTATE, "step counter beyond 2^32");
+    if (!x->g_moved && x->classified)
+        return fail(DSMC_ESTATE, "the state is moved (dsmc_step_moved) and the graph starts from a settled one");
     hipStream_t s = S(stream);
+    if (x->g_moved && !x->classified) {
+        TRY(step_run(x, 0, 0, true, stream));  // the moving pass first (completes a pending reseed)
+        if (x->cur != x->g_cur)
+            return fail(DSMC_ESTATE, "the moved state is on the other buffer than the graph was captured with");
+    }
     TRY(settle(x, s));
     x->last = s;
     k_set_step_base<<<1, 64, 0, s>>>(x->ctr, (uint32_t)x->step);
@@ -1826,6 +1853,12 @@ int dsmc_step(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
 {
     t_reason = nullptr;
     return noted(x, "dsmc_step", dsmc_step_impl(x, nsteps, sample_every, stream));
+}
+
+int dsmc_step_moved(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_step_moved", dsmc_step_moved_impl(x, nsteps, sample_every, stream));
 }
 
 int dsmc_sample_moments(dsmc_ctx *x, double *out, int32_t reset, void *stream)
@@ -1880,7 +1913,13 @@ int dsmc_profile_read(dsmc_ctx *x, int32_t kernel, double *ms_total, int64_t *la
 int dsmc_graph_create(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
 {
     t_reason = nullptr;
-    return noted(x, "dsmc_graph_create", dsmc_graph_create_impl(x, nsteps, sample_every, stream));
+    return noted(x, "dsmc_graph_create", graph_create(x, nsteps, sample_every, false, stream));
+}
+
+int dsmc_graph_create_moved(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, void *stream)
+{
+    t_reason = nullptr;
+    return noted(x, "dsmc_graph_create_moved", graph_create(x, nsteps, sample_every, true, stream));
 }
 
 int dsmc_graph_launch(dsmc_ctx *x, void *stream)

@@ -87,8 +87,16 @@ class Channel:
             pass
 
     # ---- the hot path -------------------------------------------------------------
-    def step(self, nsteps: int = 1, sample_every: int = 0, stream=None):
-        check(lib().dsmc_step(self._h, int(nsteps), int(sample_every), _stream(stream)), "dsmc_step", self._h)
+    def step(self, nsteps: int = 1, sample_every: int = 0, stream=None, moved: bool = False):
+        """nsteps steps (sampling when (step + 1) % sample_every == 0).  With
+        moved=True the state is left moved for the coming step, so the next
+        call starts without re-moving it; particles() then refuses until a
+        plain step() call (nsteps >= 1) settles it again."""
+        if moved:
+            check(lib().dsmc_step_moved(self._h, int(nsteps), int(sample_every), _stream(stream)), "dsmc_step_moved",
+                  self._h)
+        else:
+            check(lib().dsmc_step(self._h, int(nsteps), int(sample_every), _stream(stream)), "dsmc_step", self._h)
 
     def sample_moments(self, reset: bool = False, stream=None) -> torch.Tensor:
         out = torch.empty((NMOM, self.ncells), dtype=torch.float64, device=self.device)
@@ -131,6 +139,8 @@ class Channel:
         return self.workspace[off:off + n * itemsize].view(dtype)
 
     def cell_start(self) -> torch.Tensor:
+        if self.status()["moved"]:
+            raise RuntimeError("the state is moved for the coming step (step(moved=True)); step() settles it")
         return self._ws_view(self.views().cell_start, self.ncells + 1, torch.int32)
 
     def cell_state(self):
@@ -143,11 +153,14 @@ class Channel:
         check(lib().dsmc_read_status(self._h, ctypes.byref(s), int(clear), _stream(stream)), "dsmc_read_status",
               self._h)
         return {"bits": int(s.bits), "n": int(s.n_particles), "ncoll": int(s.ncoll), "ncand": int(s.ncand),
-                "nwall": int(s.nwall), "nfar": int(s.nfar)}
+                "nwall": int(s.nwall), "nfar": int(s.nfar), "moved": bool(s.moved)}
 
     def particles(self):
         """(x, y, vx, vy, vz) device views of the current, cell-sorted state."""
-        n = self.status()["n"]
+        st = self.status()
+        if st["moved"]:
+            raise RuntimeError("the state is moved for the coming step (step(moved=True)); step() settles it")
+        n = st["n"]
         cur = self.views().current
         return tuple(self.state[cur, k, :n] for k in range(5))
 
@@ -177,11 +190,14 @@ class Channel:
                                       _ptr(avg_out) if avg_out is not None else None, _stream(stream)),
               "dsmc_hybrid_cycle", self._h)
 
-    def graph_create(self, nsteps: int, sample_every: int = 0, stream=None):
-        """Capture one step(nsteps, sample_every) call into a HIP graph on
-        `stream` (a torch.cuda.Stream; capture cannot use the null stream)."""
-        check(lib().dsmc_graph_create(self._h, int(nsteps), int(sample_every), _stream(stream)),
-              "dsmc_graph_create", self._h)
+    def graph_create(self, nsteps: int, sample_every: int = 0, stream=None, moved: bool = False):
+        """Capture one step(nsteps, sample_every, moved=moved) call into a HIP
+        graph on `stream` (a torch.cuda.Stream; capture cannot use the null
+        stream).  A moved graph replays from a moved state and leaves it moved
+        (the first replay on a settled state moves it first)."""
+        fn, name = ((lib().dsmc_graph_create_moved, "dsmc_graph_create_moved") if moved else
+                    (lib().dsmc_graph_create, "dsmc_graph_create"))
+        check(fn(self._h, int(nsteps), int(sample_every), _stream(stream)), name, self._h)
 
     def graph_launch(self, stream=None):
         """Replay the captured steps from the current step."""
