@@ -104,7 +104,8 @@ PMC_CMDS = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fe
             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
             "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-precision --no-adjoint --no-batched --no-hybrid --no-c1 --copy-calibration")
 # kernel-name prefixes of the library's kernels, by profiling id
-KERNEL_PREFIX = {"step": "void dsmc::k_step<", "classify": "void dsmc::k_classify<", "project": "void dsmc::k_project<",
+KERNEL_PREFIX = {"step": "void dsmc::k_step<", "classify": "void dsmc::k_classify<", "complete": "void dsmc::k_complete<",
+                 "project": "void dsmc::k_project<",
                  "reseed_gen": "void dsmc::k_reseed_gen<", "lbm": "void dsmc::k_lbm<"}
 # VALU instruction counts of the same cycle (one counter pass): the reseed's
 # FP64 work against the FP64 peak
@@ -308,9 +309,10 @@ def profile_batched():
         r["mach"] = B["mach"]
     b = D.Batch(reps)
     tune = b.autotune(B["tune_steps"], 1)
+    b.step(0, 1, moved=True)  # as the timed replays run: the state moved between calls
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.step(10, 1)
+    b.step(10, 1, moved=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n = b.status()["n"]
@@ -1120,7 +1122,9 @@ def main():
     nparticles = NX * NY * PPC
 
     def cycle():
-        ch.step(STEPS_PER_CYCLE, sample_every=1)
+        # the state stays moved between calls: the strip reseed goes into the
+        # moved state, and no call begins with a pass that moves it again
+        ch.step(STEPS_PER_CYCLE, sample_every=1, moved=True)
         ch.map_to_lbm(37, 3, out=f)
         ch.reset_moments()
         D.lbm_step(f, NX, NY, 37, tau, g_lb, 1, 1, f_tmp=ftmp)

@@ -165,15 +165,19 @@ int dsmc_step(dsmc_ctx *ctx, int32_t nsteps, int32_t sample_every, void *stream)
  * writes them settled (sorted into their cells), so that the next call
  * begins with a pass that moves them again.  Here the last step moves as
  * the others do and the next call (either kind) begins without that pass.
- * Every later result is identical to a run of dsmc_step calls; the wall
- * hits of the coming step's move are counted in this call.  While moved
- * (dsmc_status.moved = 1) the state buffers do not hold cell-sorted
- * particles, map_lbm_to_dsmc and dsmc_graph_launch of a dsmc_graph_create
- * graph return DSMC_ESTATE, and a dsmc_step call with nsteps >= 1 settles
- * the state again.  Moments, the mapping to the lattice and the status are
- * available as usual.  nsteps = 0 runs only the moving pass (none on a
- * moved state).  For loops that step and sample without reading particles
- * between calls.  Errors: DSMC_EINVAL. */
+ * Every later result is identical to a run of dsmc_step calls, also with
+ * a map_lbm_to_dsmc between calls (see there); the wall hits of the coming
+ * step's move are counted in this call or in the next one.  In a one-channel
+ * context the last step leaves the tiles that hold a particle bound for a
+ * wall unmoved (a reseed before the next step changes the cell starts that
+ * key its wall draws); the next call (or graph replay) moves them first, in
+ * a pass over those cells only.  While moved (dsmc_status.moved = 1) the
+ * state buffers do not hold cell-sorted particles, dsmc_graph_launch of a
+ * dsmc_graph_create graph returns DSMC_ESTATE, and a dsmc_step call with
+ * nsteps >= 1 settles the state again.  Moments, both mappings and the
+ * status are available as usual.  nsteps = 0 runs only the moving pass (none
+ * on a moved state).  For loops that step, sample and map without reading
+ * particles between calls.  Errors: DSMC_EINVAL. */
 int dsmc_step_moved(dsmc_ctx *ctx, int32_t nsteps, int32_t sample_every, void *stream);
 
 /* The cumulative averages of the DSMC moments that DSMC2LB projects
@@ -214,8 +218,14 @@ int dsmc_project_moments(const double *avg, int64_t ncells, int32_t ppc, double 
  * their new slots in the next dsmc_step's first pass over the state (which
  * reads every particle anyway), or, if another call that reads the state
  * comes first (dsmc_get_views, dsmc_read_status, map_lbm_to_dsmc, the graph
- * calls), in a copy that call enqueues.  cell_ids is not read after the call's
- * work has run.  Errors: DSMC_EINVAL. */
+ * calls), in a copy that call enqueues.  On a moved state (dsmc_step_moved)
+ * the new particles are written after the state's last slot, and the next
+ * step's pass over the listed cells and the unmoved tiles moves them; the
+ * results equal those of the same reseed of the settled state, except that
+ * the buffer must also hold the replaced particles until that step (a
+ * reseed that does not fit is skipped with DSMC_ST_CAPACITY), and a second
+ * reseed of the same moved state returns DSMC_ESTATE.  cell_ids is not read
+ * after the call's work has run.  Errors: DSMC_EINVAL, DSMC_ESTATE. */
 int map_lbm_to_dsmc(dsmc_ctx *ctx, int32_t lattice, int32_t order, const double *f_in, const int32_t *cell_ids,
                     int32_t nsel, void *stream);
 

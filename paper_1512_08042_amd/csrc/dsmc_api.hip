@@ -219,7 +219,7 @@ int far_cap_of(const dsmc_config &c)
 
 struct Layout {
     size_t cs0, cs1, grp0, grp1, plan, countnew, farcnt, blocksum, far0, far1, nbar, sigcmax, rem, mom, mark, prm, nnew,
-        perm, tstat, kc, ctr, rep, tiles, cell_rep, rstat, total;
+        perm, tstat, kc, ctr, rep, tiles, cell_rep, rstat, comp, complist, appoff, total;
 };
 
 // nc: cells of all channels together; nrep: channels
@@ -259,6 +259,9 @@ Layout make_layout(const dsmc_config &c, size_t nc, size_t nrep)
     L.tiles = take(2 * TILE_WORDS * nc * 4);  // at most one tile per cell, in two orders (see set_tiling)
     L.cell_rep = take(nc * 4);
     L.rstat = take(3 * nrep * 8);
+    L.comp = take(nc * 4);      // completion of a moved state: reasons per cell,
+    L.complist = take(nc * 4);  // the listed cells,
+    L.appoff = take(nc * 4);    // a moved reseed's appended particles per list entry
     L.total = o;
     return L;
 }
@@ -329,6 +332,7 @@ struct dsmc_ctx {
     void *st[2][5];  // double, or float when state32
     int32_t *cs[2];
     int32_t *grp[2], *plan, *countnew, *farcnt, *blocksum, *far[2], *mark, *nnew, *perm;
+    int32_t *comp, *complist, *appoff;
     double *nbar, *sigcmax, *rem, *mom, *prm;
     Counters *ctr;
     unsigned long long *tstat;
@@ -380,6 +384,11 @@ struct dsmc_ctx {
     // classify pass completes it (it reads every particle anyway); any other
     // call that reads particles or cell starts settles it first with a copy.
     bool pending;
+    // A moved state of one channel may have cells left for the completion
+    // pass (k_complete, run before the next step): tiles that ended unmoved
+    // (STEP_DEFER) and, after a reseed of the moved state (comp_reseed), the
+    // replaced cells, whose new particles sit after the state's last slot.
+    bool comp_pending, comp_reseed;
     // the step kernels read the state with non-temporal loads (a state buffer
     // of the nominal particle count below 384 MB, 1.5 x the memory-side cache)
     bool nt_loads;
@@ -449,6 +458,7 @@ StepArgs step_args(const dsmc_ctx *x, int32_t cur, int64_t step, bool sample, bo
     a.r = 0;
     a.dev_step = x->capturing ? 1 : 0;
     a.reseed = 0;
+    a.flags = 0;
     a.step = (uint32_t)step;
     a.cur = cur;
     a.sample = sample ? 1 : 0;
@@ -477,6 +487,11 @@ int upload_tile_const(dsmc_ctx *x, hipStream_t s)
     k.sigcmax = x->sigcmax;
     k.rem = x->rem;
     k.mark = x->mark;
+    k.comp = x->comp;
+    k.complist = x->complist;
+    k.appoff = x->appoff;
+    k.nnew = x->nnew;
+    k.cap = (int)std::min<int64_t>(x->cfg.capacity, 0x7fffffff);
     k.rep = x->rep;
     k.s_th = x->s_th;
     k.nbar_mode = x->cfg.nbar_mode;
@@ -585,6 +600,7 @@ int set_tiling(dsmc_ctx *x, int ppt, hipStream_t s)
 // streams the second and later groups run beside the first.
 int launch_tiles(const dsmc_ctx *x, int kind, bool move, hipStream_t s, const StepArgs &a0)
 {
+    const bool defer = (a0.flags & STEP_DEFER) != 0 && move;
     const int ng = (int)x->groups.size();
     const bool fork = x->forked && ng > 1 && ng <= 4;
     if (fork && hipEventRecord(x->ev_fork, s) != hipSuccess) return DSMC_EHIP;
@@ -600,18 +616,24 @@ int launch_tiles(const dsmc_ctx *x, int kind, bool move, hipStream_t s, const St
         // row order; the step's gathers read across rows and take the bands
         a.tiles = x->tiles + TILE_WORDS * ((kind == 0 ? (size_t)x->ntiles : 0) + (size_t)g.tile0);
         const unsigned n = (unsigned)g.ntiles;
-#define DSMC_LAUNCH(TC, CH, S)                                   \
-    do {                                                         \
-        if (kind == 0)                                           \
-            k_classify<TC, CH, S><<<n, 64, 0, gs>>>(a);          \
-        else if (x->nt_loads && move)                            \
-            k_step<TC, CH, true, S, true><<<n, 64, 0, gs>>>(a);  \
-        else if (x->nt_loads)                                    \
-            k_step<TC, CH, false, S, true><<<n, 64, 0, gs>>>(a); \
-        else if (move)                                           \
-            k_step<TC, CH, true, S, false><<<n, 64, 0, gs>>>(a); \
-        else                                                     \
-            k_step<TC, CH, false, S, false><<<n, 64, 0, gs>>>(a); \
+#define DSMC_LAUNCH(TC, CH, S)                                          \
+    do {                                                                \
+        if (kind == 0 && defer)                                         \
+            k_classify<TC, CH, S, true><<<n, 64, 0, gs>>>(a);           \
+        else if (kind == 0)                                             \
+            k_classify<TC, CH, S, false><<<n, 64, 0, gs>>>(a);          \
+        else if (defer && x->nt_loads)                                  \
+            k_step<TC, CH, true, S, true, true><<<n, 64, 0, gs>>>(a);   \
+        else if (defer)                                                 \
+            k_step<TC, CH, true, S, false, true><<<n, 64, 0, gs>>>(a);  \
+        else if (x->nt_loads && move)                                   \
+            k_step<TC, CH, true, S, true, false><<<n, 64, 0, gs>>>(a);  \
+        else if (x->nt_loads)                                           \
+            k_step<TC, CH, false, S, true, false><<<n, 64, 0, gs>>>(a); \
+        else if (move)                                                  \
+            k_step<TC, CH, true, S, false, false><<<n, 64, 0, gs>>>(a); \
+        else                                                            \
+            k_step<TC, CH, false, S, false, false><<<n, 64, 0, gs>>>(a); \
     } while (0)
         if (state32(x->cfg)) {
             if (g.tc == 4 && g.ch == 8)
@@ -935,6 +957,9 @@ int init_ctx(const dsmc_config *cfg, const dsmc_replica *reps, int32_t nrep, con
     x->tiles = (int32_t *)(w + L.tiles);
     x->cell_rep = (int32_t *)(w + L.cell_rep);
     x->rstat = (unsigned long long *)(w + L.rstat);
+    x->comp = (int32_t *)(w + L.comp);
+    x->complist = (int32_t *)(w + L.complist);
+    x->appoff = (int32_t *)(w + L.appoff);
     x->ncells = (int)ncells;
     x->nblk = (int)((ncells + 255) / 256);
     x->far_cap = far_cap_of(*cfg);
@@ -973,6 +998,8 @@ int init_ctx(const dsmc_config *cfg, const dsmc_replica *reps, int32_t nrep, con
     x->reseed_events = 0;
     x->classified = false;
     x->pending = false;
+    x->comp_pending = false;
+    x->comp_reseed = false;
     {
         const int64_t nominal = mode == 1 ? n_load : npart;
         const int64_t bytes = nominal * 5 * (cfg->state_bits == 32 ? 4 : 8);
@@ -1000,6 +1027,7 @@ int init_ctx(const dsmc_config *cfg, const dsmc_replica *reps, int32_t nrep, con
     if (rc == DSMC_OK) rc = fill_f64(x->mom, (size_t)NMOM * ncells, 0.0, s);
     if (rc == DSMC_OK) rc = fill_i32(x->farcnt, 2 * (size_t)ncells, 0, s);
     if (rc == DSMC_OK) rc = fill_i32(x->mark, (size_t)ncells, 0, s);
+    if (rc == DSMC_OK) rc = fill_i32(x->comp, (size_t)ncells, 0, s);
     if (rc == DSMC_OK) rc = fill_i32((int32_t *)x->tstat, 6 * (size_t)ncells, 0, s);
     if (rc == DSMC_OK) rc = upload_tile_const(x, s);
     if (rc == DSMC_OK && mode == 0) {
@@ -1276,8 +1304,46 @@ int adjoint_step_on(const lbm_config *cfg, const double *f_n, const double *lam_
 
 extern "C" {
 
+// The completion pass of a moved state (see STEP_COMPLETE): after a moved
+// reseed the replaced cells' recorded long jumps are dropped first, then
+// every listed cell is moved as a one-cell classify tile.
+static int complete(dsmc_ctx *x, hipStream_t s)
+{
+    if (!x->comp_pending) return DSMC_OK;
+    StepArgs a = step_args(x, x->cur, x->step, false, true);
+    a.flags = STEP_COMPLETE | (x->comp_reseed ? STEP_COMP_RESEED : 0);
+    const bool f32 = state32(x->cfg);
+    int tc = 1, ch = 8;
+    tile_shape(f32, x->cfg.ppc, 1, tc, ch);
+    const unsigned far_blocks = (unsigned)((std::max<size_t>((size_t)x->far_cap, (size_t)x->ncells) + 255) / 256);
+    const unsigned grid = (unsigned)std::min(x->ncells, 4096);
+    TRY(launch(x, DSMC_K_CLASSIFY, s, [&] {
+        if (x->comp_reseed) {
+            for (int pass = 0; pass < 2; ++pass) {
+                if (f32)
+                    k_comp_far<float><<<far_blocks, 256, 0, s>>>(a, pass);
+                else
+                    k_comp_far<double><<<far_blocks, 256, 0, s>>>(a, pass);
+            }
+        }
+        if (f32)
+            k_complete<8, float><<<grid, 64, 0, s>>>(a);
+        else if (ch == 4)
+            k_complete<4, double><<<grid, 64, 0, s>>>(a);
+        else
+            k_complete<8, double><<<grid, 64, 0, s>>>(a);
+        if (x->comp_reseed) k_comp_done<<<1, 64, 0, s>>>(x->ctr, 1);
+    }));
+    if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
+    x->comp_pending = false;
+    x->comp_reseed = false;
+    return DSMC_OK;
+}
+
 // nsteps steps; the state ends settled, or with moved_end moved for the
-// coming step (the call's last step moves and partitions as the others do)
+// coming step (the call's last step moves and partitions as the others do;
+// in a one-channel context it leaves tiles with particles bound for a wall
+// unmoved, for a reseed that may come first: see STEP_DEFER)
 static int step_run(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, bool moved_end, void *stream)
 {
     if (!x) return DSMC_EINVAL;
@@ -1286,14 +1352,18 @@ static int step_run(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, bool move
     x->last = s;
     const int nc = x->ncells;
     int rc_tiles = DSMC_OK;
+    const bool defer = moved_end && x->nrep == 1;
+    if (x->classified && nsteps > 0) TRY(complete(x, s));
     if ((nsteps > 0 || moved_end) && !x->classified) {
         // moves of the coming step for a state set or changed from outside
         const int p = (int)(x->step & 1);
         TRY(fill_i32(x->farcnt, 2 * (size_t)nc, 0, s));
         k_far_reset<<<1, 64, 0, s>>>(x->ctr, p);
+        const int fl = (defer && nsteps == 0) ? STEP_DEFER : 0;  // the call's moved state comes from this pass
         if (x->pending) {  // the classify pass completes the reseed into the other buffer
             StepArgs a = step_args(x, 1 - x->cur, x->step, false, true);
             a.reseed = 1;
+            a.flags = fl;
             TRY(launch(x, DSMC_K_CLASSIFY, s, [&] {
                 rc_tiles = launch_tiles(x, 0, true, s, a);
                 k_reseed_done<<<1, 64, 0, s>>>(x->ctr);
@@ -1301,11 +1371,13 @@ static int step_run(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, bool move
             x->cur = 1 - x->cur;
             x->pending = false;
         } else {
-            const StepArgs a = step_args(x, x->cur, x->step, false, true);
+            StepArgs a = step_args(x, x->cur, x->step, false, true);
+            a.flags = fl;
             TRY(launch(x, DSMC_K_CLASSIFY, s, [&] { rc_tiles = launch_tiles(x, 0, true, s, a); }));
         }
         TRY(rc_tiles);
         x->classified = true;
+        if (fl) x->comp_pending = true;
     }
     for (int32_t it = 0; it < nsteps; ++it) {
         const int cur = x->cur, nxt = 1 - cur;
@@ -1328,14 +1400,18 @@ static int step_run(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, bool move
 
         const bool sample = sample_every > 0 && ((x->step + 1) % sample_every) == 0;
         const bool move = moved_end || it + 1 < nsteps;  // a dsmc_step call's last step leaves the state settled
-        const StepArgs a = step_args(x, cur, x->step, sample, false);
+        StepArgs a = step_args(x, cur, x->step, sample, false);
+        if (defer && it + 1 == nsteps) a.flags = STEP_DEFER;
         TRY(launch(x, DSMC_K_STEP, s, [&] { rc_tiles = launch_tiles(x, 1, move, s, a); }));
         TRY(rc_tiles);
         x->cur = nxt;
         if (sample) x->nsamples += 1;
         x->step += 1;
     }
-    if (nsteps > 0) x->classified = moved_end;
+    if (nsteps > 0) {
+        x->classified = moved_end;
+        x->comp_pending = defer;
+    }
     return DSMC_OK;
 }
 
@@ -1470,12 +1546,15 @@ static int map_lbm_to_dsmc_impl(dsmc_ctx *x, int32_t lattice, int32_t order, con
     if (!L || (order != 2 && order != 3) || !f_in || nsel < 0 || (nsel > 0 && !cell_ids))
         return fail(DSMC_EINVAL, "lattice must be 9 or 37, order 2 or 3, f_in non-NULL, nsel >= 0 with cell_ids");
     if (nsel > x->ncells) return fail(DSMC_EINVAL, "nsel exceeds the number of cells");
-    if (x->classified)
-        return fail(DSMC_ESTATE, "the state is moved (dsmc_step_moved): a reseed needs the settled state that a "
-                                 "dsmc_step call leaves");
+    // a moved state (dsmc_step_moved): the new particles go after its last
+    // slot and the replaced cells are completed with the rest before the
+    // next step (see STEP_COMPLETE); one reseed per moved state
+    const bool moved = x->classified;
+    if (moved && x->comp_reseed)
+        return fail(DSMC_ESTATE, "the moved state was reseeded already: step before the next reseed");
     hipStream_t s = S(stream);
     x->last = s;
-    TRY(settle(x, s));
+    if (!moved) TRY(settle(x, s));
     const uint32_t event = (uint32_t)x->reseed_events;
     x->reseed_events += 1;
     const int cur = x->cur, nxt = 1 - cur;
@@ -1492,8 +1571,12 @@ static int map_lbm_to_dsmc_impl(dsmc_ctx *x, int32_t lattice, int32_t order, con
     a.blocksum = x->blocksum;
     for (int k = 0; k < 5; ++k) {
         a.in[k] = x->st[cur][k];
-        a.out[k] = x->st[nxt][k];
+        a.out[k] = x->st[moved ? cur : nxt][k];
     }
+    a.moved = moved ? 1 : 0;
+    a.appoff = x->appoff;
+    a.comp = x->comp;
+    a.complist = x->complist;
     a.ctr = x->ctr;
     a.L = *L;
     a.nx = x->cfg.nx;
@@ -1511,8 +1594,13 @@ static int map_lbm_to_dsmc_impl(dsmc_ctx *x, int32_t lattice, int32_t order, con
         if (nsel > 0) k_reseed_prep<<<gsel, 256, 0, s>>>(a);
         k_reseed_count<<<x->nblk, 256, 0, s>>>(a);
         k_reseed_starts<<<x->nblk, 256, 0, s>>>(a);
-        // the new particles go to buffer nxt; the kept ones follow when the
-        // state settles (the next step's classify pass, or settle())
+        if (moved) {
+            k_reseed_appoff<<<1, 1024, 0, s>>>(a);
+            k_reseed_list<<<gsel, 256, 0, s>>>(a);
+        }
+        // settled state: the new particles go to buffer nxt; the kept ones
+        // follow when the state settles (the next step's classify pass, or
+        // settle()).  moved state: they go after its last slot
         if (nsel > 0) {
             if (state32(x->cfg))
                 k_reseed_gen<float><<<grid_cells_wave(nsel), 256, 0, s>>>(a);
@@ -1520,8 +1608,13 @@ static int map_lbm_to_dsmc_impl(dsmc_ctx *x, int32_t lattice, int32_t order, con
                 k_reseed_gen<double><<<grid_cells_wave(nsel), 256, 0, s>>>(a);
         }
     }));
-    x->pending = true;
-    x->classified = false;
+    if (moved) {
+        x->comp_pending = true;
+        x->comp_reseed = true;
+    } else {
+        x->pending = true;
+        x->classified = false;
+    }
     return DSMC_OK;
 }
 
@@ -1681,13 +1774,17 @@ static int dsmc_read_status_impl(dsmc_ctx *x, dsmc_status *out, int32_t clear, v
     hipStream_t s = S(stream);
     TRY(settle(x, s));
     Counters h;
-    int32_t n = 0;
+    int32_t n = 0, n_re = 0;
     k_tile_stats<<<1, 1024, 0, s>>>(x->tstat, x->ncells, x->ctr);
     if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
     if (hipMemcpyAsync(&h, x->ctr, sizeof(Counters), hipMemcpyDeviceToHost, s) != hipSuccess) return DSMC_EHIP;
     if (hipMemcpyAsync(&n, x->cs[x->cur] + x->ncells, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
         return DSMC_EHIP;
+    if (x->comp_reseed &&  // a moved reseed not yet completed: its count, if it goes ahead
+        hipMemcpyAsync(&n_re, x->cs[1 - x->cur] + x->ncells, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return DSMC_EHIP;
     if (hipStreamSynchronize(s) != hipSuccess) return DSMC_EHIP;
+    if (x->comp_reseed && h.reseed_err == 0u) n = n_re;
     out->bits = h.status;
     out->moved = x->classified ? 1u : 0u;
     out->n_particles = n;
@@ -1769,11 +1866,12 @@ static int graph_create(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, bool 
     // state; one of dsmc_step_moved calls starts from, and ends in, a moved one)
     const int64_t step = x->step, nsamples = x->nsamples;
     const int cur = x->cur;
-    const bool prof = x->prof, classified = x->classified;
+    const bool prof = x->prof, classified = x->classified, comp_pending = x->comp_pending;
     x->step = 0;
     x->prof = false;
     x->capturing = true;
     x->classified = moved;
+    x->comp_pending = false;  // (a pending completion runs eagerly before a replay)
     int rc = DSMC_OK;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = DSMC_EHIP;
     const int rc_step = rc == DSMC_OK ? step_run(x, nsteps, sample_every, moved, stream) : DSMC_OK;
@@ -1787,6 +1885,7 @@ static int graph_create(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, bool 
     x->cur = cur;
     x->prof = prof;
     x->classified = classified;
+    x->comp_pending = comp_pending;
     if (rc != DSMC_OK) {
         if (g) (void)hipGraphDestroy(g);
         x->gexec = nullptr;
@@ -1821,11 +1920,13 @@ static int dsmc_graph_launch_impl(dsmc_ctx *x, void *stream)
         if (x->cur != x->g_cur)
             return fail(DSMC_ESTATE, "the moved state is on the other buffer than the graph was captured with");
     }
+    if (x->g_moved) TRY(complete(x, s));  // cells left unmoved, or a moved reseed
     TRY(settle(x, s));
     x->last = s;
     k_set_step_base<<<1, 64, 0, s>>>(x->ctr, (uint32_t)x->step);
     if (hipGetLastError() != hipSuccess) return DSMC_EHIP;
     if (hipGraphLaunch(x->gexec, s) != hipSuccess) return DSMC_EHIP;
+    if (x->g_moved) x->comp_pending = x->nrep == 1;  // its last step left wall tiles unmoved
     x->step += x->g_nsteps;
     if (x->g_sample_every > 0) x->nsamples += x->g_nsteps / x->g_sample_every;
     return DSMC_OK;

@@ -44,7 +44,7 @@ struct Counters {
     unsigned long long ncoll, ncand, nwall, nfar_total;
     unsigned long long reseed_new, reseed_removed;  // particle totals of the reseed in progress
     uint32_t step_base;   // first step of a replayed step graph (added to the steps it was captured with)
-    uint32_t pad;
+    uint32_t ncomp;       // cells listed for the completion pass of a moved state (see k_complete)
 };
 
 struct U4 {

@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256, 4) void k_reseed_gen(ReseedArgs a)
     if (a.ctr->reseed_err != 0u) return;
     const int c = a.cells[i];
     const int nn = a.nnew[i];
-    const int d0 = a.cs_new[c];
+    const int d0 = a.moved ? a.cs_old[a.ncells] + a.appoff[i] : a.cs_new[c];
     if (lane < 12) s_prm[w][lane] = a.prm[(size_t)i * 12 + lane];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -420,6 +420,68 @@ __global__ __launch_bounds__(256, 4) void k_reseed_gen(ReseedArgs a)
 
 template __global__ void k_reseed_gen<double>(ReseedArgs);
 template __global__ void k_reseed_gen<float>(ReseedArgs);
+
+// A reseed of a moved state: the first slot of every list entry's new
+// particles after the state's last slot (an exclusive scan of the counts in
+// list order, one workgroup: each thread sums a run of entries, the runs'
+// sums are scanned across the waves), and whether they fit the buffer
+// there: the replaced particles keep their slots until the next step, so
+// this needs room for both (a reseed that does not fit is skipped, as one
+// above capacity is).
+__global__ __launch_bounds__(1024) void k_reseed_appoff(ReseedArgs a)
+{
+    __shared__ long long wsum[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int per = (a.nsel + 1023) / 1024;
+    const int i0 = min(t * per, a.nsel), i1 = min(i0 + per, a.nsel);
+    long long part = 0;
+    for (int i = i0; i < i1; ++i) part += a.nnew[i];
+    long long inc = part;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long v = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += v;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    long long before = 0;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    long long run = before + inc - part;
+    for (int i = i0; i < i1; ++i) {
+        a.appoff[i] = (int)min(run, (long long)0x7fffffff);
+        run += a.nnew[i];
+    }
+    if (t == 1023 && (long long)a.cs_old[a.ncells] + before + inc > a.capacity) {
+        a.ctr->reseed_err |= ST_CAPACITY;
+        a.ctr->status |= ST_CAPACITY;
+    }
+}
+
+// ... and the listing: a reseed that goes ahead lists every replaced cell
+// not listed already (one add per wave on the list length); one that is
+// skipped clears the marks, since no completion will read them
+__global__ __launch_bounds__(256) void k_reseed_list(ReseedArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const bool ok = a.ctr->reseed_err == 0u;
+    bool add = false;
+    int c = -1;
+    if (i < a.nsel) {
+        c = a.cells[i];
+        if (c >= 0 && c < a.ncells) {
+            if (ok)
+                add = (atomicOr(&a.comp[c], 2) == 0);
+            else
+                a.mark[c] = 0;
+        }
+    }
+    const uint64_t m = ballot64(add);
+    const int lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    if (m != 0 && lane == 0) base = atomicAdd(&a.ctr->ncomp, (uint32_t)__popcll(m));
+    base = __shfl(base, 0, 64);
+    if (add) a.complist[base + rank_below(m)] = c;
+}
 
 // the end of a reseed (its cells' marks were cleared as the state settled)
 __global__ void k_reseed_done(Counters *ctr)

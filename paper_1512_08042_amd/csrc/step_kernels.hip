@@ -121,6 +121,7 @@ struct TileLds : CellStash<TC> {
     int32_t csn[TC + 1];           // cell starts of the tile after the sort
     int32_t tix[TC], tiy[TC];      // cell coordinates
     int32_t anyfar;                // long jumps arrive in some cell of the tile
+    int32_t kdelta;                // wall-draw keys: slot + kdelta (a completed cell's starts after a reseed)
     // the 9 near groups arriving in each cell, in the order of the sort (by
     // source cell; groups without a source last, empty); the keys and sizes
     // only where long jumps arrive
@@ -588,8 +589,10 @@ __device__ void move_chunk_walls(const StepArgs &a, const TileLds<TC, CH, S> &L,
     if (i < nt && kr[i] == KEY_WALL) {
         const int t = tile_cell<TC, CH, S>(L, ntc, L.csn[0], i);
         double x = px, y = py, vx = s[2][i], vy = s[3][i], vz = s[4][i];
-        // wall draws are keyed by the slot inside the channel
-        walls += move_particle(a.geo(), a.M1(), (uint32_t)(L.csn[0] + i - a.R().pbase), x, y, vx, vy, vz, limit);
+        // wall draws are keyed by the slot inside the channel (of the settled
+        // state the move starts from: see STEP_COMPLETE for L.kdelta)
+        walls += move_particle(a.geo(), a.M1(), (uint32_t)(L.csn[0] + L.kdelta + i - a.R().pbase), x, y, vx, vy, vz,
+                               limit);
         const S xs = (S)x, ys = (S)y;
         px = xs;
         py = ys;
@@ -666,7 +669,7 @@ __device__ __forceinline__ void tile_group_offsets(const StepArgs &a, TileLds<TC
 //     and partitioned in place.
 // STAGED tiles (at most 64*CH particles) are staged in LDS; larger ones run
 // the same steps on the tile's destination range in global memory.
-template <int TC, int CH, class S, bool GATHER, bool MOVE, bool STAGED, bool NT>
+template <int TC, int CH, class S, bool GATHER, bool MOVE, bool STAGED, bool NT, bool DEFER>
 __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int ntc, int nt, int n_old, bool own_ntc,
                           double &nbar, double &sig, double &rem, bool mown, double mprev, double *mdst,
                           unsigned long long &ncoll, unsigned long long &ncand, int &walls, bool &limit)
@@ -829,6 +832,52 @@ __device__ void tile_body(const StepArgs &a, TileLds<TC, CH, S> &L, int c0, int 
         return;  // unstaged: already in place, in sorted order
     }
 
+    // STEP_DEFER: a tile with a particle that may reach a wall in the coming
+    // move ends settled, in place, and its cells are listed for k_complete
+    // (the test is the move's own wall test with a margin: deferring a tile
+    // that needs no wall draw changes nothing)
+    if constexpr (DEFER) {
+        const double dt = a.R().dt, H = a.R().G.H, tol = 1e-9 * H;
+        bool w = false;
+        if (STAGED) {
+#pragma unroll
+            for (int b = 0; b < CH; ++b) {
+                const int i = 64 * b + lane;
+                if (i < nt) {
+                    const double yn = (double)yr[b] + (double)L.v[1][i] * dt;
+                    w |= !(yn > tol && yn < H - tol);
+                }
+            }
+        } else {
+            for (int i = lane; i < nt; i += 64) {
+                const double yn = (double)s[1][i] + (double)s[3][i] * dt;
+                w |= !(yn > tol && yn < H - tol);
+            }
+        }
+        if (ballot64(w) != 0) {
+            if (STAGED) {
+#pragma unroll
+                for (int b = 0; b < CH; ++b) {
+                    const int i = 64 * b + lane;
+                    if (i < nt) {
+                        a.template out<S>(0)[D0 + i] = xr[b];
+                        a.template out<S>(1)[D0 + i] = yr[b];
+#pragma unroll
+                        for (int k = 2; k < 5; ++k) a.template out<S>(k)[D0 + i] = L.v[k - 2][i];
+                    }
+                }
+            }  // unstaged: already in place, in sorted order
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&a.K().ctr->ncomp, (uint32_t)ntc);
+            base = __shfl(base, 0, 64);
+            if (lane < ntc) {
+                a.K().complist[base + lane] = c0 + lane;
+                a.K().comp[c0 + lane] = 1;
+            }
+            return;
+        }
+    }
+
     // 4. move for the next step (walls in a second pass), grouped by (cell,
     // direction) in slot order
     bool anywall = false;
@@ -924,8 +973,9 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 }
 
 // NT: the gather reads the state with non-temporal loads (see k_step)
-template <int TC, int CH, class S, bool GATHER, bool MOVE, bool NT>
-__device__ __forceinline__ void tile_kernel(const StepArgs &a0)
+// cc: the cell of a STEP_COMPLETE pass (TC 1), else -1 (tiles from the table)
+template <int TC, int CH, class S, bool GATHER, bool MOVE, bool NT, bool DEFER = false>
+__device__ __forceinline__ void tile_kernel(const StepArgs &a0, int cc = -1)
 {
     static_assert(TC == 1 || TC == 2 || TC == 4, "tile sizes with teams of >= 16 lanes");
     static_assert(TC * NGRP <= 64 && NTC_ROUND <= 64, "");
@@ -941,13 +991,22 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     // still in that cache.  (Graph replays start at even steps: the parity of
     // the launch's step is the parity of the step.)
     StepArgs a = a0;
-    const int tx = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    const int tile = (a0.step & 1u) ? (int)gridDim.x - 1 - tx : tx;
-    const __attribute__((address_space(4))) int32_t *td =
-        (const __attribute__((address_space(4))) int32_t *)a0.tiles + TILE_WORDS * (size_t)tile;
-    const int c0 = td[0];
-    a.r = td[1];
-    const int iy0 = td[2], ix0 = td[3];
+    int c0, iy0, ix0;
+    if (cc >= 0) {  // one channel: its first replica entry
+        c0 = cc;
+        a.r = 0;
+        iy0 = cc / a.R().G.nx;
+        ix0 = cc - iy0 * a.R().G.nx;
+    } else {
+        const int tx = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+        const int tile = (a0.step & 1u) ? (int)gridDim.x - 1 - tx : tx;
+        const __attribute__((address_space(4))) int32_t *td =
+            (const __attribute__((address_space(4))) int32_t *)a0.tiles + TILE_WORDS * (size_t)tile;
+        c0 = td[0];
+        a.r = td[1];
+        iy0 = td[2];
+        ix0 = td[3];
+    }
     // a step graph is captured with steps counted from 0 and replayed from
     // the step the host sets (an even one, so every parity is unchanged)
     if (a0.dev_step) a.step += ((const __attribute__((address_space(4))) Counters *)a.K().ctr)->step_base;
@@ -967,7 +1026,31 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     // waits on leave as early as possible.
     __builtin_amdgcn_s_setprio(2);
     // set-up: every per-cell quantity of the tile is loaded in one round
-    if (lane <= TC) L.csn[lane] = (rerr ? cs_old : a.cs_new())[min(c0 + lane, ce)];
+    if (cc >= 0) {
+        // the listed cell's settled particles: its slots in the moved state,
+        // or, when a moved reseed that went ahead replaced it, its new
+        // particles after the state's last slot; wall draws keyed by its
+        // start after that reseed
+        if (lane == 0) {
+            const bool acc = (a0.flags & STEP_COMP_RESEED) &&
+                             ((const __attribute__((address_space(4))) Counters *)a.K().ctr)->reseed_err == 0u;
+            const int32_t *cs = a.K().cs[a.cur];
+            const int mk = acc ? a.K().mark[cc] : 0;
+            int src = cs[cc], n = cs[cc + 1] - cs[cc];
+            if (mk > 0) {
+                src = cs[nc] + a.K().appoff[mk - 1];
+                n = a.K().nnew[mk - 1];
+            }
+            L.csn[0] = src;
+            L.csn[1] = src + n;
+            L.kdelta = (acc ? a.K().cs[1 - a.cur][cc] : cs[cc]) - src;
+            a.K().mark[cc] = 0;
+            a.K().comp[cc] = 0;
+        }
+    } else {
+        if (lane <= TC) L.csn[lane] = (rerr ? cs_old : a.cs_new())[min(c0 + lane, ce)];
+        if (lane == 0) L.kdelta = 0;
+    }
     if (lane < TC * NGRP) L.run[lane] = 0;  // the next step's group sizes, counted by the rank
     if (rs && lane < TC) {
         const int c = min(c0 + lane, ce - 1);
@@ -1016,7 +1099,7 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
             mprev = *mdst;
     }
     double *const mdst_held = TC == 4 ? nullptr : mdst;
-    const int n_old = GATHER ? a.cs_old()[nc] : 0;
+    const int n_old = GATHER ? a.K().cap : 0;  // source slots are checked against the buffer
     if (GATHER) {  // the tile's cells' plans (see tile_groups), in the same round of loads
 #pragma unroll
         for (int e = lane; e < TC * 2 * NDIR; e += 64) {
@@ -1037,11 +1120,11 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
     int walls = 0;
     bool limit = false;
     if (nt <= TileLds<TC, CH, S>::CAP)
-        tile_body<TC, CH, S, GATHER, MOVE, true, NT>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev, mdst_held,
-                                              ncoll, ncand, walls, limit);
+        tile_body<TC, CH, S, GATHER, MOVE, true, NT, DEFER>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown,
+                                                            mprev, mdst_held, ncoll, ncand, walls, limit);
     else
-        tile_body<TC, CH, S, GATHER, MOVE, false, NT>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown, mprev,
-                                               mdst_held, ncoll, ncand, walls, limit);
+        tile_body<TC, CH, S, GATHER, MOVE, false, NT, DEFER>(a, L, c0, ntc, nt, n_old, own_ntc, nbar, sig, rem, mown,
+                                                             mprev, mdst_held, ncoll, ncand, walls, limit);
 
     // the tile's running counters.  Collisions and candidates were counted by
     // the lanes that ran the cells' collisions (lanes below TC); wall hits on
@@ -1066,10 +1149,11 @@ __device__ __forceinline__ void tile_kernel(const StepArgs &a0)
 // path.  FP64 tiles stay at four: at five their positions spill around the
 // rank and the write-out (measured 367 against 425 us on a 512 x 256 x 100
 // channel).
-template <int TC, int CH, class S>
+// DEFER: the moving pass that leaves a call's state moved (see STEP_DEFER)
+template <int TC, int CH, class S, bool DEFER>
 __global__ __launch_bounds__(64, (CH == 4 && sizeof(S) == 4) ? 5 : 4) void k_classify(StepArgs a)
 {
-    tile_kernel<TC, CH, S, false, true, true>(a);  // whole cells, read once: non-temporal
+    tile_kernel<TC, CH, S, false, true, true, DEFER>(a);  // whole cells, read once: non-temporal
 }
 
 // four waves per SIMD: the tile fits 128 VGPRs (a few spills in the cold
@@ -1082,18 +1166,106 @@ __global__ __launch_bounds__(64, (CH == 4 && sizeof(S) == 4) ? 5 : 4) void k_cla
 // the written state there for the next step (measured: +4 % at 0.3 GB); at
 // twice its size and more, the L2 reuse of the lines that neighbouring tiles
 // share matters more and plain loads win (-1.5 % with NT at 0.5 GB).
-template <int TC, int CH, bool MOVE, class S, bool NT>
+// DEFER (with MOVE): the last step of a call that leaves the state moved
+template <int TC, int CH, bool MOVE, class S, bool NT, bool DEFER>
 __global__ __launch_bounds__(64, 4) void k_step(StepArgs a)
 {
-    tile_kernel<TC, CH, S, true, MOVE, NT>(a);
+    tile_kernel<TC, CH, S, true, MOVE, NT, DEFER>(a);
 }
 
-#define DSMC_TILE_INSTANCES(TC, CH, S)                              \
-    template __global__ void k_classify<TC, CH, S>(StepArgs);       \
-    template __global__ void k_step<TC, CH, true, S, false>(StepArgs);  \
-    template __global__ void k_step<TC, CH, false, S, false>(StepArgs); \
-    template __global__ void k_step<TC, CH, true, S, true>(StepArgs);   \
-    template __global__ void k_step<TC, CH, false, S, true>(StepArgs);
+// The completion pass of a moved state (see STEP_COMPLETE): the listed
+// cells one by one, each a one-cell classify tile; a block takes list
+// entries b, b + grid, ...  Launched with flags STEP_COMPLETE and, after a
+// moved reseed, STEP_COMP_RESEED.
+template <int CH, class S>
+__global__ __launch_bounds__(64, 4) void k_complete(StepArgs a)
+{
+    const uint32_t n = ((const volatile Counters *)a.K().ctr)->ncomp;
+    for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
+        tile_kernel<1, CH, S, false, true, true>(a, a.K().complist[e]);
+        __syncthreads();
+    }
+}
+template __global__ void k_complete<4, double>(StepArgs);
+template __global__ void k_complete<8, double>(StepArgs);
+template __global__ void k_complete<8, float>(StepArgs);
+
+// Before the completion pass after a moved reseed that went ahead: the long
+// jumps the step recorded for the replaced cells' old particles are void.
+// From a complete list (pass 0, one thread per entry) they are dropped (new
+// cell -1) and taken off the arrival counts.  After an overflow of the list
+// the counts are rebuilt instead: pass 0 clears them, pass 1 (one thread
+// per cell) counts the long jumps of every cell that keeps its moved state
+// (neither replaced nor listed for completion) from its partitioned groups;
+// the completion adds those of the listed cells.  The long-jump total drops
+// by the void ones in either case.
+template <class S>
+__global__ __launch_bounds__(256) void k_comp_far(StepArgs a, int pass)
+{
+    const Counters *ct = a.K().ctr;
+    if (ct->reseed_err != 0u) return;
+    const int slot = (int)(a.step & 1u);
+    const uint32_t nf = ct->nfar[slot];
+    const bool listed = nf <= (uint32_t)a.K().far_cap;
+    const int nc = a.K().ncells;
+    int32_t *cnt = a.K().farcnt[slot];
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    unsigned long long dropped = 0;
+    if (listed && pass == 0) {
+        if (i < nf) {
+            int32_t *e = a.K().far[slot] + 4 * i;
+            const int o = e[1], d = e[2];
+            if (d >= 0 && o >= 0 && o < nc && a.K().mark[o] != 0) {
+                e[2] = -1;
+                atomicSub(&cnt[d], 1);
+                dropped = 1;
+            }
+        }
+    } else if (!listed && pass == 0) {
+        if (i < (size_t)nc) cnt[i] = 0;
+    } else if (!listed && pass == 1 && i < (size_t)nc) {
+        // (a cell that ended unmoved recorded no long jumps and has no groups yet)
+        const int o = (int)i;
+        const int32_t *g = a.K().grp[slot] + (size_t)o * GSTRIDE + DIR_FAR;
+        if ((a.K().comp[o] & 1) == 0) {
+            if (a.K().mark[o] != 0) {
+                dropped = (unsigned long long)(g[1] - g[0]);
+            } else {
+                for (int q = g[0]; q < g[1]; ++q) atomicAdd(&cnt[far_new_cell<S>(a, q)], 1);
+            }
+        }
+    }
+    dropped = wave_sum_u64(dropped);
+    if ((threadIdx.x & 63) == 0 && dropped)
+        atomicAdd(&a.K().ctr->nfar_total, ~dropped + 1ull);  // minus: the sum with nfar[] stays exact mod 2^64
+}
+
+template __global__ void k_comp_far<double>(StepArgs, int);
+template __global__ void k_comp_far<float>(StepArgs, int);
+
+// after the completion pass of a moved reseed: the reseed is over and the
+// list is empty (without a reseed the next step's cell pass empties it)
+__global__ void k_comp_done(Counters *ctr, int reseed)
+{
+    if (threadIdx.x == 0) {
+        ctr->ncomp = 0u;
+        if (reseed) {
+            ctr->reseed_err = 0u;
+            ctr->reseed_new = 0ull;
+            ctr->reseed_removed = 0ull;
+        }
+    }
+}
+
+#define DSMC_TILE_INSTANCES(TC, CH, S)                                    \
+    template __global__ void k_classify<TC, CH, S, false>(StepArgs);      \
+    template __global__ void k_classify<TC, CH, S, true>(StepArgs);       \
+    template __global__ void k_step<TC, CH, true, S, false, false>(StepArgs);  \
+    template __global__ void k_step<TC, CH, false, S, false, false>(StepArgs); \
+    template __global__ void k_step<TC, CH, true, S, true, false>(StepArgs);   \
+    template __global__ void k_step<TC, CH, false, S, true, false>(StepArgs);  \
+    template __global__ void k_step<TC, CH, true, S, false, true>(StepArgs);   \
+    template __global__ void k_step<TC, CH, true, S, true, true>(StepArgs);
 DSMC_TILE_INSTANCES(4, 4, double)
 DSMC_TILE_INSTANCES(2, 4, double)
 DSMC_TILE_INSTANCES(1, 4, double)
@@ -1258,7 +1430,8 @@ __global__ __launch_bounds__(256) void k_block_sums(const int32_t *counts, int n
 // of blocks 0 .. b-1 itself (at most a few hundred integers, exact in any
 // order), then scans its own 256 counts; the last block writes the total.
 // Block 0 also retires the long-jump list of parity reset_slot (the previous
-// step's, already sorted), which the coming step refills.
+// step's, already sorted), which the coming step refills, and empties the
+// completion list of a moved state (its pass, if any, ran before).
 __global__ __launch_bounds__(256) void k_cell_final(const int32_t *counts, int ncells, const int32_t *blocksum,
                                                     int32_t *cs, Counters *ctr, int reset_slot)
 {
@@ -1267,6 +1440,7 @@ __global__ __launch_bounds__(256) void k_cell_final(const int32_t *counts, int n
     if (b == 0 && threadIdx.x == 0 && reset_slot >= 0) {
         ctr->nfar_total += ctr->nfar[reset_slot];
         ctr->nfar[reset_slot] = 0u;
+        ctr->ncomp = 0u;
     }
     int part = 0;
     for (int i = threadIdx.x; i < b; i += 256) part += blocksum[i];
@@ -1350,7 +1524,10 @@ __global__ void k_zero_counters(Counters *c)
         c->ncand = 0ull;
         c->nwall = 0ull;
         c->nfar_total = 0ull;
+        c->reseed_new = 0ull;
+        c->reseed_removed = 0ull;
         c->step_base = 0u;
+        c->ncomp = 0u;
     }
 }
 

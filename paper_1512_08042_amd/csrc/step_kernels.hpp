@@ -56,9 +56,16 @@ struct TileConst {
     double *mom;             // [11][ncells] sums
     double *nbar, *sigcmax, *rem;
     int32_t *mark;           // [ncells] cells of a pending reseed (list index + 1, else 0)
+    // a moved state's completion pass (k_complete): per cell its reason to
+    // be completed (1: its tile ended unmoved, 2: a reseed replaced it), the
+    // listed cells, and a moved reseed's new particles (first slot after
+    // the appended base, count) per reseed list entry
+    int32_t *comp, *complist, *appoff;
+    const int32_t *nnew;
     const RepConst *rep;     // [nrep] the channels (stored right after this block, at REP_OFFSET)
     double s_th;             // sqrt(kT/m)
     int nbar_mode, ncells, far_cap, nrep;
+    int cap;                 // slots of a state buffer (bound of every source slot)
 };
 
 // the channels' constants follow the TileConst block in device memory, so a
@@ -82,6 +89,20 @@ constexpr int TILE_BAND = 8;
 // 1 - cur (at its cell starts) and the marked cells' new particles from
 // buffer cur, all moved into buffer cur.  Buffers of parity step & 1 hold
 // the partition read by the step's sort.
+//
+// A moved state (a call that ends moved, see dsmc_step_moved) may be
+// reseeded before the next step, and a reseed changes the cell starts that
+// key the wall draws of the coming move.  So the last step of such a call
+// (flags STEP_DEFER) leaves every tile with a particle bound for a wall
+// unmoved: it writes the tile settled, in place, and lists its cells.
+// k_complete (flags STEP_COMPLETE) later moves the listed cells one by one
+// as k_classify would, keyed by the cell starts after the reseed, if any,
+// and moves a reseeded cell's new particles, which the reseed appended
+// after the state's last slot.
+constexpr int STEP_DEFER = 1;
+constexpr int STEP_COMPLETE = 2;
+constexpr int STEP_COMP_RESEED = 4;  // with STEP_COMPLETE: a moved reseed precedes it
+
 struct StepArgs {
     const TileConst *kc;
     const int32_t *tiles;  // [tiles][TILE_WORDS]: first cell, replica, and the first cell's row and column
@@ -90,6 +111,7 @@ struct StepArgs {
     int r;                 // replica of the tile (the launch's, or set by the tile kernel from the table)
     int dev_step;          // step graphs: add the device step base to `step`
     int reseed;            // k_classify: complete a pending reseed (see above)
+    int flags;             // STEP_DEFER (k_step), STEP_COMPLETE (k_complete)
 
     // the blocks are read through the constant address space: they do not
     // change while a kernel runs, so their fields come in by scalar loads
@@ -206,6 +228,11 @@ struct ReseedArgs {
     int64_t capacity;
     double s_th;
     uint32_t k0, k1, event;
+    // a reseed of a moved state (moved != 0): the new particles of list
+    // entry i go to the moved buffer (out) from slot cs_old[ncells] +
+    // appoff[i]; the replaced cells are listed for the completion pass
+    int moved;
+    int32_t *appoff, *comp, *complist;
 };
 
 // Velocity sets in the ABI order (shells of increasing |e|, counter-clockwise
@@ -330,9 +357,9 @@ struct ProjectAdjArgs {
 
 // TC cells per tile (one wave); tiles of up to 64*CH particles are staged in
 // LDS; S is the stored particle type (double, or float with FP64 arithmetic)
-template <int TC, int CH, class S>
+template <int TC, int CH, class S, bool DEFER>
 __global__ void k_classify(StepArgs a);
-template <int TC, int CH, bool MOVE, class S, bool NT>
+template <int TC, int CH, bool MOVE, class S, bool NT, bool DEFER>
 __global__ void k_step(StepArgs a);
 __global__ void k_cell_count(CellArgs a);
 __global__ void k_scan_blocks(int32_t *blocksum, int nblk, int32_t *cs_out, int ncells, Counters *ctr,
@@ -353,6 +380,13 @@ __global__ void k_adopt_gather(AdoptArgs a);
 __global__ void k_fill_f64(double *p, size_t n, double v);
 __global__ void k_fill_i32(int32_t *p, size_t n, int32_t v);
 __global__ void k_zero_counters(Counters *c);
+template <int CH, class S>
+__global__ void k_complete(StepArgs a);
+template <class S>
+__global__ void k_comp_far(StepArgs a, int pass);
+__global__ void k_comp_done(Counters *ctr, int reseed);
+__global__ void k_reseed_appoff(ReseedArgs a);
+__global__ void k_reseed_list(ReseedArgs a);
 __global__ void k_clear_status(Counters *c);
 __global__ void k_tile_stats(const unsigned long long *tstat, int ntiles, Counters *c);
 __global__ void k_set_step_base(Counters *c, uint32_t step);

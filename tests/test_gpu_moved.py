@@ -6,13 +6,23 @@ sequence of steps and every random-number key are those of plain dsmc_step
 calls.  Runs that mix both kinds of call, re-tile while moved, or replay moved
 step graphs must therefore give the same bits as plain calls: particles, cell
 starts, per-cell NTC state, moment sums and counters.  While moved, reading
-particles and reseeding are refused.
+particles is refused.
+
+A reseed (map_lbm_to_dsmc) of a moved state appends the new particles and
+moves them, with the tiles the last step left unmoved (those with a particle
+bound for a wall, whose wall draws are keyed by the cell starts after the
+reseed), before the next step: runs of reseed cycles on moved states must
+equal the same cycles on settled states bit for bit, also when the reseed is
+rejected and when long jumps overflow their list, and follow the oracle.
 """
 import numpy as np
 import pytest
 import torch
 
+import inputs
 from oracle import oracle as O
+
+ST_BAD_CELL, ST_FAR_OVERFLOW = 0x40, 0x2
 
 pytestmark = pytest.mark.gpu
 
@@ -54,11 +64,6 @@ def test_moved_calls_match_plain_calls(bits):
     assert moved.status()["moved"]
     with pytest.raises(RuntimeError):
         moved.particles()
-    f = torch.zeros((9, moved.ncells), dtype=torch.float64, device="cuda")
-    ids = torch.arange(4, dtype=torch.int32, device="cuda")
-    with pytest.raises(_lib.DsmcError) as e:
-        moved.map_from_lbm(f, ids, 9, 2)
-    assert e.value.code == _lib.ESTATE
     moved.step(0, moved=True)  # nothing to do on a moved state
     moved.set_tiling(60)  # the moved state does not depend on the tiling
     moved.step(4, sample_every=1, moved=True)
@@ -141,3 +146,109 @@ def test_moved_batch_graph_matches_plain_batch():
     assert np.array_equal(graphed.replica_counters(), plain.replica_counters())
     plain.close()
     graphed.close()
+
+
+def _reseed_cycles(settled, moved, cells, q, order, ncyc, steps):
+    ids = torch.as_tensor(cells, device="cuda")
+    for k in range(ncyc):
+        settled.step(steps, sample_every=1)
+        moved.step(steps, sample_every=1, moved=True)
+        fs, fm = settled.map_to_lbm(q, order), moved.map_to_lbm(q, order)
+        assert torch.equal(fs, fm), "populations, cycle %d" % k
+        settled.map_from_lbm(fs, ids, q, order)
+        moved.map_from_lbm(fm, ids, q, order)
+        ss, sm = settled.status(), moved.status()
+        assert (ss["n"], ss["bits"]) == (sm["n"], sm["bits"]), (k, ss, sm)
+        assert sm["moved"] and not ss["moved"]
+    settled.step(2, sample_every=1)
+    moved.step(2, sample_every=1)
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+def test_moved_reseed_matches_settled_reseed(bits):
+    D, ChannelConfig, _lib = _gpu()
+    nx, ny = 16, 24
+    cfg = ChannelConfig(nx=nx, ny=ny, ppc=30, kn=0.05, mach=0.1, seed=21, state_bits=bits).resolved()
+    settled, moved = D.Channel(cfg), D.Channel(cfg)
+    cells = inputs.strip_cells(nx, ny, 3)[::-1].copy()  # both wall rows, in any order
+    _reseed_cycles(settled, moved, cells, 37, 3, 4, 5)
+    _same(moved, settled, "after 4 reseed cycles (bits %d)" % bits)
+    # one reseed per moved state
+    ids = torch.as_tensor(cells, device="cuda")
+    moved.step(3, sample_every=1, moved=True)
+    f = moved.map_to_lbm(37, 3)
+    moved.map_from_lbm(f, ids, 37, 3)
+    with pytest.raises(_lib.DsmcError) as e:
+        moved.map_from_lbm(f, ids, 37, 3)
+    assert e.value.code == _lib.ESTATE
+    settled.close()
+    moved.close()
+
+
+@pytest.mark.parametrize("far_capacity", [0, 4])
+def test_moved_reseed_with_long_jumps_and_walls(far_capacity):
+    # a time step of two cells: most tiles hold particles bound for a wall
+    # and many particles jump further than a neighbour cell (with a list of 4
+    # entries those overflow it)
+    D, ChannelConfig, _lib = _gpu()
+    nx, ny = 9, 7
+    counts = np.full(nx * ny, 20)
+    p = [torch.as_tensor(a) for a in inputs.particles_per_cell(1, nx, ny, counts, vscale=2.0)]
+    cfg = ChannelConfig(nx=nx, ny=ny, ppc=20, kn=0.5, dt=2.0, seed=4, capacity=int(counts.sum()) * 3,
+                        far_capacity=far_capacity).resolved()
+    settled, moved = D.Channel(cfg, particles=p), D.Channel(cfg, particles=p)
+    _reseed_cycles(settled, moved, inputs.strip_cells(nx, ny, 2), 9, 2, 3, 2)
+    _same(moved, settled, "after 3 reseed cycles (far_capacity %d)" % far_capacity)
+    st = moved.status()
+    assert st["nfar"] > 0 and st["nwall"] > 0
+    if far_capacity:
+        assert st["bits"] & ST_FAR_OVERFLOW
+    settled.close()
+    moved.close()
+
+
+def test_rejected_moved_reseed_matches_settled():
+    D, ChannelConfig, _lib = _gpu()
+    cfg = ChannelConfig(nx=8, ny=12, ppc=25, kn=0.1, mach=0.1, seed=8).resolved()
+    settled, moved = D.Channel(cfg), D.Channel(cfg)
+    settled.step(4, sample_every=1)
+    moved.step(4, sample_every=1, moved=True)
+    f = settled.map_to_lbm(9, 2)
+    dup = torch.tensor([3, 5, 3], dtype=torch.int32, device="cuda")  # a repeated id: the whole reseed is skipped
+    settled.map_from_lbm(f, dup, 9, 2)
+    moved.map_from_lbm(f, dup, 9, 2)
+    ss, sm = settled.status(), moved.status()
+    assert ss["bits"] & ST_BAD_CELL and ss["bits"] == sm["bits"] and ss["n"] == sm["n"]
+    settled.step(3, sample_every=1)
+    moved.step(3, sample_every=1)
+    _same(moved, settled, "after a rejected reseed")
+    settled.close()
+    moved.close()
+
+
+def test_moved_reseed_cycles_follow_the_oracle():
+    # both sides reseed from the same populations (the oracle's projection),
+    # so every integer decision of the reseed is taken on identical inputs
+    D, ChannelConfig, _lib = _gpu()
+    nx, ny, ppc = 8, 12, 25
+    cfg = ChannelConfig(nx=nx, ny=ny, ppc=ppc, kn=0.05, mach=0.1, seed=13).resolved()
+    ch = D.Channel(cfg)
+    ref = O.Sim(nx, ny, ppc, cfg.kn, dt=cfg.dt, g=cfg.body_force_x, seed=cfg.seed, capacity=cfg.capacity)
+    ref.init_maxwell()
+    lat = O.lattice(37)
+    cells = inputs.strip_cells(nx, ny, 2)
+    ids = torch.as_tensor(cells, device="cuda")
+    for k in range(3):
+        ch.step(4, sample_every=1, moved=True)
+        ref.step(4, sample_every=1)
+        want = O.dsmc2lb(ref.averages(), ppc, lat, 3)
+        ch.map_from_lbm(torch.as_tensor(want, device="cuda").contiguous(), ids, 37, 3)
+        assert ref.lb2dsmc(lat, 3, want, cells) == 0
+    ch.step(2, sample_every=1)
+    ref.step(2, sample_every=1)
+    assert np.array_equal(ch.cell_start().cpu().numpy(), ref.cells()[0])
+    for name, g, w in zip("x y vx vy vz".split(), [t.cpu().numpy() for t in ch.particles()], ref.particles()):
+        assert g.shape == w.shape and np.allclose(g, w, rtol=1e-12, atol=1e-12), name
+    rc, st = ref.counters(), ch.status()
+    assert (st["ncoll"], st["ncand"], st["nwall"]) == (rc["ncoll"], rc["ncand"], rc["nwall"])
+    ch.close()
