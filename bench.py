@@ -635,7 +635,7 @@ def hybrid_benchmark():
 
         def cycle(a=None):
             ch.hybrid_cycle(f, tmp, nx_l, tau, g / r, dsmc_steps=ds, lbm_steps=Hh["lbm_steps"], mapping=mapping,
-                            order=2, avg_out=a)
+                            order=2, avg_out=a, moved=True)  # only moments are read between cycles
 
         for _ in range(Hh["warm"]):
             cycle()

@@ -344,7 +344,10 @@ int dsmc_project_equilibrium(const double *avg, int64_t ncells, int32_t ppc, dou
  * the sampled non-equilibrium moments up to `order`); writes the cycle's
  * averages of every DSMC cell to avg_out (device [11][ncells], may be NULL);
  * resets the sums; and runs lbm_steps lattice steps (f_tmp: scratch of
- * f_lb's size).  Errors: DSMC_EINVAL, DSMC_ESTATE (batch contexts). */
+ * f_lb's size).  flags DSMC_HYBRID_MOVED: the DSMC steps end with the state
+ * moved, as dsmc_step_moved leaves it (for loops of cycles that read no
+ * particles in between).  Errors: DSMC_EINVAL, DSMC_ESTATE (batch contexts). */
+#define DSMC_HYBRID_MOVED 0x1
 typedef struct dsmc_hybrid {
     lbm_config lbm;
     int32_t dsmc_steps;
@@ -352,7 +355,7 @@ typedef struct dsmc_hybrid {
     int32_t mapping;
     int32_t order;
     int32_t dsmc_column;
-    int32_t reserved;
+    int32_t flags;            /* 0 or DSMC_HYBRID_MOVED */
 } dsmc_hybrid;
 int dsmc_hybrid_cycle(dsmc_ctx *ctx, const dsmc_hybrid *h, double *f_lb, double *f_tmp, double *avg_out,
                       void *stream);

@@ -69,7 +69,7 @@ class LbmConfig(ctypes.Structure):
 
 class Hybrid(ctypes.Structure):
     _fields_ = [("lbm", LbmConfig), ("dsmc_steps", c_i32), ("lbm_steps", c_i32), ("mapping", c_i32),
-                ("order", c_i32), ("dsmc_column", c_i32), ("reserved", c_i32)]
+                ("order", c_i32), ("dsmc_column", c_i32), ("flags", c_i32)]
 
 
 _lib = None

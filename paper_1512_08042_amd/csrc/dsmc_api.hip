@@ -1521,10 +1521,12 @@ static int dsmc_hybrid_cycle_impl(dsmc_ctx *x, const dsmc_hybrid *h, double *f_l
     if (h->order < 1 || h->order > 3 || (h->mapping == 0 && h->order == 3 && h->lbm.lattice == 9))
         return fail(DSMC_EINVAL, "order must be 1..3 (the third-order equilibrium needs D2Q37)");
     if (h->dsmc_column < 0 || h->dsmc_column >= x->cfg.nx) return fail(DSMC_EINVAL, "dsmc_column outside [0, nx)");
+    if (h->flags & ~DSMC_HYBRID_MOVED) return fail(DSMC_EINVAL, "flags must be 0 or DSMC_HYBRID_MOVED");
     hipStream_t s = S(stream);
     x->last = s;
     // the DSMC subdomain, sampled every step over the cycle
-    TRY(dsmc_step(x, h->dsmc_steps, 1, stream));
+    TRY((h->flags & DSMC_HYBRID_MOVED) ? dsmc_step_moved(x, h->dsmc_steps, 1, stream)
+                                       : dsmc_step(x, h->dsmc_steps, 1, stream));
     // its buffer-layer column, averaged over the cycle, onto every held
     // inflow column of the lattice
     const int ny = x->cfg.ny;

@@ -171,19 +171,21 @@ class Channel:
 
     def hybrid_cycle(self, f_lb: torch.Tensor, f_tmp: torch.Tensor, lbm_nx: int, tau: float, body_force_x: float,
                      dsmc_steps: int, lbm_steps: int, mapping: int = 0, order: int = 2, dsmc_column: int | None = None,
-                     lattice_q: int = 9, x_buffer: int = 1, avg_out: torch.Tensor | None = None, stream=None):
+                     lattice_q: int = 9, x_buffer: int = 1, avg_out: torch.Tensor | None = None, stream=None,
+                     moved: bool = False):
         """One cycle of the Section 4 coupling: this channel is the DSMC
         subdomain; f_lb[Q][lbm_nx * ny] the lattice subdomain with diffuse
         walls, its first x_buffer columns the buffer layer fed from DSMC column
         dsmc_column (default: the last) by the equilibrium mapping (mapping 0)
         or the full projection (mapping 1).  avg_out ([11][ncells], optional)
-        receives the cycle's DSMC averages."""
+        receives the cycle's DSMC averages.  moved=True leaves the DSMC state
+        moved (see step(moved=True))."""
         ny = self.cfg.ny
         assert f_lb.dtype == torch.float64 and f_lb.is_contiguous() and f_lb.shape == (lattice_q, lbm_nx * ny)
         col = self.cfg.nx - 1 if dsmc_column is None else int(dsmc_column)
         h = _lib.Hybrid(_lib.LbmConfig(int(lbm_nx), int(ny), int(lattice_q), 2 if lattice_q == 9 else 1, float(tau),
                                        float(body_force_x), int(x_buffer), 0),
-                        int(dsmc_steps), int(lbm_steps), int(mapping), int(order), col, 0)
+                        int(dsmc_steps), int(lbm_steps), int(mapping), int(order), col, 1 if moved else 0)
         if avg_out is not None:
             assert avg_out.dtype == torch.float64 and avg_out.is_contiguous() and avg_out.shape == (NMOM, self.ncells)
         check(lib().dsmc_hybrid_cycle(self._h, ctypes.byref(h), _ptr(f_lb), _ptr(f_tmp),

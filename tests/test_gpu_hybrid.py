@@ -62,8 +62,9 @@ def _oracle_cycle(ref, f_lb, lat, nx_d, nx_l, ny, ppc, tau, g, dsmc_steps, lbm_s
     return O.lbm_step(f_lb, lat, nx_l, ny, tau, g, 2, lbm_steps, x_buffer=1), avg
 
 
-@pytest.mark.parametrize("mapping", [0, 1])
-def test_hybrid_cycles_match_the_oracle_composition(mapping):
+@pytest.mark.parametrize("mapping,moved", [(0, False), (1, False), (0, True)])
+def test_hybrid_cycles_match_the_oracle_composition(mapping, moved):
+    # moved: every cycle leaves the DSMC state moved for the next one
     D, ChannelConfig = _gpu()
     nx_d, nx_l, ny, ppc, kn = 8, 10, 12, 30, 0.1
     cfg = ChannelConfig(nx=nx_d, ny=ny, ppc=ppc, kn=kn, mach=0.1, seed=3).resolved()
@@ -79,11 +80,15 @@ def test_hybrid_cycles_match_the_oracle_composition(mapping):
     avg = torch.empty((11, nx_d * ny), dtype=torch.float64, device="cuda")
     for cyc in range(3):
         ch.hybrid_cycle(f_gpu, tmp, nx_l, tau, g_lb, dsmc_steps=4, lbm_steps=2, mapping=mapping, order=2,
-                        avg_out=avg)
+                        avg_out=avg, moved=moved)
+        assert ch.status()["moved"] == moved
         f_ref, want_avg = _oracle_cycle(ref, f_ref, lat, nx_d, nx_l, ny, ppc, tau, g_lb, 4, 2, mapping, 2)
         assert np.allclose(f_gpu.cpu().numpy(), f_ref, rtol=1e-11, atol=1e-14), "cycle %d" % cyc
         scale = np.abs(want_avg).max(axis=1, keepdims=True) + 1.0
         assert np.all(np.abs(avg.cpu().numpy() - want_avg) <= 1e-12 * scale), "cycle %d averages" % cyc
+    if moved:  # one more step on both sides settles it
+        ch.step(1)
+        ref.step(1)
     for gp, w in zip(ch.particles(), ref.particles()):
         assert np.allclose(gp.cpu().numpy(), w, rtol=1e-12, atol=1e-12)
     # the buffer column holds the DSMC column's state of the last cycle
@@ -105,6 +110,8 @@ def test_hybrid_cycle_rejects_bad_arguments():
     h = _lib.Hybrid(_lib.LbmConfig(5, 6, 9, 2, 0.9, 0.0, 0, 0), 2, 1, 0, 2, 3, 0)  # no buffer column
     assert L.dsmc_hybrid_cycle(ch._h, ctypes.byref(h), f.data_ptr(), tmp.data_ptr(), None, stream) == _lib.EINVAL
     h = _lib.Hybrid(_lib.LbmConfig(5, 6, 9, 2, 0.9, 0.0, 1, 0), 2, 1, 0, 2, 4, 0)  # DSMC column out of range
+    assert L.dsmc_hybrid_cycle(ch._h, ctypes.byref(h), f.data_ptr(), tmp.data_ptr(), None, stream) == _lib.EINVAL
+    h = _lib.Hybrid(_lib.LbmConfig(5, 6, 9, 2, 0.9, 0.0, 1, 0), 2, 1, 0, 2, 3, 2)  # unknown flag
     assert L.dsmc_hybrid_cycle(ch._h, ctypes.byref(h), f.data_ptr(), tmp.data_ptr(), None, stream) == _lib.EINVAL
     assert ch.views().step == 0  # nothing ran
     ch.close()

@@ -252,3 +252,32 @@ def test_moved_reseed_cycles_follow_the_oracle():
     rc, st = ref.counters(), ch.status()
     assert (st["ncoll"], st["ncand"], st["nwall"]) == (rc["ncoll"], rc["ncand"], rc["nwall"])
     ch.close()
+
+
+def test_moving_pass_alone_then_reseeds():
+    # step(0, moved) moves a settled state (deferring its wall tiles as a
+    # call's last step does), also when it completes a pending settled
+    # reseed; a reseed of that moved state, then steps, equal the settled path
+    D, ChannelConfig, _lib = _gpu()
+    nx, ny = 12, 16
+    cfg = ChannelConfig(nx=nx, ny=ny, ppc=30, kn=0.05, mach=0.1, seed=17).resolved()
+    settled, moved = D.Channel(cfg), D.Channel(cfg)
+    ids = torch.as_tensor(inputs.strip_cells(nx, ny, 2), device="cuda")
+    for ch in (settled, moved):
+        ch.step(4, sample_every=1)
+    f = settled.map_to_lbm(9, 2)
+    for ch in (settled, moved):
+        ch.map_from_lbm(f, ids, 9, 2)  # settled state: a pending reseed
+    moved.step(0, moved=True)  # completes it and moves the result
+    assert moved.status()["moved"]
+    for ch in (settled, moved):
+        ch.step(3, sample_every=1)
+    f = settled.map_to_lbm(37, 3)
+    settled.map_from_lbm(f, ids, 37, 3)
+    moved.step(0, moved=True)
+    moved.map_from_lbm(f, ids, 37, 3)  # a reseed of the state the moving pass left
+    for ch in (settled, moved):
+        ch.step(3, sample_every=1)
+    _same(moved, settled, "after moving passes and reseeds")
+    settled.close()
+    moved.close()
