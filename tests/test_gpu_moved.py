@@ -281,3 +281,33 @@ def test_moving_pass_alone_then_reseeds():
     _same(moved, settled, "after moving passes and reseeds")
     settled.close()
     moved.close()
+
+
+def test_moved_reseed_edge_cases():
+    # an empty cell list (only the unmoved tiles are completed), then a
+    # reseed that does not fit the buffer (three times the density on the
+    # strip): skipped on both paths with the capacity bit, state unchanged
+    D, ChannelConfig, _lib = _gpu()
+    nx, ny, ppc = 10, 12, 20
+    cfg = ChannelConfig(nx=nx, ny=ny, ppc=ppc, kn=0.1, mach=0.1, seed=23,
+                        capacity=nx * ny * ppc + 2 * ny * ppc).resolved()
+    settled, moved = D.Channel(cfg), D.Channel(cfg)
+    none = torch.zeros(0, dtype=torch.int32, device="cuda")
+    ids = torch.as_tensor(inputs.strip_cells(nx, ny, 3), device="cuda")
+    settled.step(4, sample_every=1)
+    moved.step(4, sample_every=1, moved=True)
+    f = settled.map_to_lbm(9, 2)
+    settled.map_from_lbm(f, none, 9, 2)
+    moved.map_from_lbm(f, none, 9, 2)
+    settled.step(3, sample_every=1)
+    moved.step(3, sample_every=1, moved=True)
+    f = settled.map_to_lbm(9, 2) * 3.0
+    settled.map_from_lbm(f, ids, 9, 2)
+    moved.map_from_lbm(f, ids, 9, 2)
+    ss, sm = settled.status(), moved.status()
+    assert ss["bits"] & 0x4 and ss["bits"] == sm["bits"] and ss["n"] == sm["n"] == nx * ny * ppc
+    settled.step(2, sample_every=1)
+    moved.step(2, sample_every=1)
+    _same(moved, settled, "after an empty and a skipped reseed")
+    settled.close()
+    moved.close()
