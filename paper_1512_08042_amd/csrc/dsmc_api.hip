@@ -1393,10 +1393,14 @@ static int step_run(dsmc_ctx *x, int32_t nsteps, int32_t sample_every, bool move
         c.ncells = nc;
         c.nx1 = x->nrep == 1 ? x->reps[0].G.nx : 0;
         c.ny1 = x->nrep == 1 ? x->reps[0].G.ny : 0;
+        c.cs_out = x->cs[nxt];
+        c.ctr = x->ctr;
+        c.reset_slot = p ^ 1;
         TRY(launch(x, DSMC_K_CELL_COUNT, s, [&] { k_cell_count<<<x->nblk, 256, 0, s>>>(c); }));
-        TRY(launch(x, DSMC_K_CELL_FINAL, s, [&] {
-            k_cell_final<<<x->nblk, 256, 0, s>>>(x->countnew, nc, x->blocksum, x->cs[nxt], x->ctr, p ^ 1);
-        }));
+        if (x->nblk > 1)  // (one block: the count kernel wrote the starts)
+            TRY(launch(x, DSMC_K_CELL_FINAL, s, [&] {
+                k_cell_final<<<x->nblk, 256, 0, s>>>(x->countnew, nc, x->blocksum, x->cs[nxt], x->ctr, p ^ 1);
+            }));
 
         const bool sample = sample_every > 0 && ((x->step + 1) % sample_every) == 0;
         const bool move = moved_end || it + 1 < nsteps;  // a dsmc_step call's last step leaves the state settled

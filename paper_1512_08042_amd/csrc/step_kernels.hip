@@ -1340,6 +1340,16 @@ __global__ __launch_bounds__(256) void k_cell_count(CellArgs a)
     for (int i = (nwords / 4) * 4 + threadIdx.x; i < nwords; i += 256) a.plan[(size_t)c0 * (2 * NDIR) + i] = stage[i];
     const int bsum = block_reduce_256(total, lds);
     if (threadIdx.x == 0) a.blocksum[blockIdx.x] = bsum;
+    if (gridDim.x == 1) {  // the whole grid: its cell starts too (no k_cell_final launch)
+        const int ex = block_exscan_256(total, lds);
+        if (c < a.ncells) a.cs_out[c] = ex;
+        if (threadIdx.x == 255) a.cs_out[a.ncells] = ex + total;
+        if (threadIdx.x == 0 && a.reset_slot >= 0) {
+            a.ctr->nfar_total += a.ctr->nfar[a.reset_slot];
+            a.ctr->nfar[a.reset_slot] = 0u;
+            a.ctr->ncomp = 0u;
+        }
+    }
 }
 
 // exclusive scan of the block sums (one workgroup of 1024); writes the grand

@@ -186,6 +186,11 @@ struct CellArgs {
     const int32_t *cell_rep; // [ncells] channel of every cell
     int ncells;
     int nx1, ny1;            // > 0: one channel of nx1 x ny1 cells (rep and cell_rep are not read)
+    // one block (ncells <= 256): the cell starts are written here too, and
+    // the step's counters retired, as k_cell_final does for larger grids
+    int32_t *cs_out;
+    Counters *ctr;
+    int reset_slot;
 };
 
 // the initial Maxwellian of one channel: its cells start at cs, nbar, ...
